@@ -1,0 +1,214 @@
+"""CPU oracle for the PIFS range-domain search.
+
+TEST INFRASTRUCTURE ONLY: the test suite, the package smoke check and the
+benchmark's CPU-baseline leg may import this; the product path never does.
+It shares no code with the GPU library (``paper_1206_4880_amd``) and neither
+imports the other.
+
+The arithmetic lives in ``fic_oracle.c`` (plain loops, exact integers, fp64
+fractal dimensions); this module only compiles it with gcc and marshals numpy
+arrays. ``bruteforce.py`` holds the pixel-level grid search used to pin it.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "fic_oracle.c")
+_SO = os.path.join(_HERE, "libfic_oracle.so")
+_lib = None
+
+_i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+_f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_u8p = np.ctypeslib.ndpointer(dtype=np.uint8, flags="C_CONTIGUOUS")
+
+
+def build(force=True):
+    """Compile the oracle with gcc (-O2, OpenMP). Returns the .so path."""
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        tmp = _SO + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
+                               "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build()
+        L = ctypes.CDLL(_SO)
+        L.fico_num_ranges.restype = ctypes.c_int64
+        L.fico_num_ranges.argtypes = [ctypes.c_int32] * 3
+        L.fico_num_domains.restype = ctypes.c_int64
+        L.fico_num_domains.argtypes = [ctypes.c_int32] * 4
+        L.fico_iso_apply.restype = None
+        L.fico_iso_apply.argtypes = [ctypes.c_int32, ctypes.c_int32, _i64p, _i64p]
+        L.fico_dbc_fd.restype = ctypes.c_double
+        L.fico_dbc_fd.argtypes = [_u8p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                  ctypes.c_int32, _i64p]
+        L.fico_fd_blocks.restype = None
+        L.fico_fd_blocks.argtypes = [_u8p] + [ctypes.c_int32] * 5 + [_f64p, ctypes.c_int32]
+        L.fico_resolve_tol.restype = ctypes.c_double
+        L.fico_resolve_tol.argtypes = [ctypes.c_double, _f64p, ctypes.c_int64]
+        L.fico_encode.restype = ctypes.c_int32
+        L.fico_encode.argtypes = ([_u8p] + [ctypes.c_int32] * 5
+                                  + [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                     ctypes.c_void_p, ctypes.c_int64]
+                                  + [_i32p] * 5 + [_i64p, _i64p, _i64p, ctypes.c_int32])
+        L.fico_pair_f.restype = ctypes.c_int64
+        L.fico_pair_f.argtypes = ([_u8p] + [ctypes.c_int32] * 5
+                                  + [ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
+                                     ctypes.POINTER(ctypes.c_int32)])
+        L.fico_decode.restype = ctypes.c_int32
+        L.fico_decode.argtypes = ([_i32p] * 4 + [ctypes.c_int32] * 5
+                                  + [ctypes.c_void_p, _u8p, ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.c_int32])
+        _lib = L
+    return _lib
+
+
+def _img(img):
+    return np.ascontiguousarray(img, dtype=np.uint8)
+
+
+def num_ranges(h, w, b):
+    return int(lib().fico_num_ranges(h, w, b))
+
+
+def num_domains(h, w, b, t):
+    return int(lib().fico_num_domains(h, w, b, t))
+
+
+def iso_apply(q, block):
+    blk = np.ascontiguousarray(block, dtype=np.int64)
+    b = blk.shape[0]
+    out = np.empty_like(blk)
+    lib().fico_iso_apply(int(q), int(b), blk, out)
+    return out
+
+
+def dbc_fd(block, return_counts=False):
+    """Fractal dimension of one square uint8 block (side a power of two)."""
+    blk = _img(block)
+    m = blk.shape[0]
+    counts = np.zeros(8, dtype=np.int64)
+    fd = lib().fico_dbc_fd(blk, m, 0, 0, m, counts)
+    if return_counts:
+        return fd, counts[: int(np.log2(m))]
+    return fd
+
+
+def fd_blocks(img, m, step, nthreads=0):
+    im = _img(img)
+    h, w = im.shape
+    rows, cols = (h - m) // step + 1, (w - m) // step + 1
+    out = np.empty(rows * cols, dtype=np.float64)
+    lib().fico_fd_blocks(im, h, w, w, m, step, out, int(nthreads))
+    return out
+
+
+def resolve_tol(tol, fd_dom):
+    fd = np.ascontiguousarray(fd_dom, dtype=np.float64)
+    return float(lib().fico_resolve_tol(float(tol), fd, fd.size))
+
+
+def classify(img, b, t, nthreads=0):
+    """(fd of ranges, fd of domains) in fp64."""
+    return fd_blocks(img, b, b, nthreads), fd_blocks(img, 2 * b, t, nthreads)
+
+
+def encode(img, b, t, tol=None, sel=None, nthreads=0, fds=None):
+    """Exact codes for the selected ranges (all when sel is None).
+
+    tol=None is exhaustive search; otherwise the fractal-dimension window with
+    half-width tol (negative: the adaptive (max - min)/3).
+    Returns a dict of numpy arrays: dom, iso, k, j, flags, err, f, pool, plus
+    the resolved tolerance under 'tol'.
+    """
+    im = _img(img)
+    h, w = im.shape
+    if sel is None:
+        n = num_ranges(h, w, b)
+        selp = None
+    else:
+        sel = np.ascontiguousarray(sel, dtype=np.int64)
+        n = sel.size
+        selp = sel.ctypes.data
+    out = {k: np.zeros(n, dtype=np.int32) for k in ("dom", "iso", "k", "j", "flags")}
+    for k in ("err", "f", "pool"):
+        out[k] = np.zeros(n, dtype=np.int64)
+    fr = fdd = None
+    rt = float("inf")
+    if tol is not None:
+        fr, fdd = fds if fds is not None else classify(im, b, t, nthreads)
+        fr = np.ascontiguousarray(fr, dtype=np.float64)
+        fdd = np.ascontiguousarray(fdd, dtype=np.float64)
+        rt = resolve_tol(tol, fdd)
+    rc = lib().fico_encode(im, h, w, w, b, t,
+                           fr.ctypes.data if fr is not None else None,
+                           fdd.ctypes.data if fdd is not None else None,
+                           rt, selp, n,
+                           out["dom"], out["iso"], out["k"], out["j"], out["flags"],
+                           out["err"], out["f"], out["pool"], int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle: invalid geometry")
+    out["tol"] = rt
+    return out
+
+
+def pair_f(img, b, t, r, d, q):
+    im = _img(img)
+    h, w = im.shape
+    k = ctypes.c_int32(0)
+    f = lib().fico_pair_f(im, h, w, w, b, t, int(r), int(d), int(q), ctypes.byref(k))
+    return int(f), int(k.value)
+
+
+def decode(codes, h, w, b, t, max_iters=32, init=None, nthreads=0):
+    """Decoded image and the number of sweeps run."""
+    arr = [np.ascontiguousarray(codes[k], dtype=np.int32) for k in ("dom", "iso", "k", "j")]
+    out = np.empty((h, w), dtype=np.uint8)
+    it = ctypes.c_int32(0)
+    ini = _img(init) if init is not None else None
+    rc = lib().fico_decode(*arr, h, w, b, t, int(max_iters),
+                           ini.ctypes.data if ini is not None else None,
+                           out, ctypes.byref(it), int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle: invalid geometry")
+    return out, int(it.value)
+
+
+def psnr(a, b):
+    """Peak signal-to-noise ratio for 8-bit images, fp64 (inf when equal)."""
+    d = a.astype(np.float64) - b.astype(np.float64)
+    mse = float(np.mean(d * d))
+    return float("inf") if mse == 0.0 else 10.0 * np.log10(255.0 * 255.0 / mse)
+
+
+def pool_margin(fd_range, fd_dom, tol):
+    """Smallest distance between any |fd_d - fd_r| and the window edge
+    tol + 1e-9: how far every membership decision is from flipping."""
+    edge = tol + 1e-9
+    s = np.sort(np.asarray(fd_dom, dtype=np.float64))
+    best = np.inf
+    for sign in (-1.0, 1.0):
+        target = np.asarray(fd_range, dtype=np.float64) + sign * edge
+        pos = np.searchsorted(s, target)
+        for off in (-1, 0):
+            p = np.clip(pos + off, 0, s.size - 1)
+            diff = np.abs(np.abs(s[p] - fd_range) - edge)
+            best = min(best, float(diff.min()))
+    return best
+
+
+def pool_bounds(fd_range, fd_dom, tol):
+    """Pool sizes per range by the plain membership rule (for pair counts)."""
+    fr = np.asarray(fd_range, dtype=np.float64)
+    fd = np.asarray(fd_dom, dtype=np.float64)
+    return np.array([int(np.count_nonzero(np.abs(fd - x) <= tol + 1e-9)) for x in fr],
+                    dtype=np.int64)

@@ -1,0 +1,359 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these checks re-types the oracle's own formula: each compares it with
+a value printed in the paper, a hand count, an independent derivation (numpy
+rotations, the pixel-level grid brute force) or an invariant.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import bruteforce as bf
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _fbm(n, h, seed):
+    from synth import fbm
+    return fbm(n, n, h, np.random.default_rng(seed))
+
+
+# ---------------------------------------------------------------- geometry
+def test_table1_counts(oracle_lib):
+    """Sec. 2, Table 1: ranges, domains and comparisons of the 8/16 lattice."""
+    with open(os.path.join(GOLD, "table1_counts.json")) as f:
+        tab = json.load(f)
+    for row in tab["rows"]:
+        n = row["image"]
+        nr = oracle_lib.num_ranges(n, n, tab["range_size"])
+        nd = oracle_lib.num_domains(n, n, tab["range_size"], tab["domain_step"])
+        assert (nr, nd, nr * nd) == (row["ranges"], row["domains"], row["comparisons"])
+    # the 1024 example of Sec. 2: about 2^34 comparisons
+    assert abs(math.log2(16384 * 1018081) - 34) < 0.05
+
+
+def test_lattice_matches_enumeration(oracle_lib):
+    for (h, w, b, t) in [(32, 48, 4, 1), (32, 48, 4, 3), (64, 64, 8, 2), (64, 96, 16, 4)]:
+        ranges, doms = bf.lattice(h, w, b, t)
+        assert oracle_lib.num_ranges(h, w, b) == len(ranges)
+        assert oracle_lib.num_domains(h, w, b, t) == len(doms)
+
+
+# -------------------------------------------------------------- isometries
+def test_isometry_table_matches_numpy_derivation(oracle_lib):
+    """The C index table against numpy's rot90/flip/transpose."""
+    rng = np.random.default_rng(7)
+    for b in (4, 8, 16):
+        blk = rng.integers(0, 1000, size=(b, b))
+        ref = bf.isometries(blk)
+        for q in range(8):
+            assert np.array_equal(oracle_lib.iso_apply(q, blk), ref[q]), (b, q)
+
+
+def test_isometry_group_laws(oracle_lib):
+    """D4: rotation of order 4, rotations compose, reflections are
+    involutions, reflection = rotation o mirror, all 8 distinct."""
+    b = 8
+    blk = np.arange(b * b, dtype=np.int64).reshape(b, b)
+    T = lambda q, x: oracle_lib.iso_apply(q, x)
+    r1 = lambda x: T(1, x)
+    assert np.array_equal(r1(r1(r1(r1(blk)))), blk)
+    assert np.array_equal(r1(r1(blk)), T(2, blk))
+    assert np.array_equal(r1(r1(r1(blk))), T(3, blk))
+    for q in (4, 5, 6, 7):
+        assert np.array_equal(T(q, T(q, blk)), blk)
+    assert np.array_equal(T(4, T(6, blk)), T(1, blk))     # mirror-LR(transpose(d)) = rot90 cw
+    assert np.array_equal(T(6, T(4, blk)), T(3, blk))     # transpose(mirror-LR(d)) = rot270 cw
+    assert np.array_equal(T(2, T(6, blk)), T(7, blk))     # anti-transpose = transpose o rot180
+    assert len({T(q, blk).tobytes() for q in range(8)}) == 8
+
+
+# ------------------------------------------------- closed form vs the grid
+@pytest.mark.parametrize("b", [4, 8])
+def test_pair_fit_equals_grid_bruteforce(oracle_lib, b):
+    """F(k) + 4096 (sum r - 2nj)^2 with the scanned k and j equals the
+    pixel-level minimum over the whole 32 x 128 (k, j) grid."""
+    rng = np.random.default_rng(11 + b)
+    for trial in range(40):
+        kind = trial % 4
+        if kind == 0:
+            img = rng.integers(0, 256, size=(4 * b, 4 * b)).astype(np.uint8)
+        elif kind == 1:
+            img = _fbm(4 * b, 0.4, int(rng.integers(1 << 30)))
+        elif kind == 2:      # a flat domain region
+            img = rng.integers(0, 256, size=(4 * b, 4 * b)).astype(np.uint8)
+            img[:2 * b, :2 * b] = rng.integers(0, 256)
+        else:                # smooth ramp
+            y, x = np.mgrid[0:4 * b, 0:4 * b]
+            img = np.clip(3 * x + 2 * y + rng.integers(0, 60), 0, 255).astype(np.uint8)
+        h = w = 4 * b
+        t = 1
+        ranges, doms = bf.lattice(h, w, b, t)
+        r = int(rng.integers(len(ranges)))
+        d = 0 if kind == 2 else int(rng.integers(len(doms)))
+        q = int(rng.integers(8))
+        f, k = oracle_lib.pair_f(img, b, t, r, d, q)
+        (ry, rx), (dy, dx) = ranges[r], doms[d]
+        rblk = img[ry:ry + b, rx:rx + b]
+        tq = bf.isometries(bf.shrink(img, dy, dx, b))[q]
+        e_ref, k_ref, j_ref = bf.brute_pair(rblk, tq)
+        sr = int(rblk.astype(np.int64).sum())
+        n = b * b
+        j = (sr + n - 1) // (2 * n)
+        assert (k, j) == (k_ref, j_ref)
+        assert f + 4096 * (sr - 2 * n * j) ** 2 == e_ref
+
+
+# --------------------------------------------------- whole-search brute force
+@pytest.mark.parametrize("case", [
+    ("uniform", 16, 4, 2), ("fbm", 16, 4, 1), ("fbm", 24, 4, 2), ("ramp", 16, 4, 2),
+    ("fbm", 32, 8, 4), ("blocks", 16, 4, 2),
+])
+def test_search_equals_grid_bruteforce(oracle_lib, case):
+    kind, size, b, t = case
+    rng = np.random.default_rng(size * 31 + b)
+    if kind == "uniform":
+        img = rng.integers(0, 256, size=(size, size)).astype(np.uint8)
+    elif kind == "fbm":
+        img = _fbm(size, 0.6, size + b)
+    elif kind == "ramp":
+        y, x = np.mgrid[0:size, 0:size]
+        img = (7 * x + 3 * y).astype(np.uint8)
+    else:                     # piecewise constant: many exact ties
+        img = np.kron(rng.integers(0, 4, size=(size // 4, size // 4)) * 60,
+                      np.ones((4, 4))).astype(np.uint8)
+    ref = bf.brute_encode(img, b, t)
+    got = oracle_lib.encode(img, b, t)
+    for key in ("dom", "iso", "k", "j", "err"):
+        assert np.array_equal(got[key], ref[key]), key
+
+
+def test_search_with_pools_equals_bruteforce(oracle_lib):
+    img = _fbm(24, 0.5, 99)
+    b, t, tol = 4, 2, 0.15
+    fr, fd = oracle_lib.classify(img, b, t)
+    pools = [np.flatnonzero(np.abs(fd - x) <= tol + 1e-9) for x in fr]
+    assert min(len(p) for p in pools) < len(fd)          # the window really prunes
+    ref = bf.brute_encode(img, b, t, pools=pools)
+    got = oracle_lib.encode(img, b, t, tol=tol, fds=(fr, fd))
+    for i, p in enumerate(pools):
+        if len(p) == 0:
+            assert got["flags"][i] == 1
+            continue
+        for key in ("dom", "iso", "k", "j", "err"):
+            assert got[key][i] == ref[key][i], (i, key)
+    assert np.array_equal(got["pool"], np.array([len(p) for p in pools]))
+
+
+# ------------------------------------------------------------ planted cases
+def test_planted_zero_error_copy(oracle_lib):
+    """A range that is exactly s=1/2 times an isometric copy of a domain
+    (plus an even offset) is encoded with zero error."""
+    b, t = 4, 2
+    rng = np.random.default_rng(5)
+    img = _fbm(32, 0.5, 3)
+    v = 2 * rng.integers(10, 100, size=(b, b))           # even cell values
+    v[0, 0] += (-v.sum()) % (2 * b * b)                    # mean(v) even
+    assert v.sum() % (2 * b * b) == 0
+    dy, dx = 16, 16
+    img[dy:dy + 2 * b, dx:dx + 2 * b] = np.kron(v, np.ones((2, 2)))
+    q = 3
+    r_blk = (bf.isometries(v)[q] - v.mean()) // 2 + 2 * 30
+    ry, rx = 0, 4
+    img[ry:ry + b, rx:rx + b] = r_blk
+    ranges, doms = bf.lattice(32, 32, b, t)
+    r = ranges.index((ry, rx))
+    d = doms.index((dy, dx))
+    f, k = oracle_lib.pair_f(img, b, t, r, d, q)
+    assert (f, k) == (0, 8)
+    got = oracle_lib.encode(img, b, t, sel=[r])
+    assert got["err"][0] == 0
+    assert (got["dom"][0], got["iso"][0]) <= (d, q)
+
+
+def test_planted_unit_contrast_copy(oracle_lib):
+    """An exact copy (s = 1) is off the grid: k = 15 and F = 16 Srr'."""
+    b, t = 4, 2
+    img = _fbm(32, 0.5, 8)
+    rng = np.random.default_rng(1)
+    cells = rng.integers(0, 64, size=(b, b))               # D = 4 * cells
+    img[16:24, 8:16] = np.kron(cells, np.ones((2, 2)))
+    q = 6
+    r_blk = bf.isometries(cells)[q]
+    img[0:4, 0:4] = r_blk
+    ranges, doms = bf.lattice(32, 32, b, t)
+    f, k = oracle_lib.pair_f(img, b, t, ranges.index((0, 0)), doms.index((16, 8)), q)
+    n = b * b
+    srr = n * int((r_blk.astype(np.int64) ** 2).sum()) - int(r_blk.sum()) ** 2
+    assert k == 15 and f == 16 * srr
+
+
+def test_flat_range_takes_first_pair(oracle_lib):
+    img = _fbm(32, 0.5, 12)
+    img[8:12, 8:12] = 77
+    ranges, _ = bf.lattice(32, 32, 4, 2)
+    got = oracle_lib.encode(img, 4, 2, sel=[ranges.index((8, 8))])
+    assert (got["dom"][0], got["iso"][0], got["k"][0]) == (0, 0, 0)
+    n = 16
+    assert got["j"][0] == (77 * n + n - 1) // (2 * n)
+    assert got["err"][0] == 4096 * (77 * n - 2 * n * got["j"][0]) ** 2
+
+
+def test_empty_pool_gives_dc_code(oracle_lib):
+    img = _fbm(32, 0.5, 4)
+    fr, fd = oracle_lib.classify(img, 4, 2)
+    fr_far = fr + 10.0                                      # nothing within the window
+    got = oracle_lib.encode(img, 4, 2, tol=0.05, fds=(fr_far, fd))
+    assert np.all(got["flags"] == 1) and np.all(got["pool"] == 0)
+    assert np.all(got["dom"] == 0) and np.all(got["iso"] == 0) and np.all(got["k"] == 0)
+    exh = oracle_lib.encode(img, 4, 2)
+    assert np.all(got["err"] >= exh["err"])
+
+
+# ------------------------------------------------------- fractal dimension
+def test_dbc_golden_values(oracle_lib):
+    with open(os.path.join(GOLD, "dbc_values.json")) as f:
+        cases = json.load(f)["cases"]
+    for c in cases:
+        for m in c["M"]:
+            if c["name"].startswith("flat"):
+                blk = np.full((m, m), 93, dtype=np.uint8)
+            elif c["name"].startswith("0/255"):
+                blk = (((np.indices((m, m)).sum(axis=0)) % 2) * 255).astype(np.uint8)
+            else:
+                blk = np.zeros((m, m), dtype=np.uint8)
+                blk[m // 2 + 1, 1] = int(c["name"].split()[-1])
+            assert abs(oracle_lib.dbc_fd(blk) - c["fd"]) < 1e-12, (c["name"], m)
+
+
+def test_dbc_invariances(oracle_lib):
+    """Box counts do not change under the square isometries (cells map to
+    cells) nor under g -> 255 - g (h divides 256)."""
+    rng = np.random.default_rng(3)
+    for m in (4, 8, 16, 32):
+        for _ in range(6):
+            blk = _fbm(m, float(rng.uniform(0.1, 0.9)), int(rng.integers(1 << 30)))
+            fd0, c0 = oracle_lib.dbc_fd(blk, return_counts=True)
+            for q in range(8):
+                fdq, cq = oracle_lib.dbc_fd(bf.isometries(blk)[q].copy(), return_counts=True)
+                assert np.array_equal(cq, c0) and fdq == fd0
+            fdi, ci = oracle_lib.dbc_fd(255 - blk, return_counts=True)
+            assert np.array_equal(ci, c0)
+
+
+def test_dbc_range_and_weights(oracle_lib):
+    """The least-squares slope over s = 2..M equals the hand-derived
+    combination of log2 counts (M=8: log2 N_2 / 2; M=16:
+    0.3 log2 N_2 + 0.1 log2 N_4 - 0.1 log2 N_8), and lies in the [2, 3]
+    band the paper reports for natural content."""
+    rng = np.random.default_rng(17)
+    for _ in range(20):
+        img = _fbm(16, float(rng.uniform(0.2, 0.9)), int(rng.integers(1 << 30)))
+        fd8, c8 = oracle_lib.dbc_fd(img[:8, :8], return_counts=True)
+        assert abs(fd8 - 0.5 * math.log2(c8[0])) < 1e-12
+        fd16, c16 = oracle_lib.dbc_fd(img, return_counts=True)
+        ref = 0.3 * math.log2(c16[0]) + 0.1 * math.log2(c16[1]) - 0.1 * math.log2(c16[2])
+        assert abs(fd16 - ref) < 1e-12
+        assert c16[3] == 1
+    big = _fbm(256, 0.5, 1)
+    fd = oracle_lib.fd_blocks(big, 16, 8)
+    assert 1.8 < fd.min() and fd.max() < 3.2 and 2.0 <= np.median(fd) <= 3.0
+
+
+def test_fd_blocks_layout(oracle_lib):
+    img = _fbm(64, 0.4, 21)
+    for (m, step) in [(8, 8), (16, 1), (16, 3)]:
+        fd = oracle_lib.fd_blocks(img, m, step)
+        rows = (64 - m) // step + 1
+        a, c = 2, rows - 1
+        assert fd[a * rows + c] == oracle_lib.dbc_fd(img[a * step:a * step + m,
+                                                         c * step:c * step + m].copy())
+
+
+# -------------------------------------------------------------- the window
+def test_fractal_distance_closed_form(oracle_lib):
+    """Sec. 3.1: D_f = (F_m - F_l) / 3 over the domain set."""
+    fd = np.array([2.31, 2.02, 2.97, 2.5])
+    assert oracle_lib.resolve_tol(-1.0, fd) == pytest.approx((2.97 - 2.02) / 3, abs=1e-15)
+    assert oracle_lib.resolve_tol(0.05, fd) == 0.05
+
+
+def test_pool_limits(oracle_lib):
+    """Infinite tolerance is the exhaustive search; a wider window holds the
+    narrower one's pool, and a larger pool never does worse."""
+    img = _fbm(64, 0.5, 31)
+    b, t = 8, 2
+    fds = oracle_lib.classify(img, b, t)
+    exh = oracle_lib.encode(img, b, t)
+    inf = oracle_lib.encode(img, b, t, tol=float("inf"), fds=fds)
+    for key in ("dom", "iso", "k", "j", "err"):
+        assert np.array_equal(exh[key], inf[key])
+    prev = None
+    for tol in (0.02, 0.05, 0.1, 0.3):
+        cur = oracle_lib.encode(img, b, t, tol=tol, fds=fds)
+        assert np.all(cur["f"] >= exh["f"])
+        if prev is not None:
+            assert np.all(cur["pool"] >= prev["pool"])
+            assert np.all(cur["f"] <= prev["f"])
+        prev = cur
+    adaptive = oracle_lib.encode(img, b, t, tol=-1.0, fds=fds)
+    assert adaptive["tol"] == pytest.approx((fds[1].max() - fds[1].min()) / 3)
+
+
+def test_sampled_encode_matches_full(oracle_lib):
+    img = _fbm(64, 0.5, 2)
+    full = oracle_lib.encode(img, 8, 2, tol=0.05)
+    sel = np.array([0, 5, 17, 63, 40])
+    part = oracle_lib.encode(img, 8, 2, tol=0.05, sel=sel)
+    for key in ("dom", "iso", "k", "j", "err", "pool"):
+        assert np.array_equal(part[key], full[key][sel])
+
+
+# -------------------------------------------------------------- decoding
+def test_decode_flat_image_is_exact(oracle_lib):
+    img = np.full((32, 32), 100, dtype=np.uint8)
+    codes = oracle_lib.encode(img, 4, 2)
+    out, it = oracle_lib.decode(codes, 32, 32, 4, 2)
+    assert np.array_equal(out, img) and it == 2
+    assert oracle_lib.psnr(out, img) == float("inf")
+
+
+def test_decode_sweep_matches_float_definition(oracle_lib):
+    rng = np.random.default_rng(9)
+    for (size, b, t) in [(32, 4, 2), (32, 8, 1), (64, 16, 4)]:
+        ranges, doms = bf.lattice(size, size, b, t)
+        nr = len(ranges)
+        codes = {"dom": rng.integers(0, len(doms), nr), "iso": rng.integers(0, 8, nr),
+                 "k": rng.integers(-16, 16, nr), "j": rng.integers(0, 128, nr)}
+        start = rng.integers(0, 256, size=(size, size)).astype(np.uint8)
+        cur = start
+        for it in range(1, 4):
+            cur = bf.decode_sweep_float(cur, codes, b, t)
+            got, done = oracle_lib.decode(codes, size, size, b, t, max_iters=it, init=start)
+            assert np.array_equal(got, cur) and done <= it
+
+
+def test_decode_reconstructs_encoding(oracle_lib):
+    img = _fbm(64, 0.7, 13)
+    codes = oracle_lib.encode(img, 4, 2)
+    out, it = oracle_lib.decode(codes, 64, 64, 4, 2)
+    assert oracle_lib.psnr(out, img) > 28.0
+    assert it <= 32
+
+
+def test_window_is_closed(oracle_lib):
+    """Sec. 3.1 bounds the window with <= on both sides: a domain exactly
+    D_f away is in the pool, including when fp64 subtraction lands an ulp
+    outside (2.1 - 2.0 = 0.10000000000000009); the 1e-9 guard keeps it."""
+    img = _fbm(32, 0.5, 4)
+    fr, fd = oracle_lib.classify(img, 4, 2)
+    fr = np.full_like(fr, 2.0)
+    fd = np.full_like(fd, 5.0)
+    fd[[3, 7]] = [2.1, 1.9]                  # exactly 0.1 away in real arithmetic
+    fd[11] = 2.1 + 2e-9                      # clearly outside
+    got = oracle_lib.encode(img, 4, 2, tol=0.1, fds=(fr, fd))
+    assert np.all(got["pool"] == 2)
+    assert set(np.unique(got["dom"])) <= {3, 7}
