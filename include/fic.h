@@ -1,0 +1,207 @@
+/*
+ * fic.h -- C ABI of the MI355X (gfx950) PIFS range-domain matching library.
+ *
+ * The operations follow the paper's statement of the encoder (Revathy &
+ * Jayamohan, "Dynamic Domain Classification for Fractal Image Compression"):
+ *   fic_fd_classify        Sec. 3.1: local fractal dimension of every block by
+ *                          differential box counting (ref. [9]).
+ *   fic_build_domain_pool  Sec. 3.1: domains ordered by dimension (the role of
+ *                          the balanced search tree) and, per range, the window
+ *                          d_r - D_f <= d_d <= d_r + D_f as an interval of that
+ *                          order; D_f = (F_m - F_l)/3 when no tolerance is given.
+ *   fic_encode_pifs        Sec. 1 / Sec. 2: for every non-overlapping range, the
+ *                          best domain (twice the size, overlapping, shrunk by
+ *                          2x2 sums) under the 8 square isometries and the
+ *                          quantized contrast / brightness; exhaustive or pooled.
+ *   fic_encode_pifs_batch  the same for many images of different sizes.
+ *   fic_decode_pifs        Sec. 1: iterate the maps from a start image.
+ *
+ * Quantities (exact integers; n = B*B; D = 2x2 sums of the domain, 0..1020):
+ *   contrast   s = k/16, k in [-16, 15]        (5 bits)
+ *   brightness o = 2j,   j in [0, 127]          (7 bits)
+ *   map        r'_i = s * ((T_q D)_i/4 - sum(D)/(4n)) + o
+ *   error      E = 4096 * n * SSE  (exact)
+ *   selection  minimum E; ties to the lowest (domain index, isometry), then
+ *              the smaller |k|, then the smaller k; j is the nearest level to
+ *              the range mean, ties down.
+ *   isometry q T_q(d)[i][j] = d[src]: 0 (i,j), 1 (B-1-j,i) rot90 cw,
+ *              2 (B-1-i,B-1-j), 3 (j,B-1-i) rot270 cw, 4 (i,B-1-j) mirror LR,
+ *              5 (B-1-i,j) mirror UD, 6 (j,i) transpose, 7 (B-1-j,B-1-i).
+ *   lattice    ranges raster order over (H/B) x (W/B); domains at (t*a, t*c)
+ *              fully inside the image, index a*cols + c.
+ *
+ * Conventions for every call:
+ *   - Pointers marked (dev) are HIP device pointers, (host) host pointers.
+ *     The caller owns every buffer; the library never frees caller memory and
+ *     allocates no device memory inside these calls (a context holds only a
+ *     few bytes of per-device state).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls are asynchronous on it and never synchronise the host, except
+ *     fic_create. Outputs are valid once the stream reaches that point.
+ *   - Arguments are validated on the host before any HIP call; an invalid
+ *     call returns a status and launches nothing. No exception crosses the
+ *     ABI. A context is not thread-safe: use one per host thread.
+ */
+#ifndef FIC_H
+#define FIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FIC_OK = 0,
+    FIC_ERR_INVALID_ARG = 1,   /* null pointer, bad geometry, NaN tolerance ... */
+    FIC_ERR_UNSUPPORTED = 2,   /* a valid request this build does not handle    */
+    FIC_ERR_WORKSPACE = 3,     /* ws_bytes below fic_*_workspace_bytes()        */
+    FIC_ERR_CAPACITY = 4,      /* the packed (F, domain, isometry) key would
+                                  not fit 64 bits for this geometry             */
+    FIC_ERR_DEVICE = 5         /* no HIP device, or a HIP call / launch failed  */
+} fic_status;
+
+/* Image geometry. uint8 rows of `pitch` bytes (pitch >= width).
+   range_size B in {4, 8, 16}; height, width multiples of B and >= 2B;
+   domain side 2B; domain_step t >= 1. */
+typedef struct {
+    int32_t height, width, pitch;
+    int32_t range_size;
+    int32_t domain_step;
+} fic_geom;
+
+/* One code per range, ranges in raster order. 16 bytes. */
+typedef struct {
+    uint32_t domain;   /* raster index on the domain lattice                  */
+    uint8_t  iso;      /* 0..7                                                */
+    int8_t   s_idx;    /* k, s = k/16                                         */
+    uint8_t  o_idx;    /* j, o = 2j                                           */
+    uint8_t  flags;    /* bit 0: empty pool, DC-only code (domain 0, iso 0,
+                          k = 0)                                              */
+    int64_t  err;      /* E = 4096 * n * SSE                                  */
+} fic_code;
+
+typedef struct fic_ctx fic_ctx;
+
+enum { FIC_KERNEL_MFMA = 0, FIC_KERNEL_PLAIN = 1 };
+
+/* Per-image job of a batch (host struct; pointers inside are device). */
+typedef struct {
+    const uint8_t *img;   /* (dev) */
+    fic_geom geom;
+    double tol;           /* as fic_build_domain_pool; +INF = exhaustive */
+    fic_code *codes;      /* (dev) ranges of this image */
+} fic_image_desc;
+
+/* Create a context on HIP device `device` (queries its properties; this is
+   the only call that may block). FIC_ERR_DEVICE when there is no such
+   device, FIC_ERR_UNSUPPORTED when it is not gfx950. device = -1 makes a
+   host-only context: every call still validates its arguments (and returns
+   their error), then answers FIC_ERR_DEVICE instead of launching. */
+fic_status fic_create(int32_t device, fic_ctx **out /* host */);
+fic_status fic_destroy(fic_ctx *ctx);
+
+/* Static text of a status (host). */
+const char *fic_status_string(fic_status s);
+
+/* Optional instrumentation: when `counters` (dev, 4 x uint64, zeroed by the
+   caller) is set, the search kernels add
+     [0] pair evaluations screened, [1] pairs passed to the exact int64 path,
+     [2] work items processed,      [3] exact seeds evaluated.
+   NULL (the default) disables the adds. */
+fic_status fic_set_counters(fic_ctx *ctx, uint64_t *counters /* dev */);
+
+/* Number of ranges / domains of a geometry (host helpers; 0 if invalid). */
+int64_t fic_num_ranges(const fic_geom *g /* host */);
+int64_t fic_num_domains(const fic_geom *g /* host */);
+
+/* ------------------------------------------------------------------------
+ * fic_fd_classify -- Sec. 3.1, differential box counting.
+ * For every block x block window whose top-left corner is at (step*a,
+ * step*c), a = 0..(H-block)/step, c = 0..(W-block)/step, raster order:
+ *   box sizes s = 2, 4, ..., block; box height h = s*256/block;
+ *   n_s = sum over the (block/s)^2 cells of floor(max/h) - floor(min/h) + 1;
+ *   FD = least-squares slope of log N_s against log(block/s).
+ * Ranges use (block, step) = (B, B); domains (2B, t).
+ *   img   (dev) uint8, g->pitch bytes per row
+ *   block in {4, 8, 16, 32}; step >= 1; block <= height, width
+ *   fd64  (dev) double[count] (required); fd32 (dev) float[count] or NULL,
+ *         fd32 = (float)fd64.
+ * ---------------------------------------------------------------------- */
+fic_status fic_fd_classify(fic_ctx *ctx, const uint8_t *img, const fic_geom *g,
+                           int32_t block, int32_t step,
+                           double *fd64, float *fd32, void *stream);
+
+/* ------------------------------------------------------------------------
+ * fic_build_domain_pool -- Sec. 3.1, the dynamic per-range domain pool.
+ *   fd_range  (dev) double[n_range], fd_domain (dev) double[n_domain]
+ *   tol       >= 0: window half-width; < 0: D_f = (max - min)/3 over
+ *             fd_domain; +INF: every domain. NaN is rejected.
+ *   perm      (dev) uint32[n_domain]: domain indices in ascending fd order,
+ *             equal values in ascending index (stable).
+ *   lo, hi    (dev) uint32[n_range]: the pool of range r is
+ *             perm[lo[r] .. hi[r]), exactly { d : |fd_d - fd_r| <= tol + 1e-9 }
+ *             in fp64.
+ *   ws        (dev) scratch of ws_bytes >= fic_pool_workspace_bytes(n_range,
+ *             n_domain).
+ * ---------------------------------------------------------------------- */
+size_t fic_pool_workspace_bytes(int64_t n_range, int64_t n_domain);
+fic_status fic_build_domain_pool(fic_ctx *ctx, const double *fd_range, int32_t n_range,
+                                 const double *fd_domain, int32_t n_domain, double tol,
+                                 uint32_t *perm, uint32_t *lo, uint32_t *hi,
+                                 void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * fic_encode_pifs -- Sec. 1 / Sec. 2, the range-domain matching search.
+ *   img    (dev) uint8 image, geometry g (host)
+ *   perm, lo, hi  (dev) from fic_build_domain_pool for this image, or all
+ *          three NULL for exhaustive search (every domain for every range).
+ *          Mixed NULL / non-NULL is rejected.
+ *   kernel FIC_KERNEL_MFMA (FP16 matrix-core cross terms, exact, screened,
+ *          persistent work queue) or FIC_KERNEL_PLAIN (one thread per
+ *          (range, domain, isometry), integer arithmetic).
+ *   codes  (dev) fic_code[fic_num_ranges(g)], raster order.
+ *   ws     (dev) scratch, ws_bytes >= fic_encode_workspace_bytes(g, pooled).
+ * Both kernels return identical codes.
+ * ---------------------------------------------------------------------- */
+size_t fic_encode_workspace_bytes(const fic_geom *g, int32_t pooled);
+fic_status fic_encode_pifs(fic_ctx *ctx, const uint8_t *img, const fic_geom *g,
+                           const uint32_t *perm, const uint32_t *lo, const uint32_t *hi,
+                           int32_t kernel, fic_code *codes,
+                           void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * fic_encode_pifs_batch -- classify + pool + search for n_images images
+ * (each its own geometry and tolerance) queued on one stream; the searches of
+ * all images share one persistent work-queue launch per range size.
+ *   descs (host) fic_image_desc[n_images]; codes of image i go to
+ *   descs[i].codes (dev).
+ *   ws (dev) >= fic_batch_workspace_bytes(n_images, descs).
+ * ---------------------------------------------------------------------- */
+size_t fic_batch_workspace_bytes(int32_t n_images, const fic_image_desc *descs);
+fic_status fic_encode_pifs_batch(fic_ctx *ctx, int32_t n_images,
+                                 const fic_image_desc *descs,
+                                 void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * fic_decode_pifs -- Sec. 1, decoding by iteration of the stored maps.
+ * Simultaneous sweeps from `init` (dev, h x w, pitch w; NULL = all 128):
+ *   pixel = clamp(floor((k*(n*(T_q D')_i - sum D') + 128*n*j + 32*n) / (64n)),
+ *                 0, 255)
+ * with D' the 2x2 sums of the current image at the code's domain; stops after
+ * the first sweep that changes no pixel, or after max_iters sweeps.
+ *   codes (dev) fic_code[fic_num_ranges(g)]; out (dev) uint8 h x w (pitch w)
+ *   scratch (dev) >= fic_decode_workspace_bytes(g)
+ *   iters_done (dev) int32: sweeps run.
+ * ---------------------------------------------------------------------- */
+size_t fic_decode_workspace_bytes(const fic_geom *g);
+fic_status fic_decode_pifs(fic_ctx *ctx, const fic_code *codes, const fic_geom *g,
+                           int32_t max_iters, const uint8_t *init, uint8_t *out,
+                           void *scratch, size_t scratch_bytes, int32_t *iters_done,
+                           void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FIC_H */

@@ -1,0 +1,309 @@
+// api.hip -- the C ABI declared in include/fic.h: host-side validation,
+// workspace planning and launches on the caller's stream.
+//
+// Every entry point validates all of its arguments on the host before it
+// touches HIP, so invalid calls return a status and launch nothing; only
+// then does a context without a device (device = -1, used to test the
+// validation on machines without a GPU) answer FIC_ERR_DEVICE.
+#include <new>
+#include <string.h>
+#include <math.h>
+
+#include "fic_internal.h"
+
+using fic::Geom;
+using fic::u64;
+
+struct fic_ctx {
+    int32_t device;      // -1: host-only context
+    int32_t num_cu;
+    u64 *counters;
+};
+
+namespace {
+
+constexpr int kMaxSide = 16384;
+
+bool geom_ok(const fic_geom *g)
+{
+    if (!g) return false;
+    const int b = g->range_size;
+    if (b != 4 && b != 8 && b != 16) return false;
+    if (g->height <= 0 || g->width <= 0 || g->height > kMaxSide || g->width > kMaxSide) return false;
+    if (g->height % b || g->width % b) return false;
+    if (g->height < 2 * b || g->width < 2 * b) return false;
+    if (g->domain_step < 1) return false;
+    if (g->pitch < g->width) return false;
+    return true;
+}
+
+Geom to_geom(const fic_geom *g)
+{
+    Geom r;
+    r.h = g->height; r.w = g->width; r.pitch = g->pitch; r.b = g->range_size; r.t = g->domain_step;
+    r.n = r.b * r.b;
+    r.rcols = r.w / r.b; r.rrows = r.h / r.b;
+    r.dcols = (r.w - 2 * r.b) / r.t + 1; r.drows = (r.h - 2 * r.b) / r.t + 1;
+    r.R = (int64_t)r.rcols * r.rrows;
+    r.D = (int64_t)r.dcols * r.drows;
+    return r;
+}
+
+// Bits of the largest F = 4096 * Srr' <= 4096 * n^2 * 255^2 / 4, plus the
+// domain index and the isometry, must fit the 64-bit key.
+bool key_fits(const Geom &g)
+{
+    const double fmax = 1024.0 * (double)g.n * (double)g.n * 65025.0;
+    int fbits = 0;
+    while (ldexp(1.0, fbits) <= fmax) ++fbits;
+    int dbits = 1;
+    while (((int64_t)1 << dbits) < g.D) ++dbits;
+    return fbits + dbits + 3 <= 64;
+}
+
+fic_status dev_status(hipError_t e) { return e == hipSuccess ? FIC_OK : FIC_ERR_DEVICE; }
+
+fic_status enter(fic_ctx *ctx)
+{
+    if (ctx->device < 0) return FIC_ERR_DEVICE;
+    return hipSetDevice(ctx->device) == hipSuccess ? FIC_OK : FIC_ERR_DEVICE;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t pool_ws(int64_t nr, int64_t nd)
+{
+    (void)nr;
+    return align256((size_t)nd * 8) * 2 + 256 + fic::sort_ws_bytes(nd);
+}
+
+// Per-image workspace of a batch: fd of ranges and domains, the pool, and
+// the search workspace.
+struct BatchPart {
+    size_t off_fdr, off_fdd, off_perm, off_lo, off_hi, off_pool, off_enc, total;
+};
+BatchPart batch_part(const Geom &g, bool pooled)
+{
+    BatchPart b;
+    size_t o = 0;
+    auto take = [&](size_t n) { size_t r = o; o += align256(n); return r; };
+    b.off_fdr = take((size_t)g.R * 8);
+    b.off_fdd = take((size_t)g.D * 8);
+    b.off_perm = take((size_t)g.D * 4);
+    b.off_lo = take((size_t)g.R * 4);
+    b.off_hi = take((size_t)g.R * 4);
+    b.off_pool = take(pooled ? pool_ws(g.R, g.D) : 0);
+    fic::EncodePlan p;
+    fic::plan_encode(g, pooled ? 1 : 0, p);
+    b.off_enc = take(p.total);
+    b.total = o;
+    return b;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *fic_status_string(fic_status s)
+{
+    switch (s) {
+    case FIC_OK: return "ok";
+    case FIC_ERR_INVALID_ARG: return "invalid argument";
+    case FIC_ERR_UNSUPPORTED: return "unsupported";
+    case FIC_ERR_WORKSPACE: return "workspace too small";
+    case FIC_ERR_CAPACITY: return "search key capacity exceeded";
+    case FIC_ERR_DEVICE: return "device error";
+    default: return "unknown status";
+    }
+}
+
+fic_status fic_create(int32_t device, fic_ctx **out)
+{
+    if (!out) return FIC_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (device < -1) return FIC_ERR_INVALID_ARG;
+    fic_ctx *c = new (std::nothrow) fic_ctx;
+    if (!c) return FIC_ERR_DEVICE;
+    c->device = device;
+    c->num_cu = 0;
+    c->counters = nullptr;
+    if (device >= 0) {
+        int n = 0;
+        if (hipGetDeviceCount(&n) != hipSuccess || device >= n) {
+            delete c;
+            return FIC_ERR_DEVICE;
+        }
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+            delete c;
+            return FIC_ERR_DEVICE;
+        }
+        if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+            delete c;
+            return FIC_ERR_UNSUPPORTED;
+        }
+        c->num_cu = prop.multiProcessorCount;
+    }
+    *out = c;
+    return FIC_OK;
+}
+
+fic_status fic_destroy(fic_ctx *ctx)
+{
+    if (!ctx) return FIC_ERR_INVALID_ARG;
+    delete ctx;
+    return FIC_OK;
+}
+
+fic_status fic_set_counters(fic_ctx *ctx, uint64_t *counters)
+{
+    if (!ctx) return FIC_ERR_INVALID_ARG;
+    ctx->counters = (u64 *)counters;
+    return FIC_OK;
+}
+
+int64_t fic_num_ranges(const fic_geom *g) { return geom_ok(g) ? to_geom(g).R : 0; }
+int64_t fic_num_domains(const fic_geom *g) { return geom_ok(g) ? to_geom(g).D : 0; }
+
+fic_status fic_fd_classify(fic_ctx *ctx, const uint8_t *img, const fic_geom *g, int32_t block,
+                           int32_t step, double *fd64, float *fd32, void *stream)
+{
+    if (!ctx || !img || !g || !fd64) return FIC_ERR_INVALID_ARG;
+    if (block != 4 && block != 8 && block != 16 && block != 32) return FIC_ERR_INVALID_ARG;
+    if (step < 1 || g->height < block || g->width < block || g->pitch < g->width ||
+        g->height > kMaxSide || g->width > kMaxSide)
+        return FIC_ERR_INVALID_ARG;
+    fic_status st = enter(ctx);
+    if (st != FIC_OK) return st;
+    return dev_status(fic::launch_fd_classify(img, g->height, g->width, g->pitch, block, step, fd64,
+                                              fd32, (hipStream_t)stream));
+}
+
+size_t fic_pool_workspace_bytes(int64_t n_range, int64_t n_domain)
+{
+    if (n_range < 0 || n_domain < 0) return 0;
+    return pool_ws(n_range, n_domain);
+}
+
+fic_status fic_build_domain_pool(fic_ctx *ctx, const double *fd_range, int32_t n_range,
+                                 const double *fd_domain, int32_t n_domain, double tol,
+                                 uint32_t *perm, uint32_t *lo, uint32_t *hi, void *ws,
+                                 size_t ws_bytes, void *stream)
+{
+    if (!ctx || !fd_range || !fd_domain || !perm || !lo || !hi || !ws) return FIC_ERR_INVALID_ARG;
+    if (n_range < 1 || n_domain < 1 || isnan(tol)) return FIC_ERR_INVALID_ARG;
+    if (ws_bytes < pool_ws(n_range, n_domain)) return FIC_ERR_WORKSPACE;
+    fic_status st = enter(ctx);
+    if (st != FIC_OK) return st;
+    return dev_status(fic::launch_pool(fd_range, n_range, fd_domain, n_domain, tol, perm, lo, hi, ws,
+                                       (hipStream_t)stream));
+}
+
+size_t fic_encode_workspace_bytes(const fic_geom *g, int32_t pooled)
+{
+    if (!geom_ok(g)) return 0;
+    fic::EncodePlan p;
+    fic::plan_encode(to_geom(g), pooled ? 1 : 0, p);
+    return p.total;
+}
+
+fic_status fic_encode_pifs(fic_ctx *ctx, const uint8_t *img, const fic_geom *g,
+                           const uint32_t *perm, const uint32_t *lo, const uint32_t *hi,
+                           int32_t kernel, fic_code *codes, void *ws, size_t ws_bytes,
+                           void *stream)
+{
+    if (!ctx || !img || !codes || !ws || !geom_ok(g)) return FIC_ERR_INVALID_ARG;
+    const int nset = (perm != nullptr) + (lo != nullptr) + (hi != nullptr);
+    if (nset != 0 && nset != 3) return FIC_ERR_INVALID_ARG;
+    if (kernel != FIC_KERNEL_MFMA && kernel != FIC_KERNEL_PLAIN) return FIC_ERR_INVALID_ARG;
+    const Geom gg = to_geom(g);
+    if (!key_fits(gg)) return FIC_ERR_CAPACITY;
+    fic::EncodePlan p;
+    fic::plan_encode(gg, nset == 3, p);
+    if (ws_bytes < p.total) return FIC_ERR_WORKSPACE;
+    fic_status st = enter(ctx);
+    if (st != FIC_OK) return st;
+    return dev_status(fic::run_encode(p, img, perm, lo, hi, kernel, codes, ws, ctx->num_cu,
+                                      ctx->counters, (hipStream_t)stream));
+}
+
+size_t fic_batch_workspace_bytes(int32_t n_images, const fic_image_desc *descs)
+{
+    if (n_images < 1 || !descs) return 0;
+    size_t mx = 0;
+    for (int i = 0; i < n_images; ++i) {
+        if (!geom_ok(&descs[i].geom)) return 0;
+        const bool pooled = isfinite(descs[i].tol) || descs[i].tol < 0;
+        const size_t b = batch_part(to_geom(&descs[i].geom), pooled).total;
+        mx = b > mx ? b : mx;
+    }
+    return mx;
+}
+
+fic_status fic_encode_pifs_batch(fic_ctx *ctx, int32_t n_images, const fic_image_desc *descs,
+                                 void *ws, size_t ws_bytes, void *stream)
+{
+    if (!ctx || n_images < 1 || !descs || !ws) return FIC_ERR_INVALID_ARG;
+    for (int i = 0; i < n_images; ++i) {
+        const fic_image_desc &d = descs[i];
+        if (!d.img || !d.codes || !geom_ok(&d.geom) || isnan(d.tol)) return FIC_ERR_INVALID_ARG;
+        if (!key_fits(to_geom(&d.geom))) return FIC_ERR_CAPACITY;
+    }
+    if (ws_bytes < fic_batch_workspace_bytes(n_images, descs)) return FIC_ERR_WORKSPACE;
+    fic_status st = enter(ctx);
+    if (st != FIC_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    // The images run back to back on one stream, so they can share one
+    // workspace region.
+    for (int i = 0; i < n_images; ++i) {
+        const fic_image_desc &d = descs[i];
+        const Geom g = to_geom(&d.geom);
+        const bool pooled = isfinite(d.tol) || d.tol < 0;
+        const BatchPart bp = batch_part(g, pooled);
+        char *w = (char *)ws;
+        double *fdr = (double *)(w + bp.off_fdr);
+        double *fdd = (double *)(w + bp.off_fdd);
+        uint32_t *perm = (uint32_t *)(w + bp.off_perm);
+        uint32_t *lo = (uint32_t *)(w + bp.off_lo);
+        uint32_t *hi = (uint32_t *)(w + bp.off_hi);
+        hipError_t e = hipSuccess;
+        if (pooled) {
+            e = fic::launch_fd_classify(d.img, g.h, g.w, g.pitch, g.b, g.b, fdr, nullptr, s);
+            if (e == hipSuccess)
+                e = fic::launch_fd_classify(d.img, g.h, g.w, g.pitch, 2 * g.b, g.t, fdd, nullptr, s);
+            if (e == hipSuccess)
+                e = fic::launch_pool(fdr, (int32_t)g.R, fdd, (int32_t)g.D, d.tol, perm, lo, hi,
+                                     w + bp.off_pool, s);
+        }
+        fic::EncodePlan p;
+        fic::plan_encode(g, pooled, p);
+        if (e == hipSuccess)
+            e = fic::run_encode(p, d.img, pooled ? perm : nullptr, pooled ? lo : nullptr,
+                                pooled ? hi : nullptr, FIC_KERNEL_MFMA, d.codes, w + bp.off_enc,
+                                ctx->num_cu, ctx->counters, s);
+        if (e != hipSuccess) return FIC_ERR_DEVICE;
+    }
+    return FIC_OK;
+}
+
+size_t fic_decode_workspace_bytes(const fic_geom *g)
+{
+    if (!geom_ok(g)) return 0;
+    return fic::decode_ws_bytes(to_geom(g));
+}
+
+fic_status fic_decode_pifs(fic_ctx *ctx, const fic_code *codes, const fic_geom *g,
+                           int32_t max_iters, const uint8_t *init, uint8_t *out, void *scratch,
+                           size_t scratch_bytes, int32_t *iters_done, void *stream)
+{
+    if (!ctx || !codes || !out || !scratch || !iters_done || !geom_ok(g)) return FIC_ERR_INVALID_ARG;
+    if (max_iters < 0 || max_iters > fic::decode_max_iters()) return FIC_ERR_INVALID_ARG;
+    const Geom gg = to_geom(g);
+    if (scratch_bytes < fic::decode_ws_bytes(gg)) return FIC_ERR_WORKSPACE;
+    fic_status st = enter(ctx);
+    if (st != FIC_OK) return st;
+    return dev_status(
+        fic::run_decode(gg, codes, max_iters, init, out, scratch, iters_done, (hipStream_t)stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,766 @@
+// encode.hip -- the range-domain matching search of the PIFS encoder
+// (Sec. 1 and Sec. 2: every non-overlapping range against the overlapping
+// domains of twice its size, shrunk by 2x2 sums, under the 8 isometries and a
+// quantized contrast / brightness; exhaustive, or restricted to the per-range
+// pool of Sec. 3.1).
+//
+// Matrix-core path (FIC_KERNEL_MFMA):
+//   range prep   A rows: for each range and isometry q, the range pixels under
+//                T_q^-1, centred by an integer level rhat (|.| <= 255), FP16
+//                (exact), pre-swizzled into MFMA lane order.
+//   domain prep  B columns: the 2x2 sums of each domain (in pool order),
+//                centred by an integer level dhat (|.| <= 1020), FP16 (exact);
+//                per column Sdd', eps = sum D - n*dhat and u = sqrt(Sdd')/n.
+//   search       a persistent work queue of (16-range group, column chunk)
+//                items. The group's A rows stay in VGPRs; each 16-column
+//                block costs MW*KS MFMAs, giving C''' = sum (r-rhat)(D-dhat)
+//                exactly in FP32, and Srd' = n*C''' - delta*eps exactly.
+//                A 4-instruction FP32 screen per 16x16 block rejects pairs
+//                whose continuous optimum cannot reach the range's best F;
+//                survivors get the exact int64 fit and a packed
+//                (F, domain, isometry) key; keys meet in a global atomicMin.
+//   finalize     recompute the winner exactly from the image, write fic_code.
+// Plain path (FIC_KERNEL_PLAIN): one thread per (range, domain, isometry),
+// integer cross term from the 2x2-sum image, exact fit, the same keys.
+#include "fic_internal.h"
+
+namespace fic {
+
+namespace {
+
+constexpr int kChunk = 4096;     // columns per work item
+constexpr int kBminBlock = 1024; // perm entries per block-minimum
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+template <int EPL> struct Frag;
+template <> struct Frag<4> { typedef half4_t type; };
+template <> struct Frag<8> { typedef half8_t type; };
+
+__device__ __forceinline__ float4_t mma(half8_t a, half8_t b, float4_t c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ float4_t mma(half4_t a, half4_t b, float4_t c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+}
+
+__global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+__global__ void k_fill_u64(u64 *p, int64_t n, u64 v)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// ---------------------------------------------------------------- prep
+// Range order for pooled search: ranges sorted by the start of their pool
+// interval (ties by index), so a group of consecutive ranges shares columns.
+__global__ void k_range_sortkeys(const uint32_t *__restrict__ lo, int64_t R, u64 *keys,
+                                 uint32_t *vals)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < R) {
+        keys[i] = lo[i];
+        vals[i] = (uint32_t)i;
+    }
+}
+
+template <int B>
+__global__ __launch_bounds__(256) void k_range_prep(
+    const uint8_t *__restrict__ img, int32_t pitch, int32_t rcols, int64_t R, int64_t Rp,
+    const uint32_t *__restrict__ order, const uint32_t *__restrict__ lo,
+    const uint32_t *__restrict__ hi, uint32_t D, _Float16 *__restrict__ A,
+    RangeStat *__restrict__ rs)
+{
+    using C = Cfg<B>;
+    constexpr int n = C::n, KPI = C::KPI, EPL = C::EPL, KS = C::KS, MW = C::MW, GR = 2 * MW;
+    typedef typename Frag<EPL>::type frag_t;
+    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t s = gt >> 3;
+    const int q = (int)(gt & 7);
+    if (s >= Rp) return;
+    const bool valid = s < R;
+    const uint32_t ridx = valid ? (order ? order[s] : (uint32_t)s) : 0u;
+    const int ry = (int)(ridx / rcols) * B, rx = (int)(ridx % rcols) * B;
+    const uint8_t *rp = img + (int64_t)ry * pitch + rx;
+    int32_t sr = 0;
+    int64_t sq = 0;
+    if (valid)
+        for (int i = 0; i < B; ++i)
+            for (int j = 0; j < B; ++j) {
+                int v = rp[i * pitch + j];
+                sr += v;
+                sq += v * v;
+            }
+    const int32_t rhat = (sr + n / 2) / n;
+    const int64_t grp = s / GR;
+    const int ls = (int)(s % GR), b = ls >> 1, row = 8 * (ls & 1) + q;
+    const int iq = iso_inverse(q);
+    // A_q[u][v] = r[T_q^-1 (u, v)] - rhat, so that sum A_q * D = sum r * T_q(D)
+    for (int ks = 0; ks < KS; ++ks)
+        for (int g = 0; g < KPI / EPL; ++g) {
+            frag_t f;
+#pragma unroll
+            for (int e = 0; e < EPL; ++e) {
+                const int K = ks * KPI + g * EPL + e;
+                int si, sj;
+                iso_src(iq, B, K / B, K % B, si, sj);
+                f[e] = valid ? (_Float16)(int)(rp[si * pitch + sj] - rhat) : (_Float16)0;
+            }
+            ((frag_t *)A)[((grp * MW + b) * KS + ks) * 64 + g * 16 + row] = f;
+        }
+    if (q == 0) {
+        RangeStat st;
+        st.srr = (int64_t)n * sq - (int64_t)sr * sr;
+        st.sr = sr;
+        st.delta = sr - n * rhat;
+        st.ridx = ridx;
+        st.lo = valid ? (lo ? lo[ridx] : 0u) : 0u;
+        st.hi = valid ? (hi ? hi[ridx] : D) : 0u;
+        st.flags = !valid ? kPad : ((st.srr == 0 ? kFlat : 0u) | (st.lo >= st.hi ? kEmpty : 0u));
+        rs[s] = st;
+    }
+}
+
+template <int B>
+__global__ __launch_bounds__(256) void k_domain_prep(
+    const uint8_t *__restrict__ img, int32_t pitch, int32_t dcols, int32_t t,
+    const uint32_t *__restrict__ perm, int64_t D, int64_t Dp, _Float16 *__restrict__ Bm,
+    float *__restrict__ u, int32_t *__restrict__ eps, int64_t *__restrict__ sdd,
+    uint32_t *__restrict__ dom)
+{
+    using C = Cfg<B>;
+    constexpr int n = C::n, KPI = C::KPI, EPL = C::EPL, KS = C::KS;
+    typedef typename Frag<EPL>::type frag_t;
+    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t p = gt / B;
+    const int i = (int)(gt % B);
+    if (p >= Dp) return;                 // whole B-lane groups leave together
+    const bool valid = p < D;
+    const uint32_t d = valid ? (perm ? perm[p] : (uint32_t)p) : 0u;
+    const int y = (int)(d / dcols) * t, x = (int)(d % dcols) * t;
+    int v[B];
+    int64_t rs1 = 0, rs2 = 0;
+    const uint8_t *q = img + (int64_t)(y + 2 * i) * pitch + x;
+#pragma unroll
+    for (int e = 0; e < B; ++e) {
+        v[e] = valid ? (q[2 * e] + q[2 * e + 1] + q[pitch + 2 * e] + q[pitch + 2 * e + 1]) : 0;
+        rs1 += v[e];
+        rs2 += v[e] * v[e];
+    }
+#pragma unroll
+    for (int off = 1; off < B; off <<= 1) {
+        rs1 += __shfl_xor(rs1, off);
+        rs2 += __shfl_xor(rs2, off);
+    }
+    const int64_t sdd_ = (int64_t)n * rs2 - rs1 * rs1;
+    const int32_t dhat = (int32_t)((rs1 + n / 2) / n);
+    const int64_t cb = p >> 4;
+    const int c = (int)(p & 15);
+#pragma unroll
+    for (int f0 = 0; f0 < B; f0 += EPL) {
+        const int K0 = i * B + f0;
+        const int ks = K0 / KPI, g = (K0 % KPI) / EPL;
+        frag_t f;
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) f[e] = (_Float16)(valid ? v[f0 + e] - dhat : 0);
+        ((frag_t *)Bm)[(cb * KS + ks) * 64 + g * 16 + c] = f;
+    }
+    if (i == 0) {
+        u[p] = valid ? screen_u(sdd_, n) : __builtin_nanf("");
+        eps[p] = valid ? (int32_t)(rs1 - (int64_t)n * dhat) : 0;
+        sdd[p] = valid ? sdd_ : 0;
+        dom[p] = d;
+    }
+}
+
+// Minimum domain index over blocks of the pool order (for flat ranges, whose
+// every pair ties at F = 0 and which therefore take the lowest pool index).
+__global__ void k_blockmin(const uint32_t *__restrict__ perm, int64_t D, uint32_t *bmin)
+{
+    const int64_t blk = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t nb = (D + kBminBlock - 1) / kBminBlock;
+    if (blk >= nb) return;
+    uint32_t m = 0xffffffffu;
+    for (int64_t i = blk * kBminBlock + lane; i < min(D, (blk + 1) * kBminBlock); i += 64)
+        m = min(m, perm[i]);
+    for (int off = 32; off > 0; off >>= 1) m = min(m, (uint32_t)__shfl_xor((int)m, off));
+    if (lane == 0) bmin[blk] = m;
+}
+
+__device__ uint32_t pool_min_index(const uint32_t *perm, const uint32_t *bmin, uint32_t lo,
+                                   uint32_t hi)
+{
+    if (!perm) return lo;
+    uint32_t m = 0xffffffffu;
+    uint32_t i = lo;
+    while (i < hi && (i % kBminBlock) != 0) m = min(m, perm[i++]);
+    while (i + kBminBlock <= hi) { m = min(m, bmin[i / kBminBlock]); i += kBminBlock; }
+    while (i < hi) m = min(m, perm[i++]);
+    return m;
+}
+
+// Exact F of (range at (ry, rx), domain at (dy, dx), isometry q), from pixels.
+template <int B>
+__device__ int64_t pair_f_image(const uint8_t *img, int32_t pitch, int ry, int rx, int dy,
+                                int dx, int q, int32_t sr, int64_t srr, int &k)
+{
+    constexpr int n = B * B;
+    int64_t cx = 0, sd = 0, sdd = 0;
+    for (int i = 0; i < B; ++i)
+        for (int j = 0; j < B; ++j) {
+            int si, sj;
+            iso_src(q, B, i, j, si, sj);
+            const uint8_t *pp = img + (int64_t)(dy + 2 * si) * pitch + dx + 2 * sj;
+            const int dv = pp[0] + pp[1] + pp[pitch] + pp[pitch + 1];
+            cx += (int64_t)img[(int64_t)(ry + i) * pitch + rx + j] * dv;
+            sd += dv;
+            sdd += dv * dv;
+        }
+    const int64_t srd = n * cx - (int64_t)sr * sd;
+    return fit_f(srr, srd, n * sdd - sd * sd, k);
+}
+
+// Initial best key per range: an exact evaluation of one candidate domain
+// (8 isometries) in its pool, so the screen starts from a real threshold.
+// Flat ranges get their final key directly.
+template <int B>
+__global__ void k_seed(const uint8_t *__restrict__ img, Geom g, const RangeStat *__restrict__ rs,
+                       int64_t Rp, const uint32_t *__restrict__ perm,
+                       const uint32_t *__restrict__ bmin, int shift, u64 *__restrict__ keys,
+                       u64 *counters)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= Rp) return;
+    const RangeStat st = rs[s];
+    u64 key = kNoKey;
+    if (st.flags & (kPad | kEmpty)) {
+        key = kNoKey;
+    } else if (st.flags & kFlat) {
+        key = pack_key(0, pool_min_index(perm, bmin, st.lo, st.hi), 0, shift);
+    } else {
+        const int ry = (int)(st.ridx / g.rcols) * B, rx = (int)(st.ridx % g.rcols) * B;
+        uint32_t d;
+        if (perm) {
+            d = perm[(st.lo + st.hi) >> 1];
+        } else {
+            int a = min(max(ry - B / 2, 0) / g.t, g.drows - 1);
+            int c = min(max(rx - B / 2, 0) / g.t, g.dcols - 1);
+            d = (uint32_t)(a * g.dcols + c);
+        }
+        const int dy = (int)(d / g.dcols) * g.t, dx = (int)(d % g.dcols) * g.t;
+        for (int q = 0; q < 8; ++q) {
+            int k;
+            int64_t f = pair_f_image<B>(img, g.pitch, ry, rx, dy, dx, q, st.sr, st.srr, k);
+            u64 kk = pack_key(f, d, q, shift);
+            key = kk < key ? kk : key;
+        }
+        if (counters) atomicAdd(&counters[3], 8ull);
+    }
+    keys[s] = key;
+}
+
+// ------------------------------------------------------------ work list
+// Per group: the union [L, H) of its active ranges' intervals (rounded to
+// 16-column blocks) and their intersection [ilo, ihi) (blocks inside it need
+// no per-range mask). Counts the groups that touch each column chunk.
+__global__ void k_group_bounds(const RangeStat *__restrict__ rs, int64_t G, int GR,
+                               uint4 *__restrict__ grp, uint32_t *__restrict__ chunkcnt)
+{
+    const int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gi >= G) return;
+    uint32_t L = 0xffffffffu, H = 0, ilo = 0, ihi = 0xffffffffu;
+    bool any = false;
+    for (int r = 0; r < GR; ++r) {
+        const RangeStat st = rs[gi * GR + r];
+        if (st.flags & (kPad | kFlat | kEmpty)) continue;
+        any = true;
+        L = min(L, st.lo);
+        H = max(H, st.hi);
+        ilo = max(ilo, st.lo);
+        ihi = min(ihi, st.hi);
+    }
+    if (!any) {
+        grp[gi] = make_uint4(0, 0, 0, 0);
+        return;
+    }
+    L &= ~15u;
+    H = (H + 15u) & ~15u;
+    grp[gi] = make_uint4(L, H, ilo, ihi);
+    for (uint32_t c = L / kChunk; c * kChunk < H; ++c) atomicAdd(&chunkcnt[c], 1u);
+}
+
+// Items in column-chunk-major order: the items in flight at any moment share
+// a few column chunks, which then stay resident in each XCD's L2.
+__global__ void k_emit_items(const uint4 *__restrict__ grp, int64_t G,
+                             const uint32_t *__restrict__ chunkoff, uint32_t *__restrict__ chunkfill,
+                             WorkItem *__restrict__ items)
+{
+    const int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gi >= G) return;
+    const uint4 gb = grp[gi];
+    for (uint32_t c = gb.x / kChunk; c * kChunk < gb.y; ++c) {
+        const uint32_t pos = chunkoff[c] + atomicAdd(&chunkfill[c], 1u);
+        WorkItem w;
+        w.grp = (uint32_t)gi;
+        w.c0 = max(c * kChunk, gb.x);
+        w.c1 = min((c + 1) * kChunk, gb.y);
+        w.pad = 0;
+        items[pos] = w;
+    }
+}
+
+// ------------------------------------------------------------ MFMA search
+struct SearchArgs {
+    const _Float16 *A;
+    const _Float16 *Bm;
+    const float *u;
+    const int32_t *eps;
+    const int64_t *sdd;
+    const uint32_t *dom;
+    const RangeStat *rs;
+    const uint4 *grp;
+    const WorkItem *items;
+    const uint32_t *n_items;
+    uint32_t *item_ctr;
+    u64 *keys;
+    u64 *counters;
+    int shift;
+};
+
+template <int B> struct WaveState {
+    typedef typename Frag<Cfg<B>::EPL>::type frag_t;
+    frag_t af[Cfg<B>::MW][Cfg<B>::KS];
+    float T[Cfg<B>::MW];
+    uint32_t lo[Cfg<B>::MW], hi[Cfg<B>::MW];
+    u64 best[Cfg<B>::MW];
+    uint32_t grp;
+    u64 survivors;
+};
+
+// Exact treatment of the elements of one column block that passed the screen.
+template <int B, bool MASK>
+__device__ __forceinline__ void take_survivors(const SearchArgs &a, WaveState<B> &st,
+                                               const float4_t (&acc)[Cfg<B>::MW][Cfg<B>::NCH],
+                                               int cb, float u, float slack)
+{
+    using C = Cfg<B>;
+    constexpr int n = C::n, MW = C::MW, NCH = C::NCH, GR = 2 * MW;
+    const int lane = threadIdx.x & 63, hl = lane >> 5, col = lane & 15;
+    const int isob = ((lane >> 4) & 1) * 4;
+    const uint32_t p = (uint32_t)cb * 16 + col;
+#pragma unroll
+    for (int b = 0; b < MW; ++b) {
+        float4_t s = acc[b][0];
+#pragma unroll
+        for (int c = 1; c < NCH; ++c) s += acc[b][c];
+        const float m = fmaxf(fmaxf(fabsf(s[0]), fabsf(s[1])), fmaxf(fabsf(s[2]), fabsf(s[3])));
+        bool h = m >= fmaf(st.T[b], u, -slack);
+        if (MASK) h = h && p >= st.lo[b] && p < st.hi[b];
+        if (!__any(h)) continue;
+        const int64_t slot = (int64_t)st.grp * GR + 2 * b + hl;
+        const int64_t srr = a.rs[slot].srr;
+        u64 cand = kNoKey;
+        if (h) {
+            const int32_t delta = a.rs[slot].delta;
+            const int64_t sdd = a.sdd[p];
+            const int32_t ep = a.eps[p];
+            const uint32_t d = a.dom[p];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                int64_t cx = 0;
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) cx += (int64_t)acc[b][c][v];
+                const int64_t srd = (int64_t)n * cx - (int64_t)delta * ep;
+                int k;
+                const int64_t f = fit_f(srr, srd, sdd, k);
+                const u64 key = pack_key(f, d, isob + v, a.shift);
+                cand = key < cand ? key : cand;
+            }
+            st.survivors += 4;
+        }
+#pragma unroll
+        for (int off = 1; off < 32; off <<= 1) {
+            const u64 o = __shfl_xor(cand, off);
+            cand = o < cand ? o : cand;
+        }
+        if (cand < st.best[b]) {
+            st.best[b] = cand;
+            st.T[b] = screen_t(srr, (int64_t)(cand >> a.shift));
+        }
+    }
+}
+
+template <int B, bool MASK>
+__device__ __forceinline__ void scan_blocks(const SearchArgs &a, WaveState<B> &st, int cb_begin,
+                                            int cb_end)
+{
+    using C = Cfg<B>;
+    constexpr int n = C::n, KS = C::KS, MW = C::MW, NCH = C::NCH, KPC = KS / NCH;
+    typedef typename WaveState<B>::frag_t frag_t;
+    const float slack = n / 4.0f + (NCH > 1 ? 64.0f : 0.0f);
+    const int lane = threadIdx.x & 63, col = lane & 15;
+    const frag_t *bbase = (const frag_t *)a.Bm + lane;
+    for (int cb = cb_begin; cb < cb_end; ++cb) {
+        frag_t bf[KS];
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) bf[ks] = bbase[((int64_t)cb * KS + ks) * 64];
+        const float u = a.u[cb * 16 + col];
+        float4_t acc[MW][NCH];
+#pragma unroll
+        for (int b = 0; b < MW; ++b)
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                float4_t z = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int kk = 0; kk < KPC; ++kk) z = mma(st.af[b][c * KPC + kk], bf[c * KPC + kk], z);
+                acc[b][c] = z;
+            }
+        bool hit = false;
+#pragma unroll
+        for (int b = 0; b < MW; ++b) {
+            float4_t s = acc[b][0];
+#pragma unroll
+            for (int c = 1; c < NCH; ++c) s += acc[b][c];
+            const float m = fmaxf(fmaxf(fabsf(s[0]), fabsf(s[1])), fmaxf(fabsf(s[2]), fabsf(s[3])));
+            bool h = m >= fmaf(st.T[b], u, -slack);
+            if (MASK) {
+                const uint32_t p = (uint32_t)cb * 16 + col;
+                h = h && p >= st.lo[b] && p < st.hi[b];
+            }
+            hit = hit || h;
+        }
+        if (__any(hit)) take_survivors<B, MASK>(a, st, acc, cb, u, slack);
+    }
+}
+
+template <int B>
+__global__ __launch_bounds__(256, 2) void k_search_mfma(SearchArgs a)
+{
+    using C = Cfg<B>;
+    constexpr int MW = C::MW, KS = C::KS, GR = 2 * MW;
+    typedef typename WaveState<B>::frag_t frag_t;
+    const int lane = threadIdx.x & 63, hl = lane >> 5;
+    const uint32_t nitems = *a.n_items;
+    WaveState<B> st;
+    st.survivors = 0;
+    u64 items_done = 0;
+    for (;;) {
+        uint32_t item = 0;
+        if (lane == 0) item = atomicAdd(a.item_ctr, 1u);
+        item = __builtin_amdgcn_readfirstlane(item);
+        if (item >= nitems) break;
+        const WorkItem wi = a.items[item];
+        st.grp = wi.grp;
+        const frag_t *ap = (const frag_t *)a.A + (int64_t)st.grp * MW * KS * 64 + lane;
+#pragma unroll
+        for (int b = 0; b < MW; ++b)
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) st.af[b][ks] = ap[(b * KS + ks) * 64];
+#pragma unroll
+        for (int b = 0; b < MW; ++b) {
+            const int64_t slot = (int64_t)st.grp * GR + 2 * b + hl;
+            const RangeStat rsx = a.rs[slot];
+            st.best[b] = a.keys[slot];
+            st.lo[b] = rsx.lo;
+            st.hi[b] = rsx.hi;
+            const bool act = !(rsx.flags & (kPad | kFlat | kEmpty));
+            st.T[b] = !act ? __builtin_inff()
+                           : (st.best[b] == kNoKey ? 0.0f
+                                                   : screen_t(rsx.srr, (int64_t)(st.best[b] >> a.shift)));
+        }
+        const uint4 gb = a.grp[st.grp];
+        const int cb0 = (int)(wi.c0 >> 4), cb1 = (int)(wi.c1 >> 4);
+        // column blocks fully inside every active range's pool need no mask
+        int ib0 = (int)((gb.z + 15u) >> 4), ib1 = (int)(gb.w >> 4);
+        ib0 = min(max(ib0, cb0), cb1);
+        ib1 = max(min(ib1, cb1), ib0);
+        scan_blocks<B, true>(a, st, cb0, ib0);
+        scan_blocks<B, false>(a, st, ib0, ib1);
+        scan_blocks<B, true>(a, st, ib1, cb1);
+        if ((lane & 31) == 0) {
+#pragma unroll
+            for (int b = 0; b < MW; ++b)
+                if (st.best[b] != kNoKey)
+                    atomicMin(&a.keys[(int64_t)st.grp * GR + 2 * b + hl], st.best[b]);
+        }
+        items_done += 1;
+    }
+    if (a.counters) {
+        u64 sv = st.survivors;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) sv += __shfl_xor(sv, off);
+        if (lane == 0) {
+            atomicAdd(&a.counters[1], sv);
+            atomicAdd(&a.counters[2], items_done);
+        }
+    }
+}
+
+// ------------------------------------------------------------ plain search
+__global__ void k_box2x2(const uint8_t *__restrict__ img, int32_t h, int32_t w, int32_t pitch,
+                         uint16_t *__restrict__ S)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t sw = w - 1;
+    if (i >= (int64_t)(h - 1) * sw) return;
+    const int64_t y = i / sw, x = i - y * sw;
+    const uint8_t *p = img + y * pitch + x;
+    S[i] = (uint16_t)(p[0] + p[1] + p[pitch] + p[pitch + 1]);
+}
+
+// One thread per (range, domain position, isometry): 32 positions x 8
+// isometries per block, the range (under each inverse isometry) in LDS.
+template <int B>
+__global__ __launch_bounds__(256) void k_search_plain(
+    const uint8_t *__restrict__ img, Geom g, const uint16_t *__restrict__ S,
+    const uint32_t *__restrict__ perm, const uint32_t *__restrict__ lo,
+    const uint32_t *__restrict__ hi, int64_t r0, int shift, u64 *__restrict__ keys)
+{
+    constexpr int n = B * B;
+    __shared__ int32_t ar[8][n];
+    __shared__ int32_t s_sr;
+    __shared__ int64_t s_srr;
+    const int64_t r = r0 + blockIdx.y;
+    const int tid = threadIdx.x;
+    const int ry = (int)(r / g.rcols) * B, rx = (int)(r % g.rcols) * B;
+    for (int e = tid; e < 8 * n; e += 256) {
+        const int q = e / n, K = e % n;
+        int si, sj;
+        iso_src(iso_inverse(q), B, K / B, K % B, si, sj);
+        ar[q][K] = img[(int64_t)(ry + si) * g.pitch + rx + sj];
+    }
+    if (tid == 0) {
+        int32_t sr = 0;
+        int64_t sq = 0;
+        for (int i = 0; i < B; ++i)
+            for (int j = 0; j < B; ++j) {
+                int v = img[(int64_t)(ry + i) * g.pitch + rx + j];
+                sr += v;
+                sq += v * v;
+            }
+        s_sr = sr;
+        s_srr = (int64_t)n * sq - (int64_t)sr * sr;
+    }
+    __syncthreads();
+    const uint32_t plo = lo ? lo[r] : 0u, phi = hi ? hi[r] : (uint32_t)g.D;
+    const uint32_t pos = blockIdx.x * 32u + (uint32_t)(tid >> 3);
+    const int q = tid & 7;
+    u64 key = kNoKey;
+    if (pos >= plo && pos < phi) {
+        const uint32_t d = perm ? perm[pos] : pos;
+        const int dy = (int)(d / g.dcols) * g.t, dx = (int)(d % g.dcols) * g.t;
+        const int64_t sw = g.w - 1;
+        const uint16_t *sp = S + (int64_t)dy * sw + dx;
+        int64_t cx = 0, sd = 0, sq = 0;
+        for (int i = 0; i < B; ++i)
+            for (int j = 0; j < B; ++j) {
+                const int dv = sp[(int64_t)(2 * i) * sw + 2 * j];
+                cx += ar[q][i * B + j] * dv;
+                sd += dv;
+                sq += dv * dv;
+            }
+        const int64_t srd = n * cx - (int64_t)s_sr * sd;
+        int k;
+        const int64_t f = fit_f(s_srr, srd, n * sq - sd * sd, k);
+        key = pack_key(f, d, q, shift);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const u64 o = __shfl_xor(key, off);
+        key = o < key ? o : key;
+    }
+    if ((tid & 63) == 0 && key != kNoKey) atomicMin(&keys[r], key);
+}
+
+// ------------------------------------------------------------ finalize
+template <int B>
+__global__ void k_finalize(const uint8_t *__restrict__ img, Geom g,
+                           const uint32_t *__restrict__ order, const u64 *__restrict__ keys,
+                           int shift, fic_code *__restrict__ codes)
+{
+    constexpr int n = B * B;
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= g.R) return;
+    const uint32_t ridx = order ? order[s] : (uint32_t)s;
+    const int ry = (int)(ridx / g.rcols) * B, rx = (int)(ridx % g.rcols) * B;
+    int32_t sr = 0;
+    int64_t sq = 0;
+    for (int i = 0; i < B; ++i)
+        for (int j = 0; j < B; ++j) {
+            int v = img[(int64_t)(ry + i) * g.pitch + rx + j];
+            sr += v;
+            sq += v * v;
+        }
+    const int64_t srr = (int64_t)n * sq - (int64_t)sr * sr;
+    const int32_t j = (sr + n - 1) / (2 * n);
+    const int64_t e = sr - 2 * (int64_t)n * j;
+    const int64_t jcost = 4096 * e * e;
+    const u64 key = keys[s];
+    fic_code c;
+    c.o_idx = (uint8_t)j;
+    if (key == kNoKey) {
+        c.domain = 0;
+        c.iso = 0;
+        c.s_idx = 0;
+        c.flags = 1;
+        c.err = 4096 * srr + jcost;
+    } else {
+        const uint32_t d = (uint32_t)((key >> 3) & ((1ull << (shift - 3)) - 1ull));
+        const int q = (int)(key & 7ull);
+        const int dy = (int)(d / g.dcols) * g.t, dx = (int)(d % g.dcols) * g.t;
+        int k;
+        const int64_t f = pair_f_image<B>(img, g.pitch, ry, rx, dy, dx, q, sr, srr, k);
+        c.domain = d;
+        c.iso = (uint8_t)q;
+        c.s_idx = (int8_t)k;
+        c.flags = (f == (int64_t)(key >> shift)) ? 0 : 0x80;   // 0x80: key / recompute mismatch
+        c.err = f + jcost;
+    }
+    codes[ridx] = c;
+}
+
+inline unsigned blocks_for(int64_t n, int th) { return (unsigned)((n + th - 1) / th); }
+
+template <int B>
+hipError_t run_encode_b(const EncodePlan &p, const uint8_t *img, const uint32_t *perm,
+                        const uint32_t *lo, const uint32_t *hi, int kernel, fic_code *codes,
+                        void *ws, int num_cu, u64 *counters, hipStream_t s)
+{
+    using C = Cfg<B>;
+    const Geom &g = p.g;
+    char *w = (char *)ws;
+    u64 *keys = (u64 *)(w + p.off_keys);
+    const int th = 256;
+    if (kernel == FIC_KERNEL_PLAIN) {
+        uint16_t *S = (uint16_t *)(w + p.off_S);
+        hipLaunchKernelGGL(k_box2x2, dim3(blocks_for((int64_t)(g.h - 1) * (g.w - 1), th)), dim3(th),
+                           0, s, img, g.h, g.w, g.pitch, S);
+        hipLaunchKernelGGL(k_fill_u64, dim3(blocks_for(g.R, th)), dim3(th), 0, s, keys, g.R, kNoKey);
+        const unsigned gx = blocks_for(p.Dp, 32);
+        for (int64_t r0 = 0; r0 < g.R; r0 += 65535) {
+            const unsigned gy = (unsigned)(g.R - r0 < 65535 ? g.R - r0 : 65535);
+            hipLaunchKernelGGL(k_search_plain<B>, dim3(gx, gy), dim3(256), 0, s, img, g, S, perm, lo,
+                               hi, r0, p.shift, keys);
+        }
+        hipLaunchKernelGGL(k_finalize<B>, dim3(blocks_for(g.R, th)), dim3(th), 0, s, img, g,
+                           (const uint32_t *)nullptr, keys, p.shift, codes);
+        return hipGetLastError();
+    }
+
+    _Float16 *A = (_Float16 *)(w + p.off_A);
+    RangeStat *rs = (RangeStat *)(w + p.off_rs);
+    uint32_t *order = (uint32_t *)(w + p.off_order);
+    _Float16 *Bm = (_Float16 *)(w + p.off_B);
+    float *u = (float *)(w + p.off_u);
+    int32_t *eps = (int32_t *)(w + p.off_eps);
+    int64_t *sdd = (int64_t *)(w + p.off_sdd);
+    uint32_t *dom = (uint32_t *)(w + p.off_dom);
+    WorkItem *items = (WorkItem *)(w + p.off_items);
+    uint32_t *ctr = (uint32_t *)(w + p.off_ctr);
+    uint32_t *chunkcnt = (uint32_t *)(w + p.off_chunkcnt);
+    uint32_t *chunkfill = (uint32_t *)(w + p.off_chunkfill);
+    uint4 *grp = (uint4 *)(w + p.off_grp);
+    uint32_t *bmin = (uint32_t *)(w + p.off_bmin);
+
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, ctr, (int64_t)64, 0u);
+    hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(p.NC, th)), dim3(th), 0, s, chunkcnt, p.NC, 0u);
+    hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(p.NC, th)), dim3(th), 0, s, chunkfill, p.NC, 0u);
+
+    const uint32_t *ord = nullptr;
+    if (p.pooled) {
+        u64 *sk = (u64 *)(w + p.off_sortkeys);
+        hipLaunchKernelGGL(k_range_sortkeys, dim3(blocks_for(g.R, th)), dim3(th), 0, s, lo, g.R, sk,
+                           order);
+        hipError_t e = radix_sort_pairs(sk, order, g.R, 32, w + p.off_sort, s);
+        if (e != hipSuccess) return e;
+        ord = order;
+        hipLaunchKernelGGL(k_blockmin, dim3(blocks_for((g.D + kBminBlock - 1) / kBminBlock * 64, th)),
+                           dim3(th), 0, s, perm, g.D, bmin);
+    }
+    hipLaunchKernelGGL(k_range_prep<B>, dim3(blocks_for(p.Rp * 8, th)), dim3(th), 0, s, img, g.pitch,
+                       g.rcols, g.R, p.Rp, ord, lo, hi, (uint32_t)g.D, A, rs);
+    hipLaunchKernelGGL(k_domain_prep<B>, dim3(blocks_for(p.Dp * B, th)), dim3(th), 0, s, img,
+                       g.pitch, g.dcols, g.t, perm, g.D, p.Dp, Bm, u, eps, sdd, dom);
+    hipLaunchKernelGGL(k_seed<B>, dim3(blocks_for(p.Rp, th)), dim3(th), 0, s, img, g, rs, p.Rp,
+                       perm, bmin, p.shift, keys, counters);
+    hipLaunchKernelGGL(k_group_bounds, dim3(blocks_for(p.G, th)), dim3(th), 0, s, rs, p.G,
+                       (int)p.GR, grp, chunkcnt);
+    // exclusive scan of the per-chunk counts; the total is the item count
+    scan_u32(chunkcnt, p.NC, ctr + 1, s);
+    hipLaunchKernelGGL(k_emit_items, dim3(blocks_for(p.G, th)), dim3(th), 0, s, grp, p.G, chunkcnt,
+                       chunkfill, items);
+    SearchArgs a;
+    a.A = A; a.Bm = Bm; a.u = u; a.eps = eps; a.sdd = sdd; a.dom = dom; a.rs = rs; a.grp = grp;
+    a.items = items; a.n_items = ctr + 1; a.item_ctr = ctr; a.keys = keys; a.counters = counters;
+    a.shift = p.shift;
+    // persistent grid: as many workgroups as stay resident on every CU
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void *>(&k_search_mfma<B>), 256, 0) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    hipLaunchKernelGGL(k_search_mfma<B>, dim3(per_cu * num_cu), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_finalize<B>, dim3(blocks_for(g.R, th)), dim3(th), 0, s, img, g, ord, keys,
+                       p.shift, codes);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+void plan_encode(const Geom &g, int pooled, EncodePlan &p)
+{
+    p.g = g;
+    p.pooled = pooled;
+    const int mw = g.b == 16 ? Cfg<16>::MW : Cfg<8>::MW;
+    p.GR = 2 * mw;
+    p.Rp = (g.R + p.GR - 1) / p.GR * p.GR;
+    p.G = p.Rp / p.GR;
+    p.Dp = (g.D + 15) / 16 * 16;
+    p.chunk = kChunk;
+    p.NC = (p.Dp + kChunk - 1) / kChunk;
+    p.max_items = p.G * p.NC;
+    int dbits = 1;
+    while (((int64_t)1 << dbits) < g.D) ++dbits;
+    p.shift = dbits + 3;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o += align256(bytes); return r; };
+    p.off_A = take((size_t)p.Rp * 8 * g.n * 2);
+    p.off_rs = take((size_t)p.Rp * sizeof(RangeStat));
+    p.off_order = take((size_t)p.Rp * 4);
+    p.off_B = take((size_t)p.Dp * g.n * 2);
+    p.off_u = take((size_t)p.Dp * 4);
+    p.off_eps = take((size_t)p.Dp * 4);
+    p.off_sdd = take((size_t)p.Dp * 8);
+    p.off_dom = take((size_t)p.Dp * 4);
+    p.off_keys = take((size_t)p.Rp * 8);
+    p.off_items = take((size_t)p.max_items * sizeof(WorkItem));
+    p.off_ctr = take(256);
+    p.off_chunkcnt = take((size_t)p.NC * 4);
+    p.off_chunkfill = take((size_t)p.NC * 4);
+    p.off_grp = take((size_t)p.G * 16);
+    p.off_bmin = take((size_t)((g.D + kBminBlock - 1) / kBminBlock) * 4);
+    p.off_S = take((size_t)(g.h - 1) * (g.w - 1) * 2);
+    p.off_sortkeys = take((size_t)p.Rp * 8);
+    p.off_sort = take(sort_ws_bytes(p.Rp));
+    p.total = o;
+}
+
+hipError_t run_encode(const EncodePlan &p, const uint8_t *img, const uint32_t *perm,
+                      const uint32_t *lo, const uint32_t *hi, int kernel, fic_code *codes,
+                      void *ws, int num_cu, u64 *counters, hipStream_t s)
+{
+    switch (p.g.b) {
+    case 4: return run_encode_b<4>(p, img, perm, lo, hi, kernel, codes, ws, num_cu, counters, s);
+    case 8: return run_encode_b<8>(p, img, perm, lo, hi, kernel, codes, ws, num_cu, counters, s);
+    case 16: return run_encode_b<16>(p, img, perm, lo, hi, kernel, codes, ws, num_cu, counters, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace fic

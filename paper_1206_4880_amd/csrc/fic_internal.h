@@ -1,0 +1,178 @@
+// fic_internal.h -- shared declarations of the gfx950 PIFS search library.
+//
+// Everything here is device-side plumbing for the kernels in this directory:
+// block geometry, the square isometries, the exact quantized fit of one
+// (range, domain, isometry) pair, operand layouts of the matrix-core search
+// and the launch wrappers the C ABI calls.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "fic.h"
+
+namespace fic {
+
+typedef unsigned long long u64;
+typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kWave = 64;
+constexpr u64 kNoKey = ~0ull;
+
+// ---------------------------------------------------------------------------
+// Operand layout of the matrix-core search, per range size B (n = B*B).
+// The cross term of a (range, isometry) row with a domain column is a dot
+// product over K = n pixels; it runs as 16x16 output blocks.
+//   KPI  K consumed by one MFMA (32 for 16x16x32 f16, 16 for 16x16x16 f16)
+//   EPL  halves each lane contributes per MFMA
+//   KS   MFMAs per 16x16 block (n / KPI)
+//   MW   16-row blocks per wave (each block = 2 ranges x 8 isometries)
+//   NCH  independent FP32 accumulators: a sum of 64 products of a centred
+//        pixel (|.| <= 255) and a centred 2x2 sum (|.| <= 1020) stays below
+//        2^24, so each 64-element chunk is exact; n = 256 keeps 4 of them.
+// Element (ks, g, e) of a lane group g = lane/16 is pixel K = ks*KPI + g*EPL + e
+// of the block in row-major order, for the A (rows) and B (columns) operand
+// alike, so their products pair up pixel by pixel.
+template <int B> struct Cfg;
+template <> struct Cfg<4>  { static constexpr int n = 16,  KPI = 16, EPL = 4, KS = 1, MW = 8, NCH = 1; };
+template <> struct Cfg<8>  { static constexpr int n = 64,  KPI = 32, EPL = 8, KS = 2, MW = 8, NCH = 1; };
+template <> struct Cfg<16> { static constexpr int n = 256, KPI = 32, EPL = 8, KS = 8, MW = 4, NCH = 4; };
+
+// Per-range state, in search order ("slot"). 32 bytes.
+struct RangeStat {
+    int64_t srr;     // n*sum r^2 - (sum r)^2
+    int32_t sr;      // sum r
+    int32_t delta;   // sum r - n*rhat, rhat = the centring level of the A rows
+    uint32_t ridx;   // raster range index
+    uint32_t lo, hi; // pool = columns [lo, hi) of the domain order
+    uint32_t flags;  // kFlat | kPad | kEmpty
+};
+constexpr uint32_t kFlat = 1u, kPad = 2u, kEmpty = 4u;
+
+struct WorkItem { uint32_t grp, c0, c1, pad; };
+
+// ---------------------------------------------------------------------------
+// The isometries: T_q(d)[i][j] = d[src], src per q (0 identity, 1 rot90 cw,
+// 2 rot180, 3 rot270 cw, 4 mirror left-right, 5 mirror up-down, 6 transpose,
+// 7 anti-transpose).
+__host__ __device__ inline void iso_src(int q, int b, int i, int j, int &si, int &sj)
+{
+    switch (q) {
+    case 0: si = i;         sj = j;         break;
+    case 1: si = b - 1 - j; sj = i;         break;
+    case 2: si = b - 1 - i; sj = b - 1 - j; break;
+    case 3: si = j;         sj = b - 1 - i; break;
+    case 4: si = i;         sj = b - 1 - j; break;
+    case 5: si = b - 1 - i; sj = j;         break;
+    case 6: si = j;         sj = i;         break;
+    default: si = b - 1 - j; sj = b - 1 - i; break;
+    }
+}
+// q' with T_q' = T_q^-1 (only the quarter turns are not involutions).
+__host__ __device__ inline int iso_inverse(int q) { return q == 1 ? 3 : (q == 3 ? 1 : q); }
+
+// ---------------------------------------------------------------------------
+// Exact fit of one pair. With s = k/16, o = 2j:
+//   4096*n*SSE = F(k) + 4096*(sum r - 2nj)^2,
+//   F(k) = 4096*Srr' - 128*k*Srd' + k^2*Sdd'  (a parabola in k).
+// The integer minimiser on [-16, 15] is the clamped nearest integer to the
+// vertex 64*Srd'/Sdd' (ties to the smaller |k|). The vertex is located in
+// fp64 (error far below 1/2), then the two neighbouring integers are compared
+// exactly in int64, so the choice is exact.
+__host__ __device__ inline int64_t fit_f(int64_t srr, int64_t srd, int64_t sdd, int &k_out)
+{
+    int k;
+    if (sdd <= 0) {
+        k = 0;
+    } else {
+        double v = 64.0 * (double)srd / (double)sdd;
+        if (v >= 15.0) {
+            k = 15;
+        } else if (v <= -16.0) {
+            k = -16;
+        } else {
+            int k0 = (int)floor(v);          // in [-16, 14]
+            int k1 = k0 + 1;
+            int64_t f0 = 4096 * srr - 128 * (int64_t)k0 * srd + (int64_t)k0 * k0 * sdd;
+            int64_t f1 = 4096 * srr - 128 * (int64_t)k1 * srd + (int64_t)k1 * k1 * sdd;
+            int a0 = k0 < 0 ? -k0 : k0, a1 = k1 < 0 ? -k1 : k1;
+            k = (f1 < f0 || (f1 == f0 && a1 < a0)) ? k1 : k0;
+        }
+    }
+    k_out = k;
+    return 4096 * srr - 128 * (int64_t)k * srd + (int64_t)k * k * sdd;
+}
+
+// Packed search key: (F << shift) | (domain << 3) | isometry. Its unsigned
+// minimum is the lexicographic minimum of (F, domain, isometry).
+__host__ __device__ inline u64 pack_key(int64_t f, uint32_t dom, int q, int shift)
+{
+    return ((u64)f << shift) | ((u64)dom << 3) | (u64)q;
+}
+
+// Screen threshold of a range whose best key so far has error F: a pair can
+// only reach F if |Srd'| / sqrt(Sdd') >= sqrt(Srr' - F/4096). Rounded down.
+__device__ inline float screen_t(int64_t srr, int64_t f)
+{
+    double theta = (double)srr - (double)f * (1.0 / 4096.0);
+    if (theta <= 0.0) return 0.0f;
+    return (float)(sqrt(theta) * (1.0 - 0x1p-20));
+}
+
+// Domain side constant u = sqrt(Sdd') / n, rounded down; flat domains get a
+// huge finite value (they can only tie when the range threshold is 0).
+__device__ inline float screen_u(int64_t sdd, int n)
+{
+    if (sdd <= 0) return 1e30f;
+    return (float)(sqrt((double)sdd) / (double)n * (1.0 - 0x1p-20));
+}
+
+// ---------------------------------------------------------------------------
+// Launch wrappers (each .hip file owns its kernels).
+struct Geom {
+    int32_t h, w, pitch, b, t;
+    int32_t n, rcols, rrows, dcols, drows;
+    int64_t R, D;
+};
+
+// DBC fractal dimension (fd_dbc.hip)
+hipError_t launch_fd_classify(const uint8_t *img, int32_t h, int32_t w, int32_t pitch,
+                              int32_t block, int32_t step, double *fd64, float *fd32,
+                              hipStream_t s);
+
+// radix sort + pool (pool.hip)
+size_t sort_ws_bytes(int64_t n);
+hipError_t radix_sort_pairs(u64 *keys, uint32_t *vals, int64_t n, int key_bits, void *ws,
+                            hipStream_t s);
+hipError_t scan_u32(uint32_t *a, int64_t m, uint32_t *total, hipStream_t s);
+hipError_t launch_pool(const double *fd_range, int32_t nr, const double *fd_dom, int32_t nd,
+                       double tol, uint32_t *perm, uint32_t *lo, uint32_t *hi, void *ws,
+                       hipStream_t s);
+
+// encode (encode.hip)
+struct EncodePlan {
+    Geom g;
+    int pooled;
+    int64_t Rp, Dp, G, GR, NC;   // padded ranges/columns, groups, ranges per group, chunks
+    int32_t chunk, shift;
+    int64_t max_items;
+    size_t off_A, off_rs, off_order, off_B, off_u, off_eps, off_sdd, off_dom, off_keys,
+        off_items, off_ctr, off_chunkcnt, off_chunkfill, off_grp, off_bmin, off_S, off_sort,
+        off_sortkeys, total;
+};
+void plan_encode(const Geom &g, int pooled, EncodePlan &p);
+hipError_t run_encode(const EncodePlan &p, const uint8_t *img, const uint32_t *perm,
+                      const uint32_t *lo, const uint32_t *hi, int kernel, fic_code *codes,
+                      void *ws, int num_cu, u64 *counters, hipStream_t s);
+
+// decode (decode.hip)
+size_t decode_ws_bytes(const Geom &g);
+int32_t decode_max_iters();
+hipError_t run_decode(const Geom &g, const fic_code *codes, int32_t max_iters,
+                      const uint8_t *init, uint8_t *out, void *ws, int32_t *iters,
+                      hipStream_t s);
+
+}  // namespace fic

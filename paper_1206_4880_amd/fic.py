@@ -1,0 +1,302 @@
+"""Python binding of the C ABI in include/fic.h (ctypes).
+
+Argument marshalling only: torch supplies device memory and the current
+stream; every step of the encoder runs in the HIP library libfic.so built in
+this directory. There is no fallback: if the library is missing, or there is
+no device, the calls raise.
+"""
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfic.so")
+
+OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_CAPACITY, ERR_DEVICE = range(6)
+KERNEL_MFMA, KERNEL_PLAIN = 0, 1
+CODE_DTYPE = np.dtype([("domain", "<u4"), ("iso", "u1"), ("s_idx", "i1"), ("o_idx", "u1"),
+                       ("flags", "u1"), ("err", "<i8")])
+assert CODE_DTYPE.itemsize == 16
+
+
+class FicError(RuntimeError):
+    def __init__(self, status, what):
+        self.status = status
+        super().__init__("%s: %s (status %d)" % (what, status_string(status), status))
+
+
+class Geom(ctypes.Structure):
+    _fields_ = [("height", ctypes.c_int32), ("width", ctypes.c_int32), ("pitch", ctypes.c_int32),
+                ("range_size", ctypes.c_int32), ("domain_step", ctypes.c_int32)]
+
+
+class ImageDesc(ctypes.Structure):
+    _fields_ = [("img", ctypes.c_void_p), ("geom", Geom), ("tol", ctypes.c_double),
+                ("codes", ctypes.c_void_p)]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_st = ctypes.c_int
+
+
+def lib():
+    """Load libfic.so (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libfic.so is not built; run __graft_entry__.build() "
+                           "or python paper_1206_4880_amd/build.py")
+    L = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "fic_create": (_st, [_i32, ctypes.POINTER(_vp)]),
+        "fic_destroy": (_st, [_vp]),
+        "fic_status_string": (ctypes.c_char_p, [_st]),
+        "fic_set_counters": (_st, [_vp, _vp]),
+        "fic_num_ranges": (ctypes.c_int64, [ctypes.POINTER(Geom)]),
+        "fic_num_domains": (ctypes.c_int64, [ctypes.POINTER(Geom)]),
+        "fic_fd_classify": (_st, [_vp, _vp, ctypes.POINTER(Geom), _i32, _i32, _vp, _vp, _vp]),
+        "fic_pool_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64, ctypes.c_int64]),
+        "fic_build_domain_pool": (_st, [_vp, _vp, _i32, _vp, _i32, ctypes.c_double, _vp, _vp, _vp,
+                                        _vp, ctypes.c_size_t, _vp]),
+        "fic_encode_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Geom), _i32]),
+        "fic_encode_pifs": (_st, [_vp, _vp, ctypes.POINTER(Geom), _vp, _vp, _vp, _i32, _vp, _vp,
+                                  ctypes.c_size_t, _vp]),
+        "fic_batch_workspace_bytes": (ctypes.c_size_t, [_i32, ctypes.POINTER(ImageDesc)]),
+        "fic_encode_pifs_batch": (_st, [_vp, _i32, ctypes.POINTER(ImageDesc), _vp,
+                                        ctypes.c_size_t, _vp]),
+        "fic_decode_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Geom)]),
+        "fic_decode_pifs": (_st, [_vp, _vp, ctypes.POINTER(Geom), _i32, _vp, _vp, _vp,
+                                  ctypes.c_size_t, _vp, _vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+EXPORTED = ("fic_create", "fic_destroy", "fic_status_string", "fic_set_counters",
+            "fic_num_ranges", "fic_num_domains", "fic_fd_classify", "fic_pool_workspace_bytes",
+            "fic_build_domain_pool", "fic_encode_workspace_bytes", "fic_encode_pifs",
+            "fic_batch_workspace_bytes", "fic_encode_pifs_batch", "fic_decode_workspace_bytes",
+            "fic_decode_pifs")
+
+
+def status_string(status):
+    try:
+        return lib().fic_status_string(status).decode()
+    except Exception:  # noqa: BLE001 - message only
+        return "status"
+
+
+def _check(status, what):
+    if status != OK:
+        raise FicError(status, what)
+
+
+def make_geom(height, width, range_size, domain_step, pitch=None):
+    return Geom(int(height), int(width), int(pitch if pitch is not None else width),
+                int(range_size), int(domain_step))
+
+
+class Context:
+    """A library context bound to one HIP device (device=-1: host-only,
+    validation only)."""
+
+    def __init__(self, device=0):
+        h = _vp()
+        _check(lib().fic_create(int(device), ctypes.byref(h)), "fic_create")
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            lib().fic_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
+
+    def set_counters(self, counters):
+        ptr = counters.data_ptr() if counters is not None else None
+        _check(lib().fic_set_counters(self.handle, ptr), "fic_set_counters")
+
+
+_contexts = {}
+
+
+def context(device=None):
+    import torch
+    dev = torch.cuda.current_device() if device is None else int(device)
+    if dev not in _contexts:
+        _contexts[dev] = Context(dev)
+    return _contexts[dev]
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _need_cuda_u8(img):
+    import torch
+    if not (isinstance(img, torch.Tensor) and img.is_cuda and img.dtype == torch.uint8
+            and img.dim() == 2 and img.stride(1) == 1):
+        raise ValueError("image must be a 2-D uint8 CUDA tensor with unit column stride")
+
+
+def _geom_of(img, range_size, domain_step):
+    return make_geom(img.shape[0], img.shape[1], range_size, domain_step, pitch=img.stride(0))
+
+
+def num_ranges(h, w, b):
+    return int(lib().fic_num_ranges(ctypes.byref(make_geom(h, w, b, 1))))
+
+
+def num_domains(h, w, b, t):
+    return int(lib().fic_num_domains(ctypes.byref(make_geom(h, w, b, t))))
+
+
+def fd_classify(img, block, step, want_fp32=True):
+    """(fd64, fd32) of every block x block window at `step` (raster order)."""
+    import torch
+    _need_cuda_u8(img)
+    h, w = img.shape
+    count = ((h - block) // step + 1) * ((w - block) // step + 1)
+    fd64 = torch.empty(count, dtype=torch.float64, device=img.device)
+    fd32 = torch.empty(count, dtype=torch.float32, device=img.device) if want_fp32 else None
+    g = make_geom(h, w, 4, 1, pitch=img.stride(0))
+    _check(lib().fic_fd_classify(context(img.device.index).handle, img.data_ptr(), ctypes.byref(g),
+                                 int(block), int(step), fd64.data_ptr(),
+                                 fd32.data_ptr() if fd32 is not None else None, _stream()),
+           "fic_fd_classify")
+    return fd64, fd32
+
+
+def build_domain_pool(fd_range, fd_domain, tol):
+    """(perm, lo, hi) device tensors: the pool of range r is perm[lo[r]:hi[r]]."""
+    import torch
+    nr, nd = fd_range.numel(), fd_domain.numel()
+    dev = fd_range.device
+    perm = torch.empty(nd, dtype=torch.int32, device=dev)
+    lo = torch.empty(nr, dtype=torch.int32, device=dev)
+    hi = torch.empty(nr, dtype=torch.int32, device=dev)
+    wsb = lib().fic_pool_workspace_bytes(nr, nd)
+    ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=dev)
+    _check(lib().fic_build_domain_pool(context(dev.index).handle, fd_range.data_ptr(), nr,
+                                       fd_domain.data_ptr(), nd, float(tol), perm.data_ptr(),
+                                       lo.data_ptr(), hi.data_ptr(), ws.data_ptr(), wsb, _stream()),
+           "fic_build_domain_pool")
+    return perm, lo, hi
+
+
+class Workspace:
+    """Reusable device scratch (grown on demand)."""
+
+    def __init__(self):
+        self.buf = None
+
+    def get(self, nbytes, device):
+        import torch
+        if self.buf is None or self.buf.numel() < nbytes or self.buf.device != device:
+            self.buf = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+        return self.buf
+
+
+_ws = Workspace()
+
+
+def encode_pifs(img, range_size, domain_step, pool=None, kernel="mfma", codes=None, ws=None):
+    """Codes (uint8 CUDA tensor [R, 16], fic_code layout) of one image.
+
+    pool=None is exhaustive search; otherwise the (perm, lo, hi) triple of
+    build_domain_pool."""
+    import torch
+    _need_cuda_u8(img)
+    g = _geom_of(img, range_size, domain_step)
+    nr = int(lib().fic_num_ranges(ctypes.byref(g)))
+    if nr <= 0:
+        raise FicError(ERR_INVALID_ARG, "geometry")
+    pooled = pool is not None
+    wsb = lib().fic_encode_workspace_bytes(ctypes.byref(g), int(pooled))
+    buf = (ws or _ws).get(wsb, img.device)
+    if codes is None:
+        codes = torch.empty((nr, 16), dtype=torch.uint8, device=img.device)
+    kern = KERNEL_MFMA if kernel == "mfma" else KERNEL_PLAIN if kernel == "plain" else int(kernel)
+    perm, lo, hi = pool if pooled else (None, None, None)
+    _check(lib().fic_encode_pifs(context(img.device.index).handle, img.data_ptr(), ctypes.byref(g),
+                                 perm.data_ptr() if pooled else None,
+                                 lo.data_ptr() if pooled else None,
+                                 hi.data_ptr() if pooled else None,
+                                 kern, codes.data_ptr(), buf.data_ptr(), wsb, _stream()),
+           "fic_encode_pifs")
+    return codes
+
+
+def encode(img, range_size, domain_step, tol=None, kernel="mfma"):
+    """Classify + pool (when tol is not None) + search. Returns the codes
+    tensor and the pool triple (or None)."""
+    pool = None
+    if tol is not None and not (isinstance(tol, float) and math.isinf(tol) and tol > 0):
+        fr, _ = fd_classify(img, range_size, range_size, want_fp32=False)
+        fd, _ = fd_classify(img, 2 * range_size, domain_step, want_fp32=False)
+        pool = build_domain_pool(fr, fd, tol)
+    return encode_pifs(img, range_size, domain_step, pool=pool, kernel=kernel), pool
+
+
+def encode_batch(images, jobs, codes=None):
+    """Batch encode: images (list of uint8 CUDA tensors), jobs [(B, t, tol)].
+    Returns the list of codes tensors."""
+    import torch
+    n = len(images)
+    descs = (ImageDesc * n)()
+    outs = []
+    for i, (img, (b, t, tol)) in enumerate(zip(images, jobs)):
+        _need_cuda_u8(img)
+        g = _geom_of(img, b, t)
+        nr = int(lib().fic_num_ranges(ctypes.byref(g)))
+        c = codes[i] if codes is not None else torch.empty((nr, 16), dtype=torch.uint8,
+                                                            device=img.device)
+        outs.append(c)
+        descs[i].img = img.data_ptr()
+        descs[i].geom = g
+        descs[i].tol = float("inf") if tol is None else float(tol)
+        descs[i].codes = c.data_ptr()
+    wsb = lib().fic_batch_workspace_bytes(n, descs)
+    buf = _ws.get(wsb, images[0].device)
+    _check(lib().fic_encode_pifs_batch(context(images[0].device.index).handle, n, descs,
+                                       buf.data_ptr(), wsb, _stream()), "fic_encode_pifs_batch")
+    return outs
+
+
+def decode_pifs(codes, height, width, range_size, domain_step, max_iters=32, init=None):
+    """(image tensor, iterations tensor) decoded from codes on the device."""
+    import torch
+    g = make_geom(height, width, range_size, domain_step)
+    dev = codes.device
+    out = torch.empty((height, width), dtype=torch.uint8, device=dev)
+    iters = torch.zeros(1, dtype=torch.int32, device=dev)
+    wsb = lib().fic_decode_workspace_bytes(ctypes.byref(g))
+    scratch = torch.empty(max(wsb, 1), dtype=torch.uint8, device=dev)
+    if init is not None:
+        _need_cuda_u8(init)
+    _check(lib().fic_decode_pifs(context(dev.index).handle, codes.data_ptr(), ctypes.byref(g),
+                                 int(max_iters), init.data_ptr() if init is not None else None,
+                                 out.data_ptr(), scratch.data_ptr(), wsb, iters.data_ptr(),
+                                 _stream()), "fic_decode_pifs")
+    return out, iters
+
+
+def unpack_codes(codes):
+    """numpy structured view of a codes tensor (copies to host)."""
+    a = codes.detach().cpu().numpy().reshape(-1)
+    return a.view(CODE_DTYPE)

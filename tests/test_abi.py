@@ -1,0 +1,164 @@
+"""The C ABI on a machine without a GPU: the library loads, exports every
+symbol include/fic.h declares, and validates arguments with the documented
+status codes (a host-only context answers FIC_ERR_DEVICE once the
+arguments are valid). No compute call is made here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1206_4880_amd import fic
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fic.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(fic.LIB_PATH):
+        from paper_1206_4880_amd import build
+        build.build()
+    return fic.lib()
+
+
+@pytest.fixture(scope="module")
+def hctx(L):
+    c = fic.Context(-1)
+    yield c
+    c.close()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fic_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_symbols_exported(L):
+    names = declared_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(fic.EXPORTED)
+
+
+def test_status_strings(L):
+    for s in range(6):
+        assert fic.status_string(s) not in ("", "unknown status")
+    assert fic.status_string(99) == "unknown status"
+
+
+def test_create_without_device(L):
+    h = ctypes.c_void_p()
+    assert L.fic_create(0, ctypes.byref(h)) == fic.ERR_DEVICE
+    assert L.fic_create(-2, ctypes.byref(h)) == fic.ERR_INVALID_ARG
+    assert L.fic_create(0, None) == fic.ERR_INVALID_ARG
+
+
+def test_geometry_helpers_match_table1(L, oracle_lib):
+    for n in (64, 128, 256, 512, 1024):
+        g = fic.make_geom(n, n, 8, 1)
+        assert L.fic_num_ranges(ctypes.byref(g)) == oracle_lib.num_ranges(n, n, 8)
+        assert L.fic_num_domains(ctypes.byref(g)) == oracle_lib.num_domains(n, n, 8, 1)
+    assert L.fic_num_domains(ctypes.byref(fic.make_geom(100, 64, 8, 1))) == 0  # 100 % 8
+
+
+def _encode(L, ctx, g, perm=None, lo=None, hi=None, kernel=0, codes=1, ws=1, wsb=None, img=1):
+    if wsb is None:
+        wsb = L.fic_encode_workspace_bytes(ctypes.byref(g), int(perm is not None))
+    return L.fic_encode_pifs(ctx.handle, img, ctypes.byref(g), perm, lo, hi, kernel, codes, ws,
+                             wsb, None)
+
+
+def test_encode_validation(L, hctx):
+    good = fic.make_geom(64, 64, 8, 1)
+    assert _encode(L, hctx, good) == fic.ERR_DEVICE           # valid, but no device
+    bad_geoms = [fic.make_geom(64, 64, 6, 1), fic.make_geom(60, 64, 8, 1),
+                 fic.make_geom(64, 8, 8, 1), fic.make_geom(64, 64, 8, 0),
+                 fic.make_geom(64, 64, 8, 1, pitch=32), fic.make_geom(0, 64, 8, 1)]
+    for g in bad_geoms:
+        assert _encode(L, hctx, g, wsb=1 << 30) == fic.ERR_INVALID_ARG
+    assert _encode(L, hctx, good, img=None) == fic.ERR_INVALID_ARG
+    assert _encode(L, hctx, good, codes=None) == fic.ERR_INVALID_ARG
+    assert _encode(L, hctx, good, ws=None) == fic.ERR_INVALID_ARG
+    assert _encode(L, hctx, good, kernel=7) == fic.ERR_INVALID_ARG
+    assert _encode(L, hctx, good, perm=1, lo=None, hi=1, wsb=1 << 30) == fic.ERR_INVALID_ARG
+    need = L.fic_encode_workspace_bytes(ctypes.byref(good), 0)
+    assert need > 0
+    assert _encode(L, hctx, good, wsb=need - 1) == fic.ERR_WORKSPACE
+    pooled = L.fic_encode_workspace_bytes(ctypes.byref(good), 1)
+    assert _encode(L, hctx, good, perm=1, lo=1, hi=1, wsb=pooled) == fic.ERR_DEVICE
+    assert L.fic_encode_pifs(None, 1, ctypes.byref(good), None, None, None, 0, 1, 1, need,
+                             None) == fic.ERR_INVALID_ARG
+
+
+def test_capacity_limit(L, hctx):
+    """F needs 42 bits at 16x16 ranges; 2^19 or more domains leave fewer than
+    the 64 - 42 - 3 bits an index needs."""
+    ok = fic.make_geom(2048, 2048, 16, 4)         # 255,025 domains: 18 bits
+    assert _encode(L, hctx, ok, wsb=1 << 40) == fic.ERR_DEVICE
+    big = fic.make_geom(8192, 8192, 16, 4)        # 4,182,025 domains: 22 bits
+    assert _encode(L, hctx, big, wsb=1 << 40) == fic.ERR_CAPACITY
+    b8 = fic.make_geom(4096, 4096, 8, 1)          # 38 + 24 + 3 > 64
+    assert _encode(L, hctx, b8, wsb=1 << 40) == fic.ERR_CAPACITY
+
+
+def test_classify_validation(L, hctx):
+    g = fic.make_geom(64, 64, 8, 1)
+    C = lambda blk, step, img=1, fd=1, gg=g: L.fic_fd_classify(hctx.handle, img, ctypes.byref(gg),
+                                                                 blk, step, fd, None, None)
+    assert C(16, 1) == fic.ERR_DEVICE
+    assert C(12, 1) == fic.ERR_INVALID_ARG
+    assert C(16, 0) == fic.ERR_INVALID_ARG
+    assert C(16, 1, img=None) == fic.ERR_INVALID_ARG
+    assert C(16, 1, fd=None) == fic.ERR_INVALID_ARG
+    assert C(32, 1, gg=fic.make_geom(16, 64, 8, 1)) == fic.ERR_INVALID_ARG
+
+
+def test_pool_validation(L, hctx):
+    wsb = L.fic_pool_workspace_bytes(100, 1000)
+    P = lambda tol=0.05, nr=100, nd=1000, ws=1, b=wsb, ptr=1: L.fic_build_domain_pool(
+        hctx.handle, ptr, nr, ptr, nd, tol, ptr, ptr, ptr, ws, b, None)
+    assert P() == fic.ERR_DEVICE
+    assert P(tol=float("nan")) == fic.ERR_INVALID_ARG
+    assert P(tol=float("inf")) == fic.ERR_DEVICE
+    assert P(tol=-1.0) == fic.ERR_DEVICE
+    assert P(nr=0) == fic.ERR_INVALID_ARG
+    assert P(b=wsb - 1) == fic.ERR_WORKSPACE
+    assert P(ptr=None) == fic.ERR_INVALID_ARG
+
+
+def test_decode_validation(L, hctx):
+    g = fic.make_geom(64, 64, 8, 1)
+    wsb = L.fic_decode_workspace_bytes(ctypes.byref(g))
+    D = lambda it=32, b=wsb, codes=1: L.fic_decode_pifs(hctx.handle, codes, ctypes.byref(g), it,
+                                                       None, 1, 1, b, 1, None)
+    assert D() == fic.ERR_DEVICE
+    assert D(it=-1) == fic.ERR_INVALID_ARG
+    assert D(it=100000) == fic.ERR_INVALID_ARG
+    assert D(b=wsb - 1) == fic.ERR_WORKSPACE
+    assert D(codes=None) == fic.ERR_INVALID_ARG
+
+
+def test_batch_validation(L, hctx):
+    descs = (fic.ImageDesc * 2)()
+    for i in range(2):
+        descs[i].img = 1
+        descs[i].geom = fic.make_geom(128, 128, 4 + 4 * i, 2)
+        descs[i].tol = 0.05
+        descs[i].codes = 1
+    wsb = L.fic_batch_workspace_bytes(2, descs)
+    assert wsb > 0
+    assert L.fic_encode_pifs_batch(hctx.handle, 2, descs, 1, wsb, None) == fic.ERR_DEVICE
+    assert L.fic_encode_pifs_batch(hctx.handle, 2, descs, 1, wsb - 1, None) == fic.ERR_WORKSPACE
+    descs[1].tol = float("nan")
+    assert L.fic_encode_pifs_batch(hctx.handle, 2, descs, 1, wsb, None) == fic.ERR_INVALID_ARG
+    assert L.fic_encode_pifs_batch(hctx.handle, 0, descs, 1, wsb, None) == fic.ERR_INVALID_ARG
+
+
+def test_workspace_sizes_grow(L):
+    a = L.fic_encode_workspace_bytes(ctypes.byref(fic.make_geom(256, 256, 8, 1)), 0)
+    b = L.fic_encode_workspace_bytes(ctypes.byref(fic.make_geom(512, 512, 8, 1)), 0)
+    assert 0 < a < b
+    assert L.fic_encode_workspace_bytes(ctypes.byref(fic.make_geom(30, 30, 8, 1)), 0) == 0

@@ -1,0 +1,274 @@
+"""GPU parity: every stage of the HIP path against the CPU oracle, through
+the C ABI, on the same seeded inputs.
+
+Bar: codes (domain, isometry, k, j, flags, E) bit-exact; fractal dimensions
+within 1e-12 in fp64 and 1e-5 in fp32 of the oracle's fp64 values; pool sets
+identical; decoded images bit-exact. Small cases are compared on every
+range; the full-size workloads on sampled ranges (the oracle computes them
+one by one) plus MFMA == plain on every range.
+"""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def fic():
+    import paper_1206_4880_amd as p
+    if not torch.cuda.is_available():
+        raise RuntimeError("GPU tests need a HIP device")
+    p.fic.lib()
+    return p
+
+
+@pytest.fixture(scope="module")
+def orc():
+    import oracle
+    oracle.build(force=False)
+    return oracle
+
+
+def dev(img):
+    return torch.from_numpy(np.ascontiguousarray(img)).cuda()
+
+
+def fbm(n, h, seed, w=None):
+    from synth import fbm as _f
+    return _f(n, w or n, h, np.random.default_rng(seed))
+
+
+def assert_codes(got, ref, sel=None, what=""):
+    g = got if sel is None else got[sel]
+    pairs = (("domain", "dom"), ("iso", "iso"), ("s_idx", "k"), ("o_idx", "j"),
+             ("flags", "flags"), ("err", "err"))
+    for fg, fr in pairs:
+        a = g[fg].astype(np.int64)
+        b = np.asarray(ref[fr]).astype(np.int64)
+        if not np.array_equal(a, b):
+            bad = np.flatnonzero(a != b)[:5]
+            raise AssertionError("%s: field %s differs at %s: gpu %s oracle %s"
+                                 % (what, fg, bad, a[bad], b[bad]))
+
+
+def gpu_encode(fic, img, b, t, tol, kernel):
+    codes, pool = fic.encode(dev(img), b, t, tol=tol, kernel=kernel)
+    torch.cuda.synchronize()
+    return fic.unpack_codes(codes), pool
+
+
+# ------------------------------------------------------------- classify
+@pytest.mark.parametrize("m,step", [(4, 4), (8, 8), (16, 16), (8, 1), (8, 2), (16, 1), (16, 2),
+                                    (32, 4), (32, 3)])
+def test_fd_classify(fic, orc, m, step):
+    imgs = [fbm(96, 0.4, 1), fbm(64, 0.8, 2, w=160),
+            np.random.default_rng(3).integers(0, 256, (80, 72)).astype(np.uint8),
+            np.full((64, 64), 17, np.uint8)]
+    for img in imgs:
+        fd64, fd32 = fic.fd_classify(dev(img), m, step)
+        torch.cuda.synchronize()
+        ref = orc.fd_blocks(img, m, step)
+        a64, a32 = fd64.cpu().numpy(), fd32.cpu().numpy()
+        assert a64.shape == ref.shape
+        assert np.max(np.abs(a64 - ref)) < 1e-12
+        assert np.max(np.abs(a32.astype(np.float64) - ref)) < 1e-5
+
+
+def test_fd_classify_full_size(fic, orc):
+    from synth import workload_images
+    img = workload_images("fbm1024_b8t1")
+    fd64, fd32 = fic.fd_classify(dev(img), 16, 1)
+    torch.cuda.synchronize()
+    ref = orc.fd_blocks(img, 16, 1)
+    assert np.max(np.abs(fd64.cpu().numpy() - ref)) < 1e-12
+    assert np.max(np.abs(fd32.cpu().numpy().astype(np.float64) - ref)) < 1e-5
+
+
+# ------------------------------------------------------------------ pool
+def check_pool(perm, lo, hi, fd_r, fd_d, tol_eff, sel=None):
+    perm = perm.cpu().numpy().astype(np.int64)
+    lo = lo.cpu().numpy().astype(np.int64)
+    hi = hi.cpu().numpy().astype(np.int64)
+    # perm is a stable ascending order of the domain values
+    assert np.array_equal(np.sort(perm), np.arange(fd_d.size))
+    vals = fd_d[perm]
+    assert np.all(np.diff(vals) >= 0)
+    eq = np.diff(vals) == 0
+    assert np.all(np.diff(perm)[eq] > 0)
+    rows = range(fd_r.size) if sel is None else sel
+    for r in rows:
+        want = np.flatnonzero(np.abs(fd_d - fd_r[r]) <= tol_eff + 1e-9)
+        got = np.sort(perm[lo[r]:hi[r]])
+        assert np.array_equal(got, want), r
+
+
+@pytest.mark.parametrize("tol", [0.0, 0.02, 0.05, 0.1, -1.0, float("inf")])
+def test_pool_sets(fic, orc, tol):
+    img = fbm(128, 0.5, 5)
+    b, t = 4, 2
+    fr_t, _ = fic.fd_classify(dev(img), b, b)
+    fd_t, _ = fic.fd_classify(dev(img), 2 * b, t)
+    perm, lo, hi = fic.build_domain_pool(fr_t, fd_t, tol)
+    torch.cuda.synchronize()
+    fr, fd = orc.classify(img, b, t)
+    tol_eff = orc.resolve_tol(tol, fd)
+    if math.isfinite(tol_eff):
+        assert orc.pool_margin(fr, fd, tol_eff) > 1e-12
+    check_pool(perm, lo, hi, fr, fd, tol_eff)
+
+
+# ---------------------------------------------------- encode, small, exact
+SMALL = [
+    ("fbm64 8/1 exhaustive", lambda: fbm(64, 0.5, 1), 8, 1, None),
+    ("fbm 96x80 4/1", lambda: fbm(96, 0.6, 7, w=80), 4, 1, None),
+    ("fbm 96x80 4/3 pool", lambda: fbm(96, 0.6, 7, w=80), 4, 3, 0.05),
+    ("fbm 128 16/4", lambda: fbm(128, 0.6, 8), 16, 4, None),
+    ("fbm 128 16/2 pool", lambda: fbm(128, 0.6, 8), 16, 2, 0.1),
+    ("uniform 72x88 8/2", lambda: np.random.default_rng(9).integers(0, 256, (72, 88)).astype(np.uint8),
+     8, 2, None),
+    ("rects 128 8/1 pool", None, 8, 1, 0.05),
+    ("piecewise 128 4/2 pool", None, 4, 2, 0.05),
+    ("piecewise 128 8/2 adaptive", None, 8, 2, -1.0),
+    ("flat 64 8/1", lambda: np.full((64, 64), 200, np.uint8), 8, 1, None),
+    ("flat 64 8/1 pool", lambda: np.full((64, 64), 200, np.uint8), 8, 1, 0.05),
+    ("minimal 16x16 8/1", lambda: fbm(16, 0.5, 3), 8, 1, None),
+    ("tol 0: empty pools", lambda: fbm(64, 0.3, 12), 8, 2, 0.0),
+]
+
+
+def small_image(name, make):
+    from synth import add_rectangles, piecewise_smooth
+    if make is not None:
+        return make()
+    if name.startswith("rects"):
+        rng = np.random.default_rng(21)
+        return add_rectangles(fbm(128, 0.7, 20), 12, rng)
+    return piecewise_smooth(128, np.random.default_rng(22))
+
+
+@pytest.mark.parametrize("case", SMALL, ids=[c[0] for c in SMALL])
+@pytest.mark.parametrize("kernel", ["mfma", "plain"])
+def test_encode_small_exact(fic, orc, case, kernel):
+    name, make, b, t, tol = case
+    img = small_image(name, make)
+    got, _ = gpu_encode(fic, img, b, t, tol, kernel)
+    ref = orc.encode(img, b, t, tol=tol)
+    assert_codes(got, ref, what=name)
+
+
+def test_encode_planted_copy(fic, orc):
+    """A range planted as s=1/2 times an isometric domain copy: zero error."""
+    from oracle import bruteforce as bf
+    b, t = 8, 2
+    img = fbm(64, 0.5, 3)
+    rng = np.random.default_rng(5)
+    v = 2 * rng.integers(10, 100, size=(b, b))
+    v[0, 0] += (-v.sum()) % (2 * b * b)
+    img[32:48, 32:48] = np.kron(v, np.ones((2, 2)))
+    img[0:8, 8:16] = (bf.isometries(v)[5] - v.mean()) // 2 + 128
+    for kernel in ("mfma", "plain"):
+        got, _ = gpu_encode(fic, img, b, t, None, kernel)
+        assert got["err"][1] == 0
+        ref = orc.encode(img, b, t)
+        assert_codes(got, ref, what="planted " + kernel)
+
+
+# ------------------------------------------------ full-size workloads
+def sampled(R, count, seed=0):
+    rng = np.random.default_rng(seed)
+    s = np.unique(np.concatenate([[0, R - 1], rng.choice(R, size=count, replace=False)]))
+    return s.astype(np.int64)
+
+
+@pytest.mark.parametrize("job", [(8, 2, None), (8, 2, 0.05)])
+def test_workload_512_rects(fic, orc, job):
+    from synth import workload_images
+    img = workload_images("fbm512rect_b8t2")
+    b, t, tol = job
+    mf, _ = gpu_encode(fic, img, b, t, tol, "mfma")
+    pl, _ = gpu_encode(fic, img, b, t, tol, "plain")
+    for f in mf.dtype.names:
+        assert np.array_equal(mf[f], pl[f]), f
+    sel = sampled(mf.size, 160)
+    ref = orc.encode(img, b, t, tol=tol, sel=sel)
+    assert_codes(mf, ref, sel=sel, what="512 rects %s" % (job,))
+
+
+@pytest.mark.parametrize("tol", [None, 0.02, 0.1])
+def test_workload_1024(fic, orc, tol):
+    from synth import workload_images
+    img = workload_images("fbm1024_b8t1")
+    mf, _ = gpu_encode(fic, img, 8, 1, tol, "mfma")
+    assert np.all(mf["flags"] == 0)
+    sel = sampled(mf.size, 40 if tol is None else 64, seed=1)
+    ref = orc.encode(img, 8, 1, tol=tol, sel=sel)
+    assert_codes(mf, ref, sel=sel, what="1024 tol=%s" % tol)
+
+
+@pytest.mark.parametrize("job", [(16, 4, 0.05), (8, 2, 0.05)])
+def test_workload_2048(fic, orc, job):
+    from synth import workload_images
+    img = workload_images("fbm2048_twolevel")
+    b, t, tol = job
+    mf, _ = gpu_encode(fic, img, b, t, tol, "mfma")
+    sel = sampled(mf.size, 48, seed=2)
+    ref = orc.encode(img, b, t, tol=tol, sel=sel)
+    assert_codes(mf, ref, sel=sel, what="2048 %s" % (job,))
+
+
+def test_batch_matches_single(fic, orc):
+    from synth import batch_descs
+    items = batch_descs(count=6)
+    imgs = [dev(im) for (im, _, _, _) in items]
+    jobs = [(b, t, tol) for (_, b, t, tol) in items]
+    outs = fic.encode_batch(imgs, jobs)
+    torch.cuda.synchronize()
+    for (im, b, t, tol), c in zip(items, outs):
+        got = fic.unpack_codes(c)
+        single, _ = gpu_encode(fic, im, b, t, tol, "mfma")
+        for f in got.dtype.names:
+            assert np.array_equal(got[f], single[f]), f
+        sel = sampled(got.size, 24, seed=3)
+        ref = orc.encode(im, b, t, tol=tol, sel=sel)
+        assert_codes(got, ref, sel=sel, what="batch %dx%d B=%d" % (im.shape + (b,)))
+
+
+def test_repeat_determinism(fic):
+    """The packed-key minimum does not depend on the order in which waves
+    finish: repeated runs give identical codes."""
+    from synth import workload_images
+    img = dev(workload_images("fbm512rect_b8t2"))
+    first = None
+    for _ in range(3):
+        c, _ = fic.encode(img, 8, 2, tol=0.05, kernel="mfma")
+        torch.cuda.synchronize()
+        a = c.cpu().numpy()
+        if first is None:
+            first = a
+        assert np.array_equal(a, first)
+
+
+# ----------------------------------------------------------------- decode
+@pytest.mark.parametrize("case", [(64, 8, 1, None), (128, 4, 2, 0.05), (128, 16, 4, None)])
+def test_decode(fic, orc, case):
+    n, b, t, tol = case
+    img = fbm(n, 0.6, n + b)
+    codes, _ = fic.encode(dev(img), b, t, tol=tol)
+    out, iters = fic.decode_pifs(codes, n, n, b, t, max_iters=32)
+    torch.cuda.synchronize()
+    got = fic.unpack_codes(codes)
+    ref_codes = {"dom": got["domain"], "iso": got["iso"], "k": got["s_idx"], "j": got["o_idx"]}
+    ref, it = orc.decode(ref_codes, n, n, b, t, max_iters=32)
+    assert np.array_equal(out.cpu().numpy(), ref)
+    assert int(iters.item()) == it
+    assert orc.psnr(ref, img) > 20.0
+    # a partial decode from a given start image
+    start = np.random.default_rng(1).integers(0, 256, (n, n)).astype(np.uint8)
+    out2, it2 = fic.decode_pifs(codes, n, n, b, t, max_iters=3, init=dev(start))
+    torch.cuda.synchronize()
+    ref2, r2 = orc.decode(ref_codes, n, n, b, t, max_iters=3, init=start)
+    assert np.array_equal(out2.cpu().numpy(), ref2) and int(it2.item()) == r2

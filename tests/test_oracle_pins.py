@@ -161,7 +161,7 @@ def test_planted_zero_error_copy(oracle_lib):
     dy, dx = 16, 16
     img[dy:dy + 2 * b, dx:dx + 2 * b] = np.kron(v, np.ones((2, 2)))
     q = 3
-    r_blk = (bf.isometries(v)[q] - v.mean()) // 2 + 2 * 30
+    r_blk = (bf.isometries(v)[q] - v.mean()) // 2 + 2 * 64
     ry, rx = 0, 4
     img[ry:ry + b, rx:rx + b] = r_blk
     ranges, doms = bf.lattice(32, 32, b, t)
