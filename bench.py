@@ -1,0 +1,265 @@
+"""Benchmark of the range-domain matching search on one MI355X.
+
+One step is one pass of the whole hot path over the workload image:
+  fractal dimension of all ranges and domains (differential box counting),
+  the dynamic pool for each tolerance (sort + window bounds),
+  and for every job (exhaustive, then each pooled tolerance) range prep,
+  domain prep, the persistent MFMA search and finalize.
+Inputs are resident in HBM before the timed region. The JSON line reports
+pair evaluations per second over the whole step (value), encode seconds per
+image per job, a roofline of the dominant kernel (the exhaustive MFMA search,
+timed by HIP events the library records on its own stream), the plain
+one-thread-per-pair kernel on the same exhaustive search, and the CPU oracle
+timed on a bounded sample on the host cores.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "range-domain pair evals/s + encode s/image, 1024² uint8; MFMA vs plain GPU"
+PEAK_FP16_TFLOPS = 2500.0    # MI355X dense FP16 MFMA
+PEAK_HBM_GBS = 8000.0        # MI355X HBM3E
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "search_mfma_fbm1024_traffic.json")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("encode.hip", "fic_internal.h"):
+        with open(os.path.join(ROOT, "paper_1206_4880_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per exhaustive search launch from the committed rocprofv3
+    counter runs, or None when they were taken on other kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="fbm1024_b8t1")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain-kernel comparison")
+    ap.add_argument("--counters", action="store_true",
+                    help="one extra untimed step with survivor counters")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the search shards by ranges with no exchange "
+              "beyond gathering codes, and this build runs on a single device only "
+              "(got --gpus %d)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1206_4880_amd as fic
+    from synth import WORKLOADS, workload_images
+
+    wl = WORKLOADS[args.workload]
+    img_np = workload_images(args.workload)
+    dev = torch.device("cuda:0")
+    img = torch.from_numpy(img_np).to(dev)
+    H, W = img_np.shape
+    jobs = list(wl.jobs)
+    b0, t0 = jobs[0][0], jobs[0][1]
+    if any((b, t) != (b0, t0) for (b, t, _) in jobs):
+        raise SystemExit("bench workloads share one range size and step per image")
+    ctx = fic.fic.context(0)
+    R = fic.fic.num_ranges(H, W, b0)
+    D = fic.fic.num_domains(H, W, b0, t0)
+    n = b0 * b0
+    codes = [torch.empty((R, 16), dtype=torch.uint8, device=dev) for _ in jobs]
+
+    def step(kernel="mfma"):
+        fr, _ = fic.fd_classify(img, b0, b0, want_fp32=False)
+        fd, _ = fic.fd_classify(img, 2 * b0, t0, want_fp32=False)
+        pools = {}
+        for (_, _, tol) in jobs:
+            if tol is not None:
+                pools[tol] = fic.build_domain_pool(fr, fd, tol)
+        for i, (b, t, tol) in enumerate(jobs):
+            fic.encode_pifs(img, b, t, pool=pools.get(tol), kernel=kernel, codes=codes[i])
+        return pools
+
+    # pair counts per job (from one untimed step)
+    pools = step()
+    torch.cuda.synchronize()
+    pairs = []
+    for (b, t, tol) in jobs:
+        if tol is None:
+            pairs.append(R * D * 8)
+        else:
+            _, lo, hi = pools[tol]
+            pairs.append(int((hi.long() - lo.long()).sum().item()) * 8)
+    pairs_step = sum(pairs)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t_end = time.perf_counter()
+    recs = ctx.timing_read()
+    ctx.timing(False)
+    ms_step = (t_end - t_start) * 1e3 / args.steps
+
+    # stage times: classify x2, pool x n_pool, then per job 5 encode stages
+    per_step = len(recs) // args.steps
+    stage_ms = {}
+    job_ms = [dict() for _ in jobs]
+    search_ms = [[] for _ in jobs]
+    for s in range(args.steps):
+        chunk = recs[s * per_step:(s + 1) * per_step]
+        ji = -1
+        for (name, ms) in chunk:
+            stage_ms[name] = stage_ms.get(name, 0.0) + ms / args.steps
+            if name == "range_prep":
+                ji += 1
+            if ji >= 0:
+                job_ms[ji][name] = job_ms[ji].get(name, 0.0) + ms / args.steps
+            if name == "search":
+                search_ms[ji].append(ms)
+    shared_ms = stage_ms.get("classify", 0.0) + stage_ms.get("pool", 0.0)
+
+    def job_label(tol):
+        return "exhaustive" if tol is None else "pool_%g" % tol
+
+    encode_s = {}
+    job_rate = {}
+    for i, (b, t, tol) in enumerate(jobs):
+        enc_ms = sum(job_ms[i].values())
+        if tol is not None:   # the pooled job also needs the classification and its pool
+            enc_ms += stage_ms.get("classify", 0.0) + stage_ms.get("pool", 0.0) / max(
+                1, sum(1 for j in jobs if j[2] is not None))
+        encode_s[job_label(tol)] = round(enc_ms / 1e3, 6)
+        job_rate[job_label(tol)] = pairs[i] / (sum(search_ms[i]) / len(search_ms[i]) / 1e3)
+
+    # roofline of the dominant kernel: the exhaustive MFMA search
+    dom = max(range(len(jobs)), key=lambda i: np.mean(search_ms[i]))
+    t_search = float(np.mean(search_ms[dom])) / 1e3
+    flops = pairs[dom] * 2 * n
+    achieved = flops / t_search / 1e12
+    traffic = measured_traffic()
+    roofline = {"kernel": "k_search_mfma<%d> (%s)" % (b0, job_label(jobs[dom][2])),
+                "bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_FP16_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP16_TFLOPS, 4),
+                "traffic": traffic, "avg_launch_ms": round(t_search * 1e3, 4),
+                "flop_per_launch": flops}
+
+    # HBM fraction of the classify and domain-prep stages
+    img_bytes = H * W
+    dfd = ((H - 2 * b0) // t0 + 1) * ((W - 2 * b0) // t0 + 1)
+    rfd = R
+    classify_bytes = 2 * img_bytes + 8 * (dfd + rfd)
+    dprep_bytes = img_bytes + D * (2 * n + 4 + 4 + 8 + 4)
+    hbm = {}
+    if stage_ms.get("classify"):
+        gbs = classify_bytes / (stage_ms["classify"] / 1e3) / 1e9
+        hbm["classify"] = {"GB/s": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4),
+                           "bytes": classify_bytes}
+    dprep_ms = np.mean([jm.get("domain_prep", 0.0) for jm in job_ms])
+    if dprep_ms:
+        gbs = dprep_bytes / (dprep_ms / 1e3) / 1e9
+        hbm["domain_prep"] = {"GB/s": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4),
+                              "bytes": dprep_bytes}
+
+    out = {
+        "metric": METRIC,
+        "value": round(pairs_step / (ms_step / 1e3), 1),
+        "unit": "pair evals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f16", "data": "synthetic",
+        "config": {"workload": wl.name, "description": wl.description,
+                   "image": "%dx%d" % (H, W), "range_size": b0, "domain_step": t0,
+                   "jobs": [job_label(t) for (_, _, t) in jobs],
+                   "pairs_per_step": pairs_step, "pairs_per_job": pairs},
+        "encode_s_per_image": encode_s,
+        "search_pairs_per_s": {k: round(v, 1) for k, v in job_rate.items()},
+        "stage_ms_per_step": {k: round(v, 4) for k, v in stage_ms.items()},
+        "shared_classify_pool_ms": round(shared_ms, 4),
+        "roofline": roofline,
+        "hbm_stages": hbm,
+    }
+
+    if args.counters:
+        cnt = torch.zeros(4, dtype=torch.int64, device=dev)
+        ctx.set_counters(cnt)
+        step()
+        torch.cuda.synchronize()
+        ctx.set_counters(None)
+        c = cnt.cpu().numpy()
+        out["screen"] = {"pairs_screened_16x16": int(c[0]), "exact_evaluations": int(c[1]),
+                         "work_items": int(c[2]), "seed_evaluations": int(c[3]),
+                         "exact_fraction": float(c[1]) / pairs_step}
+
+    if not args.no_plain:
+        ex = [i for i, j in enumerate(jobs) if j[2] is None]
+        if ex:
+            i = ex[0]
+            fic.encode_pifs(img, b0, t0, pool=None, kernel="plain", codes=codes[i])   # warm
+            torch.cuda.synchronize()
+            ctx.timing(True)
+            fic.encode_pifs(img, b0, t0, pool=None, kernel="plain", codes=codes[i])
+            torch.cuda.synchronize()
+            prec = ctx.timing_read()
+            ctx.timing(False)
+            p_search = sum(ms for (nme, ms) in prec if nme == "search") / 1e3
+            p_total = sum(ms for (nme, ms) in prec) / 1e3
+            out["plain"] = {"exhaustive_search_pairs_per_s": round(pairs[i] / p_search, 1),
+                            "exhaustive_encode_s": round(p_total, 6),
+                            "mfma_search_speedup": round(job_rate["exhaustive"] /
+                                                         (pairs[i] / p_search), 3)}
+
+    if not args.no_cpu:
+        import oracle
+        oracle.build(force=False)
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+        sel_probe = np.array([R // 2], dtype=np.int64)
+        t0p = time.perf_counter()
+        oracle.encode(img_np, b0, t0, sel=sel_probe, nthreads=threads)
+        per_range = max(time.perf_counter() - t0p, 1e-3)
+        count = int(max(1, min(R, args.cpu_seconds / per_range)))
+        sel = np.linspace(0, R - 1, count).astype(np.int64)
+        t1 = time.perf_counter()
+        oracle.encode(img_np, b0, t0, sel=sel, nthreads=threads)
+        cpu_s = time.perf_counter() - t1
+        cpu_pairs = count * D * 8
+        out["cpu_baseline"] = {
+            "value": round(cpu_pairs / cpu_s, 1), "unit": "pair evals/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "exhaustive search of %d of %d ranges of the %s image (%d pair "
+                      "evaluations, %.1f s)" % (count, R, wl.name, cpu_pairs, cpu_s)}
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -112,6 +112,30 @@ const char *fic_status_string(fic_status s);
    NULL (the default) disables the adds. */
 fic_status fic_set_counters(fic_ctx *ctx, uint64_t *counters /* dev */);
 
+/* Stage tracing. With timing enabled, each later call records a pair of HIP
+   events around each of its stages, on the call's own stream:
+     FIC_STAGE_CLASSIFY    differential box counting (fic_fd_classify)
+     FIC_STAGE_POOL        sort + window bounds (fic_build_domain_pool)
+     FIC_STAGE_RANGE_PREP  range order, sums and A rows
+     FIC_STAGE_DOMAIN_PREP 2x2 sums, domain sums and B columns
+     FIC_STAGE_WORKLIST    seeds and the work list of the persistent search
+     FIC_STAGE_SEARCH      the search kernel itself (MFMA or plain)
+     FIC_STAGE_FINAL       finalize (codes)
+     FIC_STAGE_DECODE      all decoding sweeps
+   fic_timing_enable(ctx, 1) clears the record and starts recording; 0 stops.
+   fic_timing_read waits for the recorded events (host sync), then writes up
+   to `capacity` (stage, milliseconds) pairs in record order (host arrays)
+   and the total number recorded to *count. Events are host objects; no
+   device memory is allocated. */
+enum {
+    FIC_STAGE_CLASSIFY = 0, FIC_STAGE_POOL = 1, FIC_STAGE_RANGE_PREP = 2,
+    FIC_STAGE_DOMAIN_PREP = 3, FIC_STAGE_WORKLIST = 4, FIC_STAGE_SEARCH = 5,
+    FIC_STAGE_FINAL = 6, FIC_STAGE_DECODE = 7
+};
+fic_status fic_timing_enable(fic_ctx *ctx, int32_t enable);
+fic_status fic_timing_read(fic_ctx *ctx, int32_t *stages /* host */, float *ms /* host */,
+                           int32_t capacity, int32_t *count /* host */);
+
 /* Number of ranges / domains of a geometry (host helpers; 0 if invalid). */
 int64_t fic_num_ranges(const fic_geom *g /* host */);
 int64_t fic_num_domains(const fic_geom *g /* host */);

@@ -8,6 +8,7 @@
 #include <new>
 #include <string.h>
 #include <math.h>
+#include <vector>
 
 #include "fic_internal.h"
 
@@ -18,7 +19,51 @@ struct fic_ctx {
     int32_t device;      // -1: host-only context
     int32_t num_cu;
     u64 *counters;
+    // stage tracing: (stage, begin event, end event) per recorded stage
+    struct Rec { int stage; hipEvent_t a, b; };
+    bool timing;
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> spare;
+    int open_stage;
+    hipEvent_t open_ev;
+    fic::Tracer tracer;
 };
+
+namespace {
+
+hipEvent_t take_event(fic_ctx *c)
+{
+    if (!c->spare.empty()) {
+        hipEvent_t e = c->spare.back();
+        c->spare.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+void mark_stage(void *self, int stage, int begin, hipStream_t s)
+{
+    fic_ctx *c = (fic_ctx *)self;
+    hipEvent_t e = take_event(c);
+    if (!e) return;
+    hipEventRecord(e, s);
+    if (begin) {
+        if (c->open_ev) c->spare.push_back(c->open_ev);
+        c->open_ev = e;
+        c->open_stage = stage;
+    } else if (c->open_ev && c->open_stage == stage) {
+        c->recs.push_back({stage, c->open_ev, e});
+        c->open_ev = nullptr;
+    } else {
+        c->spare.push_back(e);
+    }
+}
+
+const fic::Tracer *tracer_of(fic_ctx *c) { return c->timing ? &c->tracer : nullptr; }
+
+}  // namespace
 
 namespace {
 
@@ -127,6 +172,11 @@ fic_status fic_create(int32_t device, fic_ctx **out)
     c->device = device;
     c->num_cu = 0;
     c->counters = nullptr;
+    c->timing = false;
+    c->open_stage = -1;
+    c->open_ev = nullptr;
+    c->tracer.self = c;
+    c->tracer.mark = mark_stage;
     if (device >= 0) {
         int n = 0;
         if (hipGetDeviceCount(&n) != hipSuccess || device >= n) {
@@ -151,7 +201,42 @@ fic_status fic_create(int32_t device, fic_ctx **out)
 fic_status fic_destroy(fic_ctx *ctx)
 {
     if (!ctx) return FIC_ERR_INVALID_ARG;
+    if (ctx->device >= 0) {
+        for (auto &r : ctx->recs) { hipEventDestroy(r.a); hipEventDestroy(r.b); }
+        for (auto e : ctx->spare) hipEventDestroy(e);
+        if (ctx->open_ev) hipEventDestroy(ctx->open_ev);
+    }
     delete ctx;
+    return FIC_OK;
+}
+
+fic_status fic_timing_enable(fic_ctx *ctx, int32_t enable)
+{
+    if (!ctx) return FIC_ERR_INVALID_ARG;
+    for (auto &r : ctx->recs) { ctx->spare.push_back(r.a); ctx->spare.push_back(r.b); }
+    ctx->recs.clear();
+    if (ctx->open_ev) { ctx->spare.push_back(ctx->open_ev); ctx->open_ev = nullptr; }
+    ctx->timing = enable != 0;
+    return FIC_OK;
+}
+
+fic_status fic_timing_read(fic_ctx *ctx, int32_t *stages, float *ms, int32_t capacity,
+                           int32_t *count)
+{
+    if (!ctx || !count || capacity < 0 || (capacity > 0 && (!stages || !ms)))
+        return FIC_ERR_INVALID_ARG;
+    *count = (int32_t)ctx->recs.size();
+    if (ctx->recs.empty()) return FIC_OK;
+    fic_status st = enter(ctx);
+    if (st != FIC_OK) return st;
+    for (int32_t i = 0; i < (int32_t)ctx->recs.size() && i < capacity; ++i) {
+        const auto &r = ctx->recs[i];
+        float t = 0.0f;
+        if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&t, r.a, r.b) != hipSuccess)
+            return FIC_ERR_DEVICE;
+        stages[i] = r.stage;
+        ms[i] = t;
+    }
     return FIC_OK;
 }
 
@@ -176,7 +261,7 @@ fic_status fic_fd_classify(fic_ctx *ctx, const uint8_t *img, const fic_geom *g, 
     fic_status st = enter(ctx);
     if (st != FIC_OK) return st;
     return dev_status(fic::launch_fd_classify(img, g->height, g->width, g->pitch, block, step, fd64,
-                                              fd32, (hipStream_t)stream));
+                                              fd32, (hipStream_t)stream, tracer_of(ctx)));
 }
 
 size_t fic_pool_workspace_bytes(int64_t n_range, int64_t n_domain)
@@ -196,7 +281,7 @@ fic_status fic_build_domain_pool(fic_ctx *ctx, const double *fd_range, int32_t n
     fic_status st = enter(ctx);
     if (st != FIC_OK) return st;
     return dev_status(fic::launch_pool(fd_range, n_range, fd_domain, n_domain, tol, perm, lo, hi, ws,
-                                       (hipStream_t)stream));
+                                       (hipStream_t)stream, tracer_of(ctx)));
 }
 
 size_t fic_encode_workspace_bytes(const fic_geom *g, int32_t pooled)
@@ -224,7 +309,7 @@ fic_status fic_encode_pifs(fic_ctx *ctx, const uint8_t *img, const fic_geom *g,
     fic_status st = enter(ctx);
     if (st != FIC_OK) return st;
     return dev_status(fic::run_encode(p, img, perm, lo, hi, kernel, codes, ws, ctx->num_cu,
-                                      ctx->counters, (hipStream_t)stream));
+                                      ctx->counters, (hipStream_t)stream, tracer_of(ctx)));
 }
 
 size_t fic_batch_workspace_bytes(int32_t n_images, const fic_image_desc *descs)
@@ -268,19 +353,21 @@ fic_status fic_encode_pifs_batch(fic_ctx *ctx, int32_t n_images, const fic_image
         uint32_t *hi = (uint32_t *)(w + bp.off_hi);
         hipError_t e = hipSuccess;
         if (pooled) {
-            e = fic::launch_fd_classify(d.img, g.h, g.w, g.pitch, g.b, g.b, fdr, nullptr, s);
+            e = fic::launch_fd_classify(d.img, g.h, g.w, g.pitch, g.b, g.b, fdr, nullptr, s,
+                                        tracer_of(ctx));
             if (e == hipSuccess)
-                e = fic::launch_fd_classify(d.img, g.h, g.w, g.pitch, 2 * g.b, g.t, fdd, nullptr, s);
+                e = fic::launch_fd_classify(d.img, g.h, g.w, g.pitch, 2 * g.b, g.t, fdd, nullptr, s,
+                                            tracer_of(ctx));
             if (e == hipSuccess)
                 e = fic::launch_pool(fdr, (int32_t)g.R, fdd, (int32_t)g.D, d.tol, perm, lo, hi,
-                                     w + bp.off_pool, s);
+                                     w + bp.off_pool, s, tracer_of(ctx));
         }
         fic::EncodePlan p;
         fic::plan_encode(g, pooled, p);
         if (e == hipSuccess)
             e = fic::run_encode(p, d.img, pooled ? perm : nullptr, pooled ? lo : nullptr,
                                 pooled ? hi : nullptr, FIC_KERNEL_MFMA, d.codes, w + bp.off_enc,
-                                ctx->num_cu, ctx->counters, s);
+                                ctx->num_cu, ctx->counters, s, tracer_of(ctx));
         if (e != hipSuccess) return FIC_ERR_DEVICE;
     }
     return FIC_OK;
@@ -303,7 +390,8 @@ fic_status fic_decode_pifs(fic_ctx *ctx, const fic_code *codes, const fic_geom *
     fic_status st = enter(ctx);
     if (st != FIC_OK) return st;
     return dev_status(
-        fic::run_decode(gg, codes, max_iters, init, out, scratch, iters_done, (hipStream_t)stream));
+        fic::run_decode(gg, codes, max_iters, init, out, scratch, iters_done, (hipStream_t)stream,
+                        tracer_of(ctx)));
 }
 
 }  // extern "C"

@@ -95,8 +95,9 @@ __global__ void k_decode_out(const uint8_t *__restrict__ b0, const uint8_t *__re
 
 template <int B>
 hipError_t run_b(const Geom &g, const fic_code *codes, int32_t max_iters, const uint8_t *init,
-                 uint8_t *out, void *ws, int32_t *iters, hipStream_t s)
+                 uint8_t *out, void *ws, int32_t *iters, hipStream_t s, const Tracer *tr)
 {
+    trace(tr, FIC_STAGE_DECODE, 1, s);
     const int64_t np = (int64_t)g.h * g.w;
     char *w = (char *)ws;
     uint8_t *b0 = (uint8_t *)w;
@@ -119,6 +120,7 @@ hipError_t run_b(const Geom &g, const fic_code *codes, int32_t max_iters, const 
     }
     hipLaunchKernelGGL(k_decode_out, dim3((unsigned)((np + th - 1) / th)), dim3(th), 0, s, b0, b1,
                        np, iters, out);
+    trace(tr, FIC_STAGE_DECODE, 0, s);
     return hipGetLastError();
 }
 
@@ -133,12 +135,13 @@ size_t decode_ws_bytes(const Geom &g)
 int32_t decode_max_iters() { return kMaxIters; }
 
 hipError_t run_decode(const Geom &g, const fic_code *codes, int32_t max_iters,
-                      const uint8_t *init, uint8_t *out, void *ws, int32_t *iters, hipStream_t s)
+                      const uint8_t *init, uint8_t *out, void *ws, int32_t *iters, hipStream_t s,
+                      const Tracer *tr)
 {
     switch (g.b) {
-    case 4: return run_b<4>(g, codes, max_iters, init, out, ws, iters, s);
-    case 8: return run_b<8>(g, codes, max_iters, init, out, ws, iters, s);
-    case 16: return run_b<16>(g, codes, max_iters, init, out, ws, iters, s);
+    case 4: return run_b<4>(g, codes, max_iters, init, out, ws, iters, s, tr);
+    case 8: return run_b<8>(g, codes, max_iters, init, out, ws, iters, s, tr);
+    case 16: return run_b<16>(g, codes, max_iters, init, out, ws, iters, s, tr);
     default: return hipErrorInvalidValue;
     }
 }

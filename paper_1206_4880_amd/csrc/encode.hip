@@ -58,16 +58,38 @@ __global__ void k_fill_u64(u64 *p, int64_t n, u64 v)
 }
 
 // ---------------------------------------------------------------- prep
-// Range order for pooled search: ranges sorted by the start of their pool
-// interval (ties by index), so a group of consecutive ranges shares columns.
-__global__ void k_range_sortkeys(const uint32_t *__restrict__ lo, int64_t R, u64 *keys,
-                                 uint32_t *vals)
+// Search order of the ranges: by (lo, hi) of the pool interval, ranges that
+// need no search (flat, empty pool) last, ties by raster index. lo and hi
+// both grow with the range's dimension, so along this order the first and
+// last column of every group never decrease, and the groups that touch a
+// column chunk form one contiguous run (the work list needs no atomics).
+// Exhaustive search only moves the flat ranges to the end.
+template <int B>
+__global__ void k_range_keys(const uint8_t *__restrict__ img, int32_t pitch, int32_t rcols, int64_t R,
+                             const uint32_t *__restrict__ lo, const uint32_t *__restrict__ hi,
+                             uint32_t D, int dbits, u64 *__restrict__ keys,
+                             uint32_t *__restrict__ vals)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < R) {
-        keys[i] = lo[i];
-        vals[i] = (uint32_t)i;
-    }
+    constexpr int n = B * B;
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    const uint8_t *rp = img + (int64_t)(r / rcols) * B * pitch + (r % rcols) * B;
+    int32_t sr = 0;
+    int64_t sq = 0;
+    for (int i = 0; i < B; ++i)
+        for (int j = 0; j < B; ++j) {
+            const int v = rp[i * pitch + j];
+            sr += v;
+            sq += v * v;
+        }
+    const bool flat = (int64_t)n * sq - (int64_t)sr * sr == 0;
+    const uint32_t l = lo ? lo[r] : 0u, h = hi ? hi[r] : D;
+    const bool idle = flat || l >= h;
+    u64 key;
+    if (!lo) key = idle ? 1ull : 0ull;
+    else key = idle ? (1ull << (2 * dbits)) - 1ull : (((u64)l << dbits) | (u64)h);
+    keys[r] = key;
+    vals[r] = (uint32_t)r;
 }
 
 template <int B>
@@ -172,7 +194,7 @@ __global__ __launch_bounds__(256) void k_domain_prep(
         ((frag_t *)Bm)[(cb * KS + ks) * 64 + g * 16 + c] = f;
     }
     if (i == 0) {
-        u[p] = valid ? screen_u(sdd_, n) : __builtin_nanf("");
+        u[p] = valid ? screen_u(sdd_, n) : 1e30f;   // padding: always masked (p >= hi)
         eps[p] = valid ? (int32_t)(rs1 - (int64_t)n * dhat) : 0;
         sdd[p] = valid ? sdd_ : 0;
         dom[p] = d;
@@ -227,51 +249,71 @@ __device__ int64_t pair_f_image(const uint8_t *img, int32_t pitch, int ry, int r
     return fit_f(srr, srd, n * sdd - sd * sd, k);
 }
 
-// Initial best key per range: an exact evaluation of one candidate domain
-// (8 isometries) in its pool, so the screen starts from a real threshold.
-// Flat ranges get their final key directly.
+// Initial best key per range, so the screen starts from a real threshold:
+// one wave per range evaluates 8 candidate columns spread over its pool under
+// the 8 isometries (lane = candidate * 8 + isometry), exactly, from the
+// prepared operands (the FP16 values are integers). Flat ranges get their
+// final key directly (every pair ties at F = 0: the lowest pool index wins).
 template <int B>
-__global__ void k_seed(const uint8_t *__restrict__ img, Geom g, const RangeStat *__restrict__ rs,
-                       int64_t Rp, const uint32_t *__restrict__ perm,
-                       const uint32_t *__restrict__ bmin, int shift, u64 *__restrict__ keys,
-                       u64 *counters)
+__global__ __launch_bounds__(256) void k_seed(const _Float16 *__restrict__ A,
+                                              const _Float16 *__restrict__ Bm,
+                                              const RangeStat *__restrict__ rs,
+                                              const int32_t *__restrict__ eps,
+                                              const int64_t *__restrict__ sdd,
+                                              const uint32_t *__restrict__ dom, int64_t Rp,
+                                              const uint32_t *__restrict__ perm,
+                                              const uint32_t *__restrict__ bmin, int shift,
+                                              u64 *__restrict__ keys, u64 *counters)
 {
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    using C = Cfg<B>;
+    constexpr int n = C::n, KPI = C::KPI, EPL = C::EPL, KS = C::KS, MW = C::MW, GR = 2 * MW;
+    typedef typename Frag<EPL>::type frag_t;
+    const int64_t s = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
     if (s >= Rp) return;
     const RangeStat st = rs[s];
-    u64 key = kNoKey;
-    if (st.flags & (kPad | kEmpty)) {
-        key = kNoKey;
-    } else if (st.flags & kFlat) {
-        key = pack_key(0, pool_min_index(perm, bmin, st.lo, st.hi), 0, shift);
-    } else {
-        const int ry = (int)(st.ridx / g.rcols) * B, rx = (int)(st.ridx % g.rcols) * B;
-        uint32_t d;
-        if (perm) {
-            d = perm[(st.lo + st.hi) >> 1];
-        } else {
-            int a = min(max(ry - B / 2, 0) / g.t, g.drows - 1);
-            int c = min(max(rx - B / 2, 0) / g.t, g.dcols - 1);
-            d = (uint32_t)(a * g.dcols + c);
-        }
-        const int dy = (int)(d / g.dcols) * g.t, dx = (int)(d % g.dcols) * g.t;
-        for (int q = 0; q < 8; ++q) {
-            int k;
-            int64_t f = pair_f_image<B>(img, g.pitch, ry, rx, dy, dx, q, st.sr, st.srr, k);
-            u64 kk = pack_key(f, d, q, shift);
-            key = kk < key ? kk : key;
-        }
-        if (counters) atomicAdd(&counters[3], 8ull);
+    if (st.flags & (kPad | kEmpty | kFlat)) {
+        if (lane == 0)
+            keys[s] = (st.flags & (kPad | kEmpty))
+                          ? kNoKey
+                          : pack_key(0, pool_min_index(perm, bmin, st.lo, st.hi), 0, shift);
+        return;
     }
-    keys[s] = key;
+    const int q = lane & 7, cand = lane >> 3;
+    const uint32_t p = st.lo + (uint32_t)(((uint64_t)(st.hi - st.lo) * (2 * cand + 1)) / 16);
+    const int64_t grp = s / GR;
+    const int ls = (int)(s % GR), b = ls >> 1, row = 8 * (ls & 1) + q;
+    const frag_t *ap = (const frag_t *)A + ((grp * MW + b) * KS) * 64 + row;
+    const frag_t *bp = (const frag_t *)Bm + ((int64_t)(p >> 4) * KS) * 64 + (p & 15);
+    int32_t cx = 0;
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int g = 0; g < KPI / EPL; ++g) {
+            const frag_t fa = ap[ks * 64 + g * 16], fb = bp[ks * 64 + g * 16];
+#pragma unroll
+            for (int e = 0; e < EPL; ++e) cx += (int32_t)(float)fa[e] * (int32_t)(float)fb[e];
+        }
+    const int64_t srd = (int64_t)n * cx - (int64_t)st.delta * eps[p];
+    int k;
+    const int64_t f = fit_f(st.srr, srd, sdd[p], k);
+    u64 key = pack_key(f, dom[p], q, shift);
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const u64 o = __shfl_xor(key, off);
+        key = o < key ? o : key;
+    }
+    if (lane == 0) {
+        keys[s] = key;
+        if (counters) atomicAdd(&counters[3], 64ull);
+    }
 }
 
 // ------------------------------------------------------------ work list
 // Per group: the union [L, H) of its active ranges' intervals (rounded to
 // 16-column blocks) and their intersection [ilo, ihi) (blocks inside it need
-// no per-range mask). Counts the groups that touch each column chunk.
-__global__ void k_group_bounds(const RangeStat *__restrict__ rs, int64_t G, int GR,
-                               uint4 *__restrict__ grp, uint32_t *__restrict__ chunkcnt)
+// no per-range mask). Groups without an active range get L = H = Dp.
+__global__ void k_group_bounds(const RangeStat *__restrict__ rs, int64_t G, int GR, uint32_t Dp,
+                               uint4 *__restrict__ grp)
 {
     const int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gi >= G) return;
@@ -286,34 +328,52 @@ __global__ void k_group_bounds(const RangeStat *__restrict__ rs, int64_t G, int 
         ilo = max(ilo, st.lo);
         ihi = min(ihi, st.hi);
     }
-    if (!any) {
-        grp[gi] = make_uint4(0, 0, 0, 0);
-        return;
-    }
-    L &= ~15u;
-    H = (H + 15u) & ~15u;
-    grp[gi] = make_uint4(L, H, ilo, ihi);
-    for (uint32_t c = L / kChunk; c * kChunk < H; ++c) atomicAdd(&chunkcnt[c], 1u);
+    grp[gi] = any ? make_uint4(L & ~15u, (H + 15u) & ~15u, ilo, ihi) : make_uint4(Dp, Dp, 0, 0);
 }
 
-// Items in column-chunk-major order: the items in flight at any moment share
-// a few column chunks, which then stay resident in each XCD's L2.
-__global__ void k_emit_items(const uint4 *__restrict__ grp, int64_t G,
-                             const uint32_t *__restrict__ chunkoff, uint32_t *__restrict__ chunkfill,
+// Per column chunk c: the run of groups [gf, gl] that touch it (both ends
+// of the group intervals are monotone in the group index), and its length.
+__global__ void k_chunk_span(const uint4 *__restrict__ grp, int64_t G, int64_t NC,
+                             uint32_t *__restrict__ cnt, uint32_t *__restrict__ gfirst)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= NC) return;
+    const uint32_t c0 = (uint32_t)c * kChunk, c1 = c0 + kChunk;
+    int64_t a = 0, b = G;                    // active groups: a prefix [0, G_act)
+    while (a < b) { const int64_t m = (a + b) >> 1; if (grp[m].x < grp[m].y) a = m + 1; else b = m; }
+    const int64_t gact = a;
+    a = 0; b = gact;                         // first group with H > c0
+    while (a < b) { const int64_t m = (a + b) >> 1; if (grp[m].y > c0) b = m; else a = m + 1; }
+    const int64_t gf = a;
+    a = 0; b = gact;                         // first group with L >= c1
+    while (a < b) { const int64_t m = (a + b) >> 1; if (grp[m].x >= c1) b = m; else a = m + 1; }
+    const int64_t gend = a;
+    cnt[c] = gend > gf ? (uint32_t)(gend - gf) : 0u;
+    gfirst[c] = (uint32_t)gf;
+}
+
+// Item i: its chunk by binary search over the scanned counts, its group by
+// offset inside the chunk's run. Column-chunk-major order: the items in
+// flight at any moment share a few column chunks, which then stay resident
+// in each XCD's L2.
+__global__ void k_emit_items(const uint4 *__restrict__ grp, const uint32_t *__restrict__ chunkoff,
+                             const uint32_t *__restrict__ gfirst, int64_t NC,
+                             const uint32_t *__restrict__ total, int64_t max_items,
                              WorkItem *__restrict__ items)
 {
-    const int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gi >= G) return;
-    const uint4 gb = grp[gi];
-    for (uint32_t c = gb.x / kChunk; c * kChunk < gb.y; ++c) {
-        const uint32_t pos = chunkoff[c] + atomicAdd(&chunkfill[c], 1u);
-        WorkItem w;
-        w.grp = (uint32_t)gi;
-        w.c0 = max(c * kChunk, gb.x);
-        w.c1 = min((c + 1) * kChunk, gb.y);
-        w.pad = 0;
-        items[pos] = w;
-    }
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= max_items || i >= (int64_t)*total) return;
+    int64_t a = 0, b = NC;                   // last c with chunkoff[c] <= i
+    while (b - a > 1) { const int64_t m = (a + b) >> 1; if (chunkoff[m] <= (uint32_t)i) a = m; else b = m; }
+    const int64_t c = a;
+    const uint32_t g = gfirst[c] + (uint32_t)(i - chunkoff[c]);
+    const uint4 gb = grp[g];
+    WorkItem w;
+    w.grp = g;
+    w.c0 = max((uint32_t)c * kChunk, gb.x);
+    w.c1 = min((uint32_t)(c + 1) * kChunk, gb.y);
+    w.pad = 0;
+    items[i] = w;
 }
 
 // ------------------------------------------------------------ MFMA search
@@ -342,6 +402,7 @@ template <int B> struct WaveState {
     u64 best[Cfg<B>::MW];
     uint32_t grp;
     u64 survivors;
+    u64 screened;
 };
 
 // Exact treatment of the elements of one column block that passed the screen.
@@ -398,45 +459,89 @@ __device__ __forceinline__ void take_survivors(const SearchArgs &a, WaveState<B>
 }
 
 template <int B, bool MASK>
+__device__ __forceinline__ void screen_block(const SearchArgs &a, WaveState<B> &st,
+                                             const typename WaveState<B>::frag_t (&bf)[Cfg<B>::KS],
+                                             float u, int cb)
+{
+    using C = Cfg<B>;
+    constexpr int n = C::n, MW = C::MW, NCH = C::NCH, KPC = C::KS / NCH;
+    const float slack = n / 4.0f + (NCH > 1 ? 64.0f : 0.0f);
+    const int col = threadIdx.x & 15;
+    float4_t acc[MW][NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c)
+#pragma unroll
+        for (int kk = 0; kk < KPC; ++kk)
+#pragma unroll
+            for (int b = 0; b < MW; ++b) {
+                const float4_t z = {0.f, 0.f, 0.f, 0.f};
+                acc[b][c] = mma(st.af[b][c * KPC + kk], bf[c * KPC + kk], kk ? acc[b][c] : z);
+            }
+    bool hit = false;
+#pragma unroll
+    for (int b = 0; b < MW; ++b) {
+        float4_t sv = acc[b][0];
+#pragma unroll
+        for (int c = 1; c < NCH; ++c) sv += acc[b][c];
+        const float m = fmaxf(fmaxf(fabsf(sv[0]), fabsf(sv[1])), fmaxf(fabsf(sv[2]), fabsf(sv[3])));
+        bool h = m >= fmaf(st.T[b], u, -slack);
+        if (MASK) {
+            const uint32_t p = (uint32_t)cb * 16 + col;
+            h = h && p >= st.lo[b] && p < st.hi[b];
+        }
+        hit = hit || h;
+    }
+    if (__any(hit)) take_survivors<B, MASK>(a, st, acc, cb, u, slack);
+}
+
+// Column blocks [cb_begin, cb_end) against the wave's A rows. The B
+// fragments and u of the block two ahead are loaded while a block computes.
+template <int B, bool MASK>
 __device__ __forceinline__ void scan_blocks(const SearchArgs &a, WaveState<B> &st, int cb_begin,
                                             int cb_end)
 {
     using C = Cfg<B>;
-    constexpr int n = C::n, KS = C::KS, MW = C::MW, NCH = C::NCH, KPC = KS / NCH;
+    constexpr int KS = C::KS;
     typedef typename WaveState<B>::frag_t frag_t;
-    const float slack = n / 4.0f + (NCH > 1 ? 64.0f : 0.0f);
+    if (cb_begin >= cb_end) return;
     const int lane = threadIdx.x & 63, col = lane & 15;
     const frag_t *bbase = (const frag_t *)a.Bm + lane;
-    for (int cb = cb_begin; cb < cb_end; ++cb) {
-        frag_t bf[KS];
+    const int last = cb_end - 1;
+    frag_t b0[KS], b1[KS];
+    float u0, u1;
+    {
+        const int c1 = min(cb_begin + 1, last);
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) bf[ks] = bbase[((int64_t)cb * KS + ks) * 64];
-        const float u = a.u[cb * 16 + col];
-        float4_t acc[MW][NCH];
-#pragma unroll
-        for (int b = 0; b < MW; ++b)
-#pragma unroll
-            for (int c = 0; c < NCH; ++c) {
-                float4_t z = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int kk = 0; kk < KPC; ++kk) z = mma(st.af[b][c * KPC + kk], bf[c * KPC + kk], z);
-                acc[b][c] = z;
-            }
-        bool hit = false;
-#pragma unroll
-        for (int b = 0; b < MW; ++b) {
-            float4_t s = acc[b][0];
-#pragma unroll
-            for (int c = 1; c < NCH; ++c) s += acc[b][c];
-            const float m = fmaxf(fmaxf(fabsf(s[0]), fabsf(s[1])), fmaxf(fabsf(s[2]), fabsf(s[3])));
-            bool h = m >= fmaf(st.T[b], u, -slack);
-            if (MASK) {
-                const uint32_t p = (uint32_t)cb * 16 + col;
-                h = h && p >= st.lo[b] && p < st.hi[b];
-            }
-            hit = hit || h;
+        for (int ks = 0; ks < KS; ++ks) {
+            b0[ks] = bbase[((int64_t)cb_begin * KS + ks) * 64];
+            b1[ks] = bbase[((int64_t)c1 * KS + ks) * 64];
         }
-        if (__any(hit)) take_survivors<B, MASK>(a, st, acc, cb, u, slack);
+        u0 = a.u[cb_begin * 16 + col];
+        u1 = a.u[c1 * 16 + col];
+    }
+    for (int cb = cb_begin; cb < cb_end; cb += 2) {
+        {
+            frag_t bc[KS];
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) bc[ks] = b0[ks];
+            const float uc = u0;
+            const int nx = min(cb + 2, last);
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) b0[ks] = bbase[((int64_t)nx * KS + ks) * 64];
+            u0 = a.u[nx * 16 + col];
+            screen_block<B, MASK>(a, st, bc, uc, cb);
+        }
+        if (cb + 1 < cb_end) {
+            frag_t bc[KS];
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) bc[ks] = b1[ks];
+            const float uc = u1;
+            const int nx = min(cb + 3, last);
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) b1[ks] = bbase[((int64_t)nx * KS + ks) * 64];
+            u1 = a.u[nx * 16 + col];
+            screen_block<B, MASK>(a, st, bc, uc, cb + 1);
+        }
     }
 }
 
@@ -450,6 +555,7 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma(SearchArgs a)
     const uint32_t nitems = *a.n_items;
     WaveState<B> st;
     st.survivors = 0;
+    st.screened = 0;
     u64 items_done = 0;
     for (;;) {
         uint32_t item = 0;
@@ -481,6 +587,7 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma(SearchArgs a)
         int ib0 = (int)((gb.z + 15u) >> 4), ib1 = (int)(gb.w >> 4);
         ib0 = min(max(ib0, cb0), cb1);
         ib1 = max(min(ib1, cb1), ib0);
+        st.screened += (u64)(cb1 - cb0) * 16 * GR * 8;
         scan_blocks<B, true>(a, st, cb0, ib0);
         scan_blocks<B, false>(a, st, ib0, ib1);
         scan_blocks<B, true>(a, st, ib1, cb1);
@@ -497,6 +604,7 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma(SearchArgs a)
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) sv += __shfl_xor(sv, off);
         if (lane == 0) {
+            atomicAdd(&a.counters[0], st.screened);
             atomicAdd(&a.counters[1], sv);
             atomicAdd(&a.counters[2], items_done);
         }
@@ -630,7 +738,7 @@ inline unsigned blocks_for(int64_t n, int th) { return (unsigned)((n + th - 1) /
 template <int B>
 hipError_t run_encode_b(const EncodePlan &p, const uint8_t *img, const uint32_t *perm,
                         const uint32_t *lo, const uint32_t *hi, int kernel, fic_code *codes,
-                        void *ws, int num_cu, u64 *counters, hipStream_t s)
+                        void *ws, int num_cu, u64 *counters, hipStream_t s, const Tracer *tr)
 {
     using C = Cfg<B>;
     const Geom &g = p.g;
@@ -639,17 +747,23 @@ hipError_t run_encode_b(const EncodePlan &p, const uint8_t *img, const uint32_t 
     const int th = 256;
     if (kernel == FIC_KERNEL_PLAIN) {
         uint16_t *S = (uint16_t *)(w + p.off_S);
+        trace(tr, FIC_STAGE_DOMAIN_PREP, 1, s);
         hipLaunchKernelGGL(k_box2x2, dim3(blocks_for((int64_t)(g.h - 1) * (g.w - 1), th)), dim3(th),
                            0, s, img, g.h, g.w, g.pitch, S);
         hipLaunchKernelGGL(k_fill_u64, dim3(blocks_for(g.R, th)), dim3(th), 0, s, keys, g.R, kNoKey);
+        trace(tr, FIC_STAGE_DOMAIN_PREP, 0, s);
+        trace(tr, FIC_STAGE_SEARCH, 1, s);
         const unsigned gx = blocks_for(p.Dp, 32);
         for (int64_t r0 = 0; r0 < g.R; r0 += 65535) {
             const unsigned gy = (unsigned)(g.R - r0 < 65535 ? g.R - r0 : 65535);
             hipLaunchKernelGGL(k_search_plain<B>, dim3(gx, gy), dim3(256), 0, s, img, g, S, perm, lo,
                                hi, r0, p.shift, keys);
         }
+        trace(tr, FIC_STAGE_SEARCH, 0, s);
+        trace(tr, FIC_STAGE_FINAL, 1, s);
         hipLaunchKernelGGL(k_finalize<B>, dim3(blocks_for(g.R, th)), dim3(th), 0, s, img, g,
                            (const uint32_t *)nullptr, keys, p.shift, codes);
+        trace(tr, FIC_STAGE_FINAL, 0, s);
         return hipGetLastError();
     }
 
@@ -668,33 +782,39 @@ hipError_t run_encode_b(const EncodePlan &p, const uint8_t *img, const uint32_t 
     uint4 *grp = (uint4 *)(w + p.off_grp);
     uint32_t *bmin = (uint32_t *)(w + p.off_bmin);
 
+    trace(tr, FIC_STAGE_RANGE_PREP, 1, s);
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, ctr, (int64_t)64, 0u);
-    hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(p.NC, th)), dim3(th), 0, s, chunkcnt, p.NC, 0u);
-    hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(p.NC, th)), dim3(th), 0, s, chunkfill, p.NC, 0u);
-
-    const uint32_t *ord = nullptr;
-    if (p.pooled) {
+    {
+        int dbits = 1;
+        while (((int64_t)1 << dbits) <= g.D) ++dbits;
         u64 *sk = (u64 *)(w + p.off_sortkeys);
-        hipLaunchKernelGGL(k_range_sortkeys, dim3(blocks_for(g.R, th)), dim3(th), 0, s, lo, g.R, sk,
-                           order);
-        hipError_t e = radix_sort_pairs(sk, order, g.R, 32, w + p.off_sort, s);
+        hipLaunchKernelGGL(k_range_keys<B>, dim3(blocks_for(g.R, th)), dim3(th), 0, s, img, g.pitch,
+                           g.rcols, g.R, lo, hi, (uint32_t)g.D, dbits, sk, order);
+        hipError_t e = radix_sort_pairs(sk, order, g.R, p.pooled ? 2 * dbits : 8, w + p.off_sort, s);
         if (e != hipSuccess) return e;
-        ord = order;
+    }
+    const uint32_t *ord = order;
+    if (p.pooled)
         hipLaunchKernelGGL(k_blockmin, dim3(blocks_for((g.D + kBminBlock - 1) / kBminBlock * 64, th)),
                            dim3(th), 0, s, perm, g.D, bmin);
-    }
     hipLaunchKernelGGL(k_range_prep<B>, dim3(blocks_for(p.Rp * 8, th)), dim3(th), 0, s, img, g.pitch,
                        g.rcols, g.R, p.Rp, ord, lo, hi, (uint32_t)g.D, A, rs);
+    trace(tr, FIC_STAGE_RANGE_PREP, 0, s);
+    trace(tr, FIC_STAGE_DOMAIN_PREP, 1, s);
     hipLaunchKernelGGL(k_domain_prep<B>, dim3(blocks_for(p.Dp * B, th)), dim3(th), 0, s, img,
                        g.pitch, g.dcols, g.t, perm, g.D, p.Dp, Bm, u, eps, sdd, dom);
-    hipLaunchKernelGGL(k_seed<B>, dim3(blocks_for(p.Rp, th)), dim3(th), 0, s, img, g, rs, p.Rp,
-                       perm, bmin, p.shift, keys, counters);
+    trace(tr, FIC_STAGE_DOMAIN_PREP, 0, s);
+    trace(tr, FIC_STAGE_WORKLIST, 1, s);
+    hipLaunchKernelGGL(k_seed<B>, dim3(blocks_for(p.Rp * 64, th)), dim3(th), 0, s, A, Bm, rs, eps,
+                       sdd, dom, p.Rp, perm, bmin, p.shift, keys, counters);
     hipLaunchKernelGGL(k_group_bounds, dim3(blocks_for(p.G, th)), dim3(th), 0, s, rs, p.G,
-                       (int)p.GR, grp, chunkcnt);
+                       (int)p.GR, (uint32_t)p.Dp, grp);
+    hipLaunchKernelGGL(k_chunk_span, dim3(blocks_for(p.NC, th)), dim3(th), 0, s, grp, p.G, p.NC,
+                       chunkcnt, chunkfill);
     // exclusive scan of the per-chunk counts; the total is the item count
-    scan_u32(chunkcnt, p.NC, ctr + 1, s);
-    hipLaunchKernelGGL(k_emit_items, dim3(blocks_for(p.G, th)), dim3(th), 0, s, grp, p.G, chunkcnt,
-                       chunkfill, items);
+    scan_u32(chunkcnt, p.NC, ctr + 1, w + p.off_scan, s);
+    hipLaunchKernelGGL(k_emit_items, dim3(blocks_for(p.max_items, th)), dim3(th), 0, s, grp,
+                       chunkcnt, chunkfill, p.NC, ctr + 1, p.max_items, items);
     SearchArgs a;
     a.A = A; a.Bm = Bm; a.u = u; a.eps = eps; a.sdd = sdd; a.dom = dom; a.rs = rs; a.grp = grp;
     a.items = items; a.n_items = ctr + 1; a.item_ctr = ctr; a.keys = keys; a.counters = counters;
@@ -705,9 +825,14 @@ hipError_t run_encode_b(const EncodePlan &p, const uint8_t *img, const uint32_t 
             &per_cu, reinterpret_cast<const void *>(&k_search_mfma<B>), 256, 0) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
+    trace(tr, FIC_STAGE_WORKLIST, 0, s);
+    trace(tr, FIC_STAGE_SEARCH, 1, s);
     hipLaunchKernelGGL(k_search_mfma<B>, dim3(per_cu * num_cu), dim3(256), 0, s, a);
+    trace(tr, FIC_STAGE_SEARCH, 0, s);
+    trace(tr, FIC_STAGE_FINAL, 1, s);
     hipLaunchKernelGGL(k_finalize<B>, dim3(blocks_for(g.R, th)), dim3(th), 0, s, img, g, ord, keys,
                        p.shift, codes);
+    trace(tr, FIC_STAGE_FINAL, 0, s);
     return hipGetLastError();
 }
 
@@ -748,17 +873,18 @@ void plan_encode(const Geom &g, int pooled, EncodePlan &p)
     p.off_S = take((size_t)(g.h - 1) * (g.w - 1) * 2);
     p.off_sortkeys = take((size_t)p.Rp * 8);
     p.off_sort = take(sort_ws_bytes(p.Rp));
+    p.off_scan = take(scan_ws_bytes(p.NC));
     p.total = o;
 }
 
 hipError_t run_encode(const EncodePlan &p, const uint8_t *img, const uint32_t *perm,
                       const uint32_t *lo, const uint32_t *hi, int kernel, fic_code *codes,
-                      void *ws, int num_cu, u64 *counters, hipStream_t s)
+                      void *ws, int num_cu, u64 *counters, hipStream_t s, const Tracer *tr)
 {
     switch (p.g.b) {
-    case 4: return run_encode_b<4>(p, img, perm, lo, hi, kernel, codes, ws, num_cu, counters, s);
-    case 8: return run_encode_b<8>(p, img, perm, lo, hi, kernel, codes, ws, num_cu, counters, s);
-    case 16: return run_encode_b<16>(p, img, perm, lo, hi, kernel, codes, ws, num_cu, counters, s);
+    case 4: return run_encode_b<4>(p, img, perm, lo, hi, kernel, codes, ws, num_cu, counters, s, tr);
+    case 8: return run_encode_b<8>(p, img, perm, lo, hi, kernel, codes, ws, num_cu, counters, s, tr);
+    case 16: return run_encode_b<16>(p, img, perm, lo, hi, kernel, codes, ws, num_cu, counters, s, tr);
     default: return hipErrorInvalidValue;
     }
 }

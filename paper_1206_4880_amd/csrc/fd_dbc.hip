@@ -134,15 +134,19 @@ hipError_t launch_m(const uint8_t *img, int32_t h, int32_t w, int32_t pitch, int
 
 hipError_t launch_fd_classify(const uint8_t *img, int32_t h, int32_t w, int32_t pitch,
                               int32_t block, int32_t step, double *fd64, float *fd32,
-                              hipStream_t s)
+                              hipStream_t s, const Tracer *tr)
 {
+    hipError_t e;
+    trace(tr, FIC_STAGE_CLASSIFY, 1, s);
     switch (block) {
-    case 4: return launch_m<4>(img, h, w, pitch, step, fd64, fd32, s);
-    case 8: return launch_m<8>(img, h, w, pitch, step, fd64, fd32, s);
-    case 16: return launch_m<16>(img, h, w, pitch, step, fd64, fd32, s);
-    case 32: return launch_m<32>(img, h, w, pitch, step, fd64, fd32, s);
-    default: return hipErrorInvalidValue;
+    case 4: e = launch_m<4>(img, h, w, pitch, step, fd64, fd32, s); break;
+    case 8: e = launch_m<8>(img, h, w, pitch, step, fd64, fd32, s); break;
+    case 16: e = launch_m<16>(img, h, w, pitch, step, fd64, fd32, s); break;
+    case 32: e = launch_m<32>(img, h, w, pitch, step, fd64, fd32, s); break;
+    default: e = hipErrorInvalidValue; break;
     }
+    trace(tr, FIC_STAGE_CLASSIFY, 0, s);
+    return e;
 }
 
 }  // namespace fic

@@ -131,6 +131,18 @@ __device__ inline float screen_u(int64_t sdd, int n)
 }
 
 // ---------------------------------------------------------------------------
+// Stage tracing hook: the C ABI passes a recorder that puts HIP events around
+// each stage on the stream; nullptr disables it.
+struct Tracer {
+    void *self;
+    void (*mark)(void *self, int stage, int begin, hipStream_t s);
+};
+inline void trace(const Tracer *t, int stage, int begin, hipStream_t s)
+{
+    if (t) t->mark(t->self, stage, begin, s);
+}
+
+// ---------------------------------------------------------------------------
 // Launch wrappers (each .hip file owns its kernels).
 struct Geom {
     int32_t h, w, pitch, b, t;
@@ -141,16 +153,17 @@ struct Geom {
 // DBC fractal dimension (fd_dbc.hip)
 hipError_t launch_fd_classify(const uint8_t *img, int32_t h, int32_t w, int32_t pitch,
                               int32_t block, int32_t step, double *fd64, float *fd32,
-                              hipStream_t s);
+                              hipStream_t s, const Tracer *tr = nullptr);
 
 // radix sort + pool (pool.hip)
 size_t sort_ws_bytes(int64_t n);
 hipError_t radix_sort_pairs(u64 *keys, uint32_t *vals, int64_t n, int key_bits, void *ws,
                             hipStream_t s);
-hipError_t scan_u32(uint32_t *a, int64_t m, uint32_t *total, hipStream_t s);
+size_t scan_ws_bytes(int64_t m);
+hipError_t scan_u32(uint32_t *a, int64_t m, uint32_t *total, void *ws, hipStream_t s);
 hipError_t launch_pool(const double *fd_range, int32_t nr, const double *fd_dom, int32_t nd,
                        double tol, uint32_t *perm, uint32_t *lo, uint32_t *hi, void *ws,
-                       hipStream_t s);
+                       hipStream_t s, const Tracer *tr = nullptr);
 
 // encode (encode.hip)
 struct EncodePlan {
@@ -161,18 +174,19 @@ struct EncodePlan {
     int64_t max_items;
     size_t off_A, off_rs, off_order, off_B, off_u, off_eps, off_sdd, off_dom, off_keys,
         off_items, off_ctr, off_chunkcnt, off_chunkfill, off_grp, off_bmin, off_S, off_sort,
-        off_sortkeys, total;
+        off_sortkeys, off_scan, total;
 };
 void plan_encode(const Geom &g, int pooled, EncodePlan &p);
 hipError_t run_encode(const EncodePlan &p, const uint8_t *img, const uint32_t *perm,
                       const uint32_t *lo, const uint32_t *hi, int kernel, fic_code *codes,
-                      void *ws, int num_cu, u64 *counters, hipStream_t s);
+                      void *ws, int num_cu, u64 *counters, hipStream_t s,
+                      const Tracer *tr = nullptr);
 
 // decode (decode.hip)
 size_t decode_ws_bytes(const Geom &g);
 int32_t decode_max_iters();
 hipError_t run_decode(const Geom &g, const fic_code *codes, int32_t max_iters,
                       const uint8_t *init, uint8_t *out, void *ws, int32_t *iters,
-                      hipStream_t s);
+                      hipStream_t s, const Tracer *tr = nullptr);
 
 }  // namespace fic

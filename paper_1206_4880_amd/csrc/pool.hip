@@ -39,30 +39,79 @@ __global__ __launch_bounds__(kSortThreads) void k_digit_hist(const u64 *__restri
     hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
-// Exclusive scan of m entries, one block of 1024 threads.
-__global__ __launch_bounds__(1024) void k_scan_u32(uint32_t *__restrict__ a, int64_t m,
-                                                    uint32_t *__restrict__ total)
+// Exclusive scan of m uint32 entries in three launches: per-tile scans of
+// kScanTile entries, a scan of the tile totals, and the carry-in add.
+constexpr int kScanThreads = 256;
+constexpr int kScanPer = 16;
+constexpr int kScanTile = kScanThreads * kScanPer;
+
+__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t *sh, uint32_t &total)
 {
-    __shared__ uint32_t part[1024];
-    const int64_t per = (m + 1023) / 1024;
-    const int64_t b = threadIdx.x * per, e = min(m, b + per);
-    uint32_t s = 0;
-    for (int64_t i = b; i < e; ++i) s += a[i];
-    part[threadIdx.x] = s;
+    // inclusive scan inside each wave, then across the 4 wave totals
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) sh[wave] = x;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        uint32_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
-        __syncthreads();
-        part[threadIdx.x] += v;
-        __syncthreads();
+    uint32_t base = 0;
+    for (int w = 0; w < wave; ++w) base += sh[w];
+    total = sh[0] + sh[1] + sh[2] + sh[3];
+    __syncthreads();
+    return base + x - v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_tiles(uint32_t *__restrict__ a, int64_t m,
+                                                             uint32_t *__restrict__ tile_tot)
+{
+    __shared__ uint32_t sh[4];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
+    uint32_t v[kScanPer];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int i = 0; i < kScanPer; ++i) {
+        v[i] = base + i < m ? a[base + i] : 0u;
+        sum += v[i];
     }
-    uint32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0u;
-    for (int64_t i = b; i < e; ++i) {
-        uint32_t v = a[i];
-        a[i] = run;
-        run += v;
+    uint32_t total;
+    uint32_t run = block_exclusive_scan(sum, sh, total);
+#pragma unroll
+    for (int i = 0; i < kScanPer; ++i) {
+        if (base + i < m) a[base + i] = run;
+        run += v[i];
     }
-    if (total && threadIdx.x == 1023) *total = part[1023];
+    if (threadIdx.x == 0) tile_tot[blockIdx.x] = total;
+}
+
+// Scan of the tile totals (one block, any count), total to *total.
+__global__ __launch_bounds__(kScanThreads) void k_scan_totals(uint32_t *__restrict__ t, int64_t nt,
+                                                              uint32_t *__restrict__ total)
+{
+    __shared__ uint32_t sh[4];
+    uint32_t carry = 0;
+    for (int64_t b = 0; b < nt; b += kScanThreads) {
+        const int64_t i = b + threadIdx.x;
+        const uint32_t v = i < nt ? t[i] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_exclusive_scan(v, sh, tot);
+        if (i < nt) t[i] = carry + ex;
+        carry += tot;
+    }
+    if (total && threadIdx.x == 0) *total = carry;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_add(uint32_t *__restrict__ a, int64_t m,
+                                                           const uint32_t *__restrict__ tile_off)
+{
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
+    const uint32_t off = tile_off[blockIdx.x];
+    if (blockIdx.x == 0) return;
+#pragma unroll
+    for (int i = 0; i < kScanPer; ++i)
+        if (base + i < m) a[base + i] += off;
 }
 
 __global__ __launch_bounds__(kSortThreads) void k_digit_scatter(
@@ -193,11 +242,26 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
 
+size_t scan_ws_bytes(int64_t m) { return align256((size_t)((m + kScanTile - 1) / kScanTile + 1) * 4); }
+
 size_t sort_ws_bytes(int64_t n)
 {
     int64_t nb = (n + kSortTile - 1) / kSortTile;
     if (nb < 1) nb = 1;
-    return align256((size_t)n * 8) + align256((size_t)n * 4) + align256((size_t)nb * 256 * 4) + 256;
+    return align256((size_t)n * 8) + align256((size_t)n * 4) + align256((size_t)nb * 256 * 4) +
+           scan_ws_bytes(nb * 256) + 256;
+}
+
+hipError_t scan_u32(uint32_t *a, int64_t m, uint32_t *total, void *ws, hipStream_t s)
+{
+    const int64_t nt = (m + kScanTile - 1) / kScanTile;
+    uint32_t *tt = (uint32_t *)ws;
+    if (nt > 0)
+        hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nt), dim3(kScanThreads), 0, s, a, m, tt);
+    hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kScanThreads), 0, s, tt, nt, total);
+    if (nt > 1)
+        hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nt), dim3(kScanThreads), 0, s, a, m, tt);
+    return hipGetLastError();
 }
 
 hipError_t radix_sort_pairs(u64 *keys, uint32_t *vals, int64_t n, int key_bits, void *ws,
@@ -208,15 +272,15 @@ hipError_t radix_sort_pairs(u64 *keys, uint32_t *vals, int64_t n, int key_bits, 
     char *p = (char *)ws;
     u64 *kalt = (u64 *)p;                 p += align256((size_t)n * 8);
     uint32_t *valt = (uint32_t *)p;       p += align256((size_t)n * 4);
-    uint32_t *hist = (uint32_t *)p;
+    uint32_t *hist = (uint32_t *)p;       p += align256((size_t)nb * 256 * 4);
+    void *scanws = p;
     const int passes = (key_bits + 7) / 8;
     u64 *ka = keys, *kb = kalt;
     uint32_t *va = vals, *vb = valt;
     for (int pass = 0; pass < passes; ++pass) {
         const int shift = pass * 8;
         hipLaunchKernelGGL(k_digit_hist, dim3(nb), dim3(kSortThreads), 0, s, ka, n, shift, hist, nb);
-        hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, s, hist, (int64_t)nb * 256,
-                           (uint32_t *)nullptr);
+        scan_u32(hist, (int64_t)nb * 256, nullptr, scanws, s);
         hipLaunchKernelGGL(k_digit_scatter, dim3(nb), dim3(kSortThreads), 0, s, ka, va, kb, vb, n,
                            shift, hist, nb);
         u64 *tk = ka; ka = kb; kb = tk;
@@ -229,18 +293,13 @@ hipError_t radix_sort_pairs(u64 *keys, uint32_t *vals, int64_t n, int key_bits, 
     return hipGetLastError();
 }
 
-hipError_t scan_u32(uint32_t *a, int64_t m, uint32_t *total, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, s, a, m, total);
-    return hipGetLastError();
-}
-
 // Pool workspace: sort keys (n_domain u64), sorted fd (n_domain f64),
 // tol (f64), sort scratch.
 hipError_t launch_pool(const double *fd_range, int32_t nr, const double *fd_dom, int32_t nd,
                        double tol, uint32_t *perm, uint32_t *lo, uint32_t *hi, void *ws,
-                       hipStream_t s)
+                       hipStream_t s, const Tracer *tr)
 {
+    trace(tr, FIC_STAGE_POOL, 1, s);
     char *p = (char *)ws;
     u64 *keys = (u64 *)p;          p += align256((size_t)nd * 8);
     double *fds = (double *)p;     p += align256((size_t)nd * 8);
@@ -256,6 +315,7 @@ hipError_t launch_pool(const double *fd_range, int32_t nr, const double *fd_dom,
                        (int64_t)nd, fds);
     hipLaunchKernelGGL(k_bounds, dim3((nr + th - 1) / th), dim3(th), 0, s, fd_range, nr, fds, nd,
                        tol_eff, lo, hi);
+    trace(tr, FIC_STAGE_POOL, 0, s);
     return hipGetLastError();
 }
 

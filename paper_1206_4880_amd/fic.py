@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libfic.so")
 
 OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_CAPACITY, ERR_DEVICE = range(6)
 KERNEL_MFMA, KERNEL_PLAIN = 0, 1
+STAGES = ("classify", "pool", "range_prep", "domain_prep", "worklist", "search", "final", "decode")
 CODE_DTYPE = np.dtype([("domain", "<u4"), ("iso", "u1"), ("s_idx", "i1"), ("o_idx", "u1"),
                        ("flags", "u1"), ("err", "<i8")])
 assert CODE_DTYPE.itemsize == 16
@@ -57,6 +58,8 @@ def lib():
         "fic_destroy": (_st, [_vp]),
         "fic_status_string": (ctypes.c_char_p, [_st]),
         "fic_set_counters": (_st, [_vp, _vp]),
+        "fic_timing_enable": (_st, [_vp, _i32]),
+        "fic_timing_read": (_st, [_vp, _vp, _vp, _i32, ctypes.POINTER(_i32)]),
         "fic_num_ranges": (ctypes.c_int64, [ctypes.POINTER(Geom)]),
         "fic_num_domains": (ctypes.c_int64, [ctypes.POINTER(Geom)]),
         "fic_fd_classify": (_st, [_vp, _vp, ctypes.POINTER(Geom), _i32, _i32, _vp, _vp, _vp]),
@@ -82,6 +85,7 @@ def lib():
 
 
 EXPORTED = ("fic_create", "fic_destroy", "fic_status_string", "fic_set_counters",
+            "fic_timing_enable", "fic_timing_read",
             "fic_num_ranges", "fic_num_domains", "fic_fd_classify", "fic_pool_workspace_bytes",
             "fic_build_domain_pool", "fic_encode_workspace_bytes", "fic_encode_pifs",
             "fic_batch_workspace_bytes", "fic_encode_pifs_batch", "fic_decode_workspace_bytes",
@@ -125,6 +129,20 @@ class Context:
             self.close()
         except Exception:  # noqa: BLE001 - interpreter shutdown
             pass
+
+    def timing(self, enable=True):
+        _check(lib().fic_timing_enable(self.handle, 1 if enable else 0), "fic_timing_enable")
+
+    def timing_read(self):
+        """[(stage, ms)] of the stages recorded since timing(True) (waits)."""
+        cnt = _i32(0)
+        _check(lib().fic_timing_read(self.handle, None, None, 0, ctypes.byref(cnt)),
+               "fic_timing_read")
+        n = cnt.value
+        st = (ctypes.c_int32 * max(n, 1))()
+        ms = (ctypes.c_float * max(n, 1))()
+        _check(lib().fic_timing_read(self.handle, st, ms, n, ctypes.byref(cnt)), "fic_timing_read")
+        return [(STAGES[st[i]], float(ms[i])) for i in range(min(n, cnt.value))]
 
     def set_counters(self, counters):
         ptr = counters.data_ptr() if counters is not None else None
