@@ -61,6 +61,10 @@ def parse():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-kernel comparison")
     ap.add_argument("--counters", action="store_true",
                     help="one extra untimed step with survivor counters")
+    ap.add_argument("--only", default=None,
+                    help="run only this job per step (e.g. 'exhaustive'), for profiling")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="only run a device copy of this many MiB (counter calibration)")
     return ap.parse_args()
 
 
@@ -78,12 +82,27 @@ def main():
     import paper_1206_4880_amd as fic
     from synth import WORKLOADS, workload_images
 
+    if args.copy_mib:
+        nbytes = args.copy_mib << 20
+        src = torch.randint(0, 255, (nbytes,), dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": nbytes}))
+        return
+
     wl = WORKLOADS[args.workload]
     img_np = workload_images(args.workload)
     dev = torch.device("cuda:0")
     img = torch.from_numpy(img_np).to(dev)
     H, W = img_np.shape
     jobs = list(wl.jobs)
+    if args.only:
+        jobs = [j for j in jobs if (("exhaustive" if j[2] is None else "pool_%g" % j[2])
+                                    == args.only)]
+        if not jobs:
+            raise SystemExit("no job named %s in %s" % (args.only, wl.name))
     b0, t0 = jobs[0][0], jobs[0][1]
     if any((b, t) != (b0, t0) for (b, t, _) in jobs):
         raise SystemExit("bench workloads share one range size and step per image")
