@@ -122,6 +122,7 @@ fic_status fic_set_counters(fic_ctx *ctx, uint64_t *counters /* dev */);
      FIC_STAGE_SEARCH      the search kernel itself (MFMA or plain)
      FIC_STAGE_FINAL       finalize (codes)
      FIC_STAGE_DECODE      all decoding sweeps
+     FIC_STAGE_BATCH       a whole fic_encode_pifs_batch replayed as one graph
    fic_timing_enable(ctx, 1) clears the record and starts recording; 0 stops.
    fic_timing_read waits for the recorded events (host sync), then writes up
    to `capacity` (stage, milliseconds) pairs in record order (host arrays)
@@ -130,7 +131,7 @@ fic_status fic_set_counters(fic_ctx *ctx, uint64_t *counters /* dev */);
 enum {
     FIC_STAGE_CLASSIFY = 0, FIC_STAGE_POOL = 1, FIC_STAGE_RANGE_PREP = 2,
     FIC_STAGE_DOMAIN_PREP = 3, FIC_STAGE_WORKLIST = 4, FIC_STAGE_SEARCH = 5,
-    FIC_STAGE_FINAL = 6, FIC_STAGE_DECODE = 7
+    FIC_STAGE_FINAL = 6, FIC_STAGE_DECODE = 7, FIC_STAGE_BATCH = 8
 };
 fic_status fic_timing_enable(fic_ctx *ctx, int32_t enable);
 fic_status fic_timing_read(fic_ctx *ctx, int32_t *stages /* host */, float *ms /* host */,
@@ -196,17 +197,31 @@ fic_status fic_encode_pifs(fic_ctx *ctx, const uint8_t *img, const fic_geom *g,
                            void *ws, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
- * fic_encode_pifs_batch -- classify + pool + search for n_images images
- * (each its own geometry and tolerance) queued on one stream; the searches of
- * all images share one persistent work-queue launch per range size.
+ * fic_encode_pifs_batch -- the encoder of Sec. 1 - Sec. 3.1 (classify, pool
+ * when tol is finite or negative, search) for n_images images, each with its
+ * own geometry and tolerance. Every image is prepared on its own workspace
+ * part; then the searches of all images of one range size run as ONE
+ * persistent work-queue launch (items of all images in one queue, largest
+ * images first); then the codes are written.
  *   descs (host) fic_image_desc[n_images]; codes of image i go to
- *   descs[i].codes (dev).
- *   ws (dev) >= fic_batch_workspace_bytes(n_images, descs).
+ *         descs[i].codes (dev). Codes equal fic_encode_pifs on each image.
+ *   ws    (dev) >= fic_batch_workspace_bytes(n_images, descs) (the sum of
+ *         the images' parts plus a small header).
+ * Graphs (default on, see fic_set_batch_graph): the first call with given
+ * descriptors, workspace and counters records the whole batch as a HIP graph
+ * (captured on a stream of the context's own) and launches it on `stream`;
+ * later calls with the same descriptors, workspace and counters replay it.
+ * A replay reads the images' current contents. The context keeps the 4 most
+ * recently used graphs (host objects; no device memory is allocated).
+ * FIC_ERR_CAPACITY also when the batch could exceed 2^32 work items.
  * ---------------------------------------------------------------------- */
 size_t fic_batch_workspace_bytes(int32_t n_images, const fic_image_desc *descs);
 fic_status fic_encode_pifs_batch(fic_ctx *ctx, int32_t n_images,
                                  const fic_image_desc *descs,
                                  void *ws, size_t ws_bytes, void *stream);
+/* enable != 0 (the default): record and replay batch graphs as above;
+   0: enqueue every kernel of each call directly (and drop recorded graphs). */
+fic_status fic_set_batch_graph(fic_ctx *ctx, int32_t enable);
 
 /* ------------------------------------------------------------------------
  * fic_decode_pifs -- Sec. 1, decoding by iteration of the stored maps.

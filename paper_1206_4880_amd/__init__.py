@@ -6,8 +6,10 @@ The compute path is the HIP library ``libfic.so`` (C ABI in include/fic.h);
 is missing: there is no CPU fallback.
 """
 from . import fic  # noqa: F401
-from .fic import (CODE_DTYPE, Context, FicError, build_domain_pool, decode_pifs,  # noqa: F401
-                  encode, encode_batch, encode_pifs, fd_classify, unpack_codes)
+from .fic import (CODE_DTYPE, Context, FicError, batch_workspace_bytes,  # noqa: F401
+                  build_domain_pool, decode_pifs, encode, encode_batch, encode_pifs,
+                  fd_classify, unpack_codes)
 
-__all__ = ["fic", "CODE_DTYPE", "Context", "FicError", "build_domain_pool", "decode_pifs",
+__all__ = ["fic", "CODE_DTYPE", "Context", "FicError", "batch_workspace_bytes",
+           "build_domain_pool", "decode_pifs",
            "encode", "encode_batch", "encode_pifs", "fd_classify", "unpack_codes"]

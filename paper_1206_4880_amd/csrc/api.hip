@@ -27,6 +27,12 @@ struct fic_ctx {
     int open_stage;
     hipEvent_t open_ev;
     fic::Tracer tracer;
+    // batch graphs, keyed by the batch's descriptors, workspace and counters;
+    // most recently used last
+    struct Graph { std::vector<unsigned char> key; hipGraphExec_t exec; };
+    bool use_graph;
+    std::vector<Graph> graphs;
+    hipStream_t cap;     // capture stream, created with the first graph
 };
 
 namespace {
@@ -114,35 +120,54 @@ fic_status enter(fic_ctx *ctx)
     return hipSetDevice(ctx->device) == hipSuccess ? FIC_OK : FIC_ERR_DEVICE;
 }
 
-size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-size_t pool_ws(int64_t nr, int64_t nd)
+constexpr size_t kMaxGraphs = 4;
+
+template <class T> void put(std::vector<unsigned char> &k, const T &v)
 {
-    (void)nr;
-    return align256((size_t)nd * 8) * 2 + 256 + fic::sort_ws_bytes(nd);
+    const unsigned char *b = (const unsigned char *)&v;
+    k.insert(k.end(), b, b + sizeof(T));
 }
 
-// Per-image workspace of a batch: fd of ranges and domains, the pool, and
-// the search workspace.
-struct BatchPart {
-    size_t off_fdr, off_fdd, off_perm, off_lo, off_hi, off_pool, off_enc, total;
-};
-BatchPart batch_part(const Geom &g, bool pooled)
+// Identity of a batch call as far as its recorded graph is concerned: every
+// descriptor field, the workspace and the counters (field by field, so no
+// padding bytes enter the key).
+std::vector<unsigned char> batch_key(int32_t n, const fic_image_desc *d, const void *ws,
+                                     size_t ws_bytes, const u64 *counters)
 {
-    BatchPart b;
-    size_t o = 0;
-    auto take = [&](size_t n) { size_t r = o; o += align256(n); return r; };
-    b.off_fdr = take((size_t)g.R * 8);
-    b.off_fdd = take((size_t)g.D * 8);
-    b.off_perm = take((size_t)g.D * 4);
-    b.off_lo = take((size_t)g.R * 4);
-    b.off_hi = take((size_t)g.R * 4);
-    b.off_pool = take(pooled ? pool_ws(g.R, g.D) : 0);
-    fic::EncodePlan p;
-    fic::plan_encode(g, pooled ? 1 : 0, p);
-    b.off_enc = take(p.total);
-    b.total = o;
-    return b;
+    std::vector<unsigned char> k;
+    put(k, n);
+    for (int32_t i = 0; i < n; ++i) {
+        put(k, d[i].img);
+        put(k, d[i].geom.height); put(k, d[i].geom.width); put(k, d[i].geom.pitch);
+        put(k, d[i].geom.range_size); put(k, d[i].geom.domain_step);
+        put(k, d[i].tol);
+        put(k, d[i].codes);
+    }
+    put(k, ws);
+    put(k, ws_bytes);
+    put(k, counters);
+    return k;
+}
+
+void drop_graphs(fic_ctx *c)
+{
+    for (auto &g : c->graphs) hipGraphExecDestroy(g.exec);
+    c->graphs.clear();
+}
+
+bool batch_jobs(int32_t n, const fic_image_desc *descs, std::vector<fic::BatchJob> &jobs)
+{
+    jobs.resize(n);
+    for (int32_t i = 0; i < n; ++i) {
+        const fic_image_desc &d = descs[i];
+        jobs[i].img = d.img;
+        jobs[i].g = to_geom(&d.geom);
+        jobs[i].tol = d.tol;
+        jobs[i].pooled = isfinite(d.tol) || d.tol < 0;
+        jobs[i].codes = d.codes;
+    }
+    return true;
 }
 
 }  // namespace
@@ -177,6 +202,8 @@ fic_status fic_create(int32_t device, fic_ctx **out)
     c->open_ev = nullptr;
     c->tracer.self = c;
     c->tracer.mark = mark_stage;
+    c->use_graph = true;
+    c->cap = nullptr;
     if (device >= 0) {
         int n = 0;
         if (hipGetDeviceCount(&n) != hipSuccess || device >= n) {
@@ -193,6 +220,10 @@ fic_status fic_create(int32_t device, fic_ctx **out)
             return FIC_ERR_UNSUPPORTED;
         }
         c->num_cu = prop.multiProcessorCount;
+        if (hipSetDevice(device) != hipSuccess || fic::init_search_occupancy() != hipSuccess) {
+            delete c;
+            return FIC_ERR_DEVICE;
+        }
     }
     *out = c;
     return FIC_OK;
@@ -205,6 +236,8 @@ fic_status fic_destroy(fic_ctx *ctx)
         for (auto &r : ctx->recs) { hipEventDestroy(r.a); hipEventDestroy(r.b); }
         for (auto e : ctx->spare) hipEventDestroy(e);
         if (ctx->open_ev) hipEventDestroy(ctx->open_ev);
+        drop_graphs(ctx);
+        if (ctx->cap) hipStreamDestroy(ctx->cap);
     }
     delete ctx;
     return FIC_OK;
@@ -267,7 +300,7 @@ fic_status fic_fd_classify(fic_ctx *ctx, const uint8_t *img, const fic_geom *g, 
 size_t fic_pool_workspace_bytes(int64_t n_range, int64_t n_domain)
 {
     if (n_range < 0 || n_domain < 0) return 0;
-    return pool_ws(n_range, n_domain);
+    return fic::pool_ws_bytes(n_range, n_domain);
 }
 
 fic_status fic_build_domain_pool(fic_ctx *ctx, const double *fd_range, int32_t n_range,
@@ -277,7 +310,7 @@ fic_status fic_build_domain_pool(fic_ctx *ctx, const double *fd_range, int32_t n
 {
     if (!ctx || !fd_range || !fd_domain || !perm || !lo || !hi || !ws) return FIC_ERR_INVALID_ARG;
     if (n_range < 1 || n_domain < 1 || isnan(tol)) return FIC_ERR_INVALID_ARG;
-    if (ws_bytes < pool_ws(n_range, n_domain)) return FIC_ERR_WORKSPACE;
+    if (ws_bytes < fic::pool_ws_bytes(n_range, n_domain)) return FIC_ERR_WORKSPACE;
     fic_status st = enter(ctx);
     if (st != FIC_OK) return st;
     return dev_status(fic::launch_pool(fd_range, n_range, fd_domain, n_domain, tol, perm, lo, hi, ws,
@@ -315,14 +348,21 @@ fic_status fic_encode_pifs(fic_ctx *ctx, const uint8_t *img, const fic_geom *g,
 size_t fic_batch_workspace_bytes(int32_t n_images, const fic_image_desc *descs)
 {
     if (n_images < 1 || !descs) return 0;
-    size_t mx = 0;
-    for (int i = 0; i < n_images; ++i) {
+    for (int32_t i = 0; i < n_images; ++i)
         if (!geom_ok(&descs[i].geom)) return 0;
-        const bool pooled = isfinite(descs[i].tol) || descs[i].tol < 0;
-        const size_t b = batch_part(to_geom(&descs[i].geom), pooled).total;
-        mx = b > mx ? b : mx;
-    }
-    return mx;
+    std::vector<fic::BatchJob> jobs;
+    batch_jobs(n_images, descs, jobs);
+    fic::BatchPlan bp;
+    fic::plan_batch(jobs.data(), n_images, bp);
+    return bp.total;
+}
+
+fic_status fic_set_batch_graph(fic_ctx *ctx, int32_t enable)
+{
+    if (!ctx) return FIC_ERR_INVALID_ARG;
+    ctx->use_graph = enable != 0;
+    if (!ctx->use_graph && ctx->device >= 0 && enter(ctx) == FIC_OK) drop_graphs(ctx);
+    return FIC_OK;
 }
 
 fic_status fic_encode_pifs_batch(fic_ctx *ctx, int32_t n_images, const fic_image_desc *descs,
@@ -334,43 +374,55 @@ fic_status fic_encode_pifs_batch(fic_ctx *ctx, int32_t n_images, const fic_image
         if (!d.img || !d.codes || !geom_ok(&d.geom) || isnan(d.tol)) return FIC_ERR_INVALID_ARG;
         if (!key_fits(to_geom(&d.geom))) return FIC_ERR_CAPACITY;
     }
-    if (ws_bytes < fic_batch_workspace_bytes(n_images, descs)) return FIC_ERR_WORKSPACE;
+    std::vector<fic::BatchJob> jobs;
+    batch_jobs(n_images, descs, jobs);
+    fic::BatchPlan bp;
+    fic::plan_batch(jobs.data(), n_images, bp);
+    if (bp.items > (int64_t)0xffffffffll) return FIC_ERR_CAPACITY;   // one 32-bit item queue
+    if (ws_bytes < bp.total) return FIC_ERR_WORKSPACE;
     fic_status st = enter(ctx);
     if (st != FIC_OK) return st;
     hipStream_t s = (hipStream_t)stream;
-    // The images run back to back on one stream, so they can share one
-    // workspace region.
-    for (int i = 0; i < n_images; ++i) {
-        const fic_image_desc &d = descs[i];
-        const Geom g = to_geom(&d.geom);
-        const bool pooled = isfinite(d.tol) || d.tol < 0;
-        const BatchPart bp = batch_part(g, pooled);
-        char *w = (char *)ws;
-        double *fdr = (double *)(w + bp.off_fdr);
-        double *fdd = (double *)(w + bp.off_fdd);
-        uint32_t *perm = (uint32_t *)(w + bp.off_perm);
-        uint32_t *lo = (uint32_t *)(w + bp.off_lo);
-        uint32_t *hi = (uint32_t *)(w + bp.off_hi);
-        hipError_t e = hipSuccess;
-        if (pooled) {
-            e = fic::launch_fd_classify(d.img, g.h, g.w, g.pitch, g.b, g.b, fdr, nullptr, s,
-                                        tracer_of(ctx));
-            if (e == hipSuccess)
-                e = fic::launch_fd_classify(d.img, g.h, g.w, g.pitch, 2 * g.b, g.t, fdd, nullptr, s,
-                                            tracer_of(ctx));
-            if (e == hipSuccess)
-                e = fic::launch_pool(fdr, (int32_t)g.R, fdd, (int32_t)g.D, d.tol, perm, lo, hi,
-                                     w + bp.off_pool, s, tracer_of(ctx));
+    if (!ctx->use_graph)
+        return dev_status(fic::run_encode_batch(jobs.data(), bp, ws, ctx->num_cu, ctx->counters, s,
+                                                tracer_of(ctx)));
+    std::vector<unsigned char> key = batch_key(n_images, descs, ws, ws_bytes, ctx->counters);
+    size_t hit = ctx->graphs.size();
+    for (size_t i = 0; i < ctx->graphs.size(); ++i)
+        if (ctx->graphs[i].key == key) { hit = i; break; }
+    if (hit == ctx->graphs.size()) {
+        // record the whole batch once, on a capture stream of our own
+        if (!ctx->cap && hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking) != hipSuccess) {
+            ctx->cap = nullptr;
+            return FIC_ERR_DEVICE;
         }
-        fic::EncodePlan p;
-        fic::plan_encode(g, pooled, p);
-        if (e == hipSuccess)
-            e = fic::run_encode(p, d.img, pooled ? perm : nullptr, pooled ? lo : nullptr,
-                                pooled ? hi : nullptr, FIC_KERNEL_MFMA, d.codes, w + bp.off_enc,
-                                ctx->num_cu, ctx->counters, s, tracer_of(ctx));
-        if (e != hipSuccess) return FIC_ERR_DEVICE;
+        if (hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return FIC_ERR_DEVICE;
+        const hipError_t e = fic::run_encode_batch(jobs.data(), bp, ws, ctx->num_cu, ctx->counters,
+                                                   ctx->cap, nullptr);
+        hipGraph_t graph = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(ctx->cap, &graph);
+        hipGraphExec_t exec = nullptr;
+        hipError_t e3 = hipErrorUnknown;
+        if (e == hipSuccess && e2 == hipSuccess && graph)
+            e3 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (graph) hipGraphDestroy(graph);
+        if (e3 != hipSuccess) return FIC_ERR_DEVICE;
+        if (ctx->graphs.size() >= kMaxGraphs) {
+            hipGraphExecDestroy(ctx->graphs.front().exec);
+            ctx->graphs.erase(ctx->graphs.begin());
+        }
+        ctx->graphs.push_back({std::move(key), exec});
+    } else if (hit + 1 != ctx->graphs.size()) {
+        fic_ctx::Graph g = std::move(ctx->graphs[hit]);
+        ctx->graphs.erase(ctx->graphs.begin() + hit);
+        ctx->graphs.push_back(std::move(g));
     }
-    return FIC_OK;
+    const fic::Tracer *tr = tracer_of(ctx);
+    fic::trace(tr, FIC_STAGE_BATCH, 1, s);
+    const hipError_t e = hipGraphLaunch(ctx->graphs.back().exec, s);
+    fic::trace(tr, FIC_STAGE_BATCH, 0, s);
+    return dev_status(e);
 }
 
 size_t fic_decode_workspace_bytes(const fic_geom *g)

@@ -24,6 +24,9 @@
 // integer cross term from the 2x2-sum image, exact fit, the same keys.
 #include "fic_internal.h"
 
+#include <algorithm>
+#include <vector>
+
 namespace fic {
 
 namespace {
@@ -309,6 +312,23 @@ __global__ __launch_bounds__(256) void k_seed(const _Float16 *__restrict__ A,
 }
 
 // ------------------------------------------------------------ work list
+// One image's search operands: an entry of the device table the persistent
+// search reads per work item, so one launch serves many images.
+struct SearchArgs {
+    const _Float16 *A;
+    const _Float16 *Bm;
+    const float *u;
+    const int32_t *eps;
+    const int64_t *sdd;
+    const uint32_t *dom;
+    const RangeStat *rs;
+    const uint4 *grp;
+    const WorkItem *items;
+    const uint32_t *n_items;
+    u64 *keys;
+    int shift;
+};
+
 // Per group: the union [L, H) of its active ranges' intervals (rounded to
 // 16-column blocks) and their intersection [ilo, ihi) (blocks inside it need
 // no per-range mask). Groups without an active range get L = H = Dp.
@@ -356,12 +376,15 @@ __global__ void k_chunk_span(const uint4 *__restrict__ grp, int64_t G, int64_t N
 // offset inside the chunk's run. Column-chunk-major order: the items in
 // flight at any moment share a few column chunks, which then stay resident
 // in each XCD's L2.
+// Thread 0 also publishes the image's table entry.
 __global__ void k_emit_items(const uint4 *__restrict__ grp, const uint32_t *__restrict__ chunkoff,
                              const uint32_t *__restrict__ gfirst, int64_t NC,
                              const uint32_t *__restrict__ total, int64_t max_items,
-                             WorkItem *__restrict__ items)
+                             WorkItem *__restrict__ items, SearchArgs args,
+                             SearchArgs *__restrict__ slot)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *slot = args;
     if (i >= max_items || i >= (int64_t)*total) return;
     int64_t a = 0, b = NC;                   // last c with chunkoff[c] <= i
     while (b - a > 1) { const int64_t m = (a + b) >> 1; if (chunkoff[m] <= (uint32_t)i) a = m; else b = m; }
@@ -376,23 +399,38 @@ __global__ void k_emit_items(const uint4 *__restrict__ grp, const uint32_t *__re
     items[i] = w;
 }
 
+// base[i] = items of the table entries before i (exclusive prefix over the
+// images' item counts), base[n] = all items. One workgroup: each thread sums
+// a contiguous run of entries, then the 256 partial sums are scanned.
+__global__ __launch_bounds__(256) void k_item_bases(const SearchArgs *__restrict__ tab, int32_t n,
+                                                    uint32_t *__restrict__ base)
+{
+    __shared__ uint32_t part[256];
+    const int t = threadIdx.x;
+    const int per = (n + 255) / 256;
+    const int i0 = min(n, t * per), i1 = min(n, i0 + per);
+    uint32_t sum = 0;
+    for (int i = i0; i < i1; ++i) sum += *tab[i].n_items;
+    part[t] = sum;
+    __syncthreads();
+    if (t == 0) {
+        uint32_t acc = 0;
+        for (int k = 0; k < 256; ++k) {
+            const uint32_t v = part[k];
+            part[k] = acc;
+            acc += v;
+        }
+        base[n] = acc;
+    }
+    __syncthreads();
+    uint32_t acc = part[t];
+    for (int i = i0; i < i1; ++i) {
+        base[i] = acc;
+        acc += *tab[i].n_items;
+    }
+}
+
 // ------------------------------------------------------------ MFMA search
-struct SearchArgs {
-    const _Float16 *A;
-    const _Float16 *Bm;
-    const float *u;
-    const int32_t *eps;
-    const int64_t *sdd;
-    const uint32_t *dom;
-    const RangeStat *rs;
-    const uint4 *grp;
-    const WorkItem *items;
-    const uint32_t *n_items;
-    uint32_t *item_ctr;
-    u64 *keys;
-    u64 *counters;
-    int shift;
-};
 
 template <int B> struct WaveState {
     typedef typename Frag<Cfg<B>::EPL>::type frag_t;
@@ -545,24 +583,37 @@ __device__ __forceinline__ void scan_blocks(const SearchArgs &a, WaveState<B> &s
     }
 }
 
+// Items of n_img images (table entries tab[0..n_img), item bases base[]) in
+// one queue: a wave claims an item, finds its image by binary search over
+// the bases, and loads that image's operands.
 template <int B>
-__global__ __launch_bounds__(256, 2) void k_search_mfma(SearchArgs a)
+__global__ __launch_bounds__(256, 2) void k_search_mfma(const SearchArgs *__restrict__ tab,
+                                                        const uint32_t *__restrict__ base,
+                                                        int32_t n_img, uint32_t *item_ctr,
+                                                        u64 *counters)
 {
     using C = Cfg<B>;
     constexpr int MW = C::MW, KS = C::KS, GR = 2 * MW;
     typedef typename WaveState<B>::frag_t frag_t;
     const int lane = threadIdx.x & 63, hl = lane >> 5;
-    const uint32_t nitems = *a.n_items;
+    const uint32_t nitems = base[n_img];
     WaveState<B> st;
     st.survivors = 0;
     st.screened = 0;
     u64 items_done = 0;
     for (;;) {
         uint32_t item = 0;
-        if (lane == 0) item = atomicAdd(a.item_ctr, 1u);
+        if (lane == 0) item = atomicAdd(item_ctr, 1u);
         item = __builtin_amdgcn_readfirstlane(item);
         if (item >= nitems) break;
-        const WorkItem wi = a.items[item];
+        int ia = 0, ib = n_img;              // last image whose base <= item
+        while (ib - ia > 1) {
+            const int m = (ia + ib) >> 1;
+            if (base[m] <= item) ia = m; else ib = m;
+        }
+        ia = __builtin_amdgcn_readfirstlane(ia);
+        const SearchArgs a = tab[ia];
+        const WorkItem wi = a.items[item - base[ia]];
         st.grp = wi.grp;
         const frag_t *ap = (const frag_t *)a.A + (int64_t)st.grp * MW * KS * 64 + lane;
 #pragma unroll
@@ -599,14 +650,14 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma(SearchArgs a)
         }
         items_done += 1;
     }
-    if (a.counters) {
+    if (counters) {
         u64 sv = st.survivors;
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) sv += __shfl_xor(sv, off);
         if (lane == 0) {
-            atomicAdd(&a.counters[0], st.screened);
-            atomicAdd(&a.counters[1], sv);
-            atomicAdd(&a.counters[2], items_done);
+            atomicAdd(&counters[0], st.screened);
+            atomicAdd(&counters[1], sv);
+            atomicAdd(&counters[2], items_done);
         }
     }
 }
@@ -735,38 +786,49 @@ __global__ void k_finalize(const uint8_t *__restrict__ img, Geom g,
 
 inline unsigned blocks_for(int64_t n, int th) { return (unsigned)((n + th - 1) / th); }
 
+// Plain search: 2x2 sums, then one thread per (range, position, isometry).
 template <int B>
-hipError_t run_encode_b(const EncodePlan &p, const uint8_t *img, const uint32_t *perm,
-                        const uint32_t *lo, const uint32_t *hi, int kernel, fic_code *codes,
-                        void *ws, int num_cu, u64 *counters, hipStream_t s, const Tracer *tr)
+hipError_t run_plain_b(const EncodePlan &p, const uint8_t *img, const uint32_t *perm,
+                       const uint32_t *lo, const uint32_t *hi, fic_code *codes, void *ws,
+                       hipStream_t s, const Tracer *tr)
 {
-    using C = Cfg<B>;
     const Geom &g = p.g;
     char *w = (char *)ws;
     u64 *keys = (u64 *)(w + p.off_keys);
     const int th = 256;
-    if (kernel == FIC_KERNEL_PLAIN) {
-        uint16_t *S = (uint16_t *)(w + p.off_S);
-        trace(tr, FIC_STAGE_DOMAIN_PREP, 1, s);
-        hipLaunchKernelGGL(k_box2x2, dim3(blocks_for((int64_t)(g.h - 1) * (g.w - 1), th)), dim3(th),
-                           0, s, img, g.h, g.w, g.pitch, S);
-        hipLaunchKernelGGL(k_fill_u64, dim3(blocks_for(g.R, th)), dim3(th), 0, s, keys, g.R, kNoKey);
-        trace(tr, FIC_STAGE_DOMAIN_PREP, 0, s);
-        trace(tr, FIC_STAGE_SEARCH, 1, s);
-        const unsigned gx = blocks_for(p.Dp, 32);
-        for (int64_t r0 = 0; r0 < g.R; r0 += 65535) {
-            const unsigned gy = (unsigned)(g.R - r0 < 65535 ? g.R - r0 : 65535);
-            hipLaunchKernelGGL(k_search_plain<B>, dim3(gx, gy), dim3(256), 0, s, img, g, S, perm, lo,
-                               hi, r0, p.shift, keys);
-        }
-        trace(tr, FIC_STAGE_SEARCH, 0, s);
-        trace(tr, FIC_STAGE_FINAL, 1, s);
-        hipLaunchKernelGGL(k_finalize<B>, dim3(blocks_for(g.R, th)), dim3(th), 0, s, img, g,
-                           (const uint32_t *)nullptr, keys, p.shift, codes);
-        trace(tr, FIC_STAGE_FINAL, 0, s);
-        return hipGetLastError();
+    uint16_t *S = (uint16_t *)(w + p.off_S);
+    trace(tr, FIC_STAGE_DOMAIN_PREP, 1, s);
+    hipLaunchKernelGGL(k_box2x2, dim3(blocks_for((int64_t)(g.h - 1) * (g.w - 1), th)), dim3(th), 0,
+                       s, img, g.h, g.w, g.pitch, S);
+    hipLaunchKernelGGL(k_fill_u64, dim3(blocks_for(g.R, th)), dim3(th), 0, s, keys, g.R, kNoKey);
+    trace(tr, FIC_STAGE_DOMAIN_PREP, 0, s);
+    trace(tr, FIC_STAGE_SEARCH, 1, s);
+    const unsigned gx = blocks_for(p.Dp, 32);
+    for (int64_t r0 = 0; r0 < g.R; r0 += 65535) {
+        const unsigned gy = (unsigned)(g.R - r0 < 65535 ? g.R - r0 : 65535);
+        hipLaunchKernelGGL(k_search_plain<B>, dim3(gx, gy), dim3(256), 0, s, img, g, S, perm, lo, hi,
+                           r0, p.shift, keys);
     }
+    trace(tr, FIC_STAGE_SEARCH, 0, s);
+    trace(tr, FIC_STAGE_FINAL, 1, s);
+    hipLaunchKernelGGL(k_finalize<B>, dim3(blocks_for(g.R, th)), dim3(th), 0, s, img, g,
+                       (const uint32_t *)nullptr, keys, p.shift, codes);
+    trace(tr, FIC_STAGE_FINAL, 0, s);
+    return hipGetLastError();
+}
 
+// Everything before the MFMA search for one image: range order and A rows,
+// B columns, seeds, the work list; the last kernel publishes the image's
+// table entry to *slot.
+template <int B>
+hipError_t prep_b(const EncodePlan &p, const uint8_t *img, const uint32_t *perm,
+                  const uint32_t *lo, const uint32_t *hi, void *ws, u64 *counters,
+                  SearchArgs *slot, hipStream_t s, const Tracer *tr)
+{
+    const Geom &g = p.g;
+    char *w = (char *)ws;
+    const int th = 256;
+    u64 *keys = (u64 *)(w + p.off_keys);
     _Float16 *A = (_Float16 *)(w + p.off_A);
     RangeStat *rs = (RangeStat *)(w + p.off_rs);
     uint32_t *order = (uint32_t *)(w + p.off_order);
@@ -793,12 +855,11 @@ hipError_t run_encode_b(const EncodePlan &p, const uint8_t *img, const uint32_t 
         hipError_t e = radix_sort_pairs(sk, order, g.R, p.pooled ? 2 * dbits : 8, w + p.off_sort, s);
         if (e != hipSuccess) return e;
     }
-    const uint32_t *ord = order;
     if (p.pooled)
         hipLaunchKernelGGL(k_blockmin, dim3(blocks_for((g.D + kBminBlock - 1) / kBminBlock * 64, th)),
                            dim3(th), 0, s, perm, g.D, bmin);
     hipLaunchKernelGGL(k_range_prep<B>, dim3(blocks_for(p.Rp * 8, th)), dim3(th), 0, s, img, g.pitch,
-                       g.rcols, g.R, p.Rp, ord, lo, hi, (uint32_t)g.D, A, rs);
+                       g.rcols, g.R, p.Rp, (const uint32_t *)order, lo, hi, (uint32_t)g.D, A, rs);
     trace(tr, FIC_STAGE_RANGE_PREP, 0, s);
     trace(tr, FIC_STAGE_DOMAIN_PREP, 1, s);
     hipLaunchKernelGGL(k_domain_prep<B>, dim3(blocks_for(p.Dp * B, th)), dim3(th), 0, s, img,
@@ -813,30 +874,91 @@ hipError_t run_encode_b(const EncodePlan &p, const uint8_t *img, const uint32_t 
                        chunkcnt, chunkfill);
     // exclusive scan of the per-chunk counts; the total is the item count
     scan_u32(chunkcnt, p.NC, ctr + 1, w + p.off_scan, s);
-    hipLaunchKernelGGL(k_emit_items, dim3(blocks_for(p.max_items, th)), dim3(th), 0, s, grp,
-                       chunkcnt, chunkfill, p.NC, ctr + 1, p.max_items, items);
     SearchArgs a;
     a.A = A; a.Bm = Bm; a.u = u; a.eps = eps; a.sdd = sdd; a.dom = dom; a.rs = rs; a.grp = grp;
-    a.items = items; a.n_items = ctr + 1; a.item_ctr = ctr; a.keys = keys; a.counters = counters;
-    a.shift = p.shift;
-    // persistent grid: as many workgroups as stay resident on every CU
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void *>(&k_search_mfma<B>), 256, 0) != hipSuccess ||
-        per_cu < 1)
-        per_cu = 1;
+    a.items = items; a.n_items = ctr + 1; a.keys = keys; a.shift = p.shift;
+    hipLaunchKernelGGL(k_emit_items, dim3(blocks_for(p.max_items, th)), dim3(th), 0, s, grp,
+                       chunkcnt, chunkfill, p.NC, ctr + 1, p.max_items, items, a, slot);
     trace(tr, FIC_STAGE_WORKLIST, 0, s);
+    return hipGetLastError();
+}
+
+// Resident workgroups per CU of k_search_mfma<4, 8, 16>, queried once per
+// process (outside any stream capture).
+int g_per_cu[3] = {0, 0, 0};
+
+template <int B> hipError_t occupancy_of(int &out)
+{
+    int v = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &v, reinterpret_cast<const void *>(&k_search_mfma<B>), 256, 0);
+    out = v < 1 ? 1 : v;
+    return e;
+}
+
+// The persistent search over the items of n table entries (all range size
+// B). item_ctr must read 0; base holds n + 1 entries.
+template <int B>
+hipError_t search_b(const SearchArgs *tab, int32_t n, uint32_t *base, uint32_t *item_ctr,
+                    int num_cu, u64 *counters, hipStream_t s, const Tracer *tr)
+{
+    // persistent grid: as many workgroups as stay resident on every CU
+    const int per_cu = g_per_cu[B == 4 ? 0 : B == 8 ? 1 : 2];
+    if (per_cu < 1) return hipErrorNotInitialized;
+    hipLaunchKernelGGL(k_item_bases, dim3(1), dim3(256), 0, s, tab, n, base);
     trace(tr, FIC_STAGE_SEARCH, 1, s);
-    hipLaunchKernelGGL(k_search_mfma<B>, dim3(per_cu * num_cu), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_search_mfma<B>, dim3(per_cu * num_cu), dim3(256), 0, s, tab,
+                       (const uint32_t *)base, n, item_ctr, counters);
     trace(tr, FIC_STAGE_SEARCH, 0, s);
+    return hipGetLastError();
+}
+
+template <int B>
+hipError_t finalize_b(const EncodePlan &p, const uint8_t *img, void *ws, fic_code *codes,
+                      hipStream_t s, const Tracer *tr)
+{
+    char *w = (char *)ws;
     trace(tr, FIC_STAGE_FINAL, 1, s);
-    hipLaunchKernelGGL(k_finalize<B>, dim3(blocks_for(g.R, th)), dim3(th), 0, s, img, g, ord, keys,
-                       p.shift, codes);
+    hipLaunchKernelGGL(k_finalize<B>, dim3(blocks_for(p.g.R, 256)), dim3(256), 0, s, img, p.g,
+                       (const uint32_t *)(w + p.off_order), (const u64 *)(w + p.off_keys), p.shift,
+                       codes);
     trace(tr, FIC_STAGE_FINAL, 0, s);
     return hipGetLastError();
 }
 
+template <int B>
+hipError_t run_encode_b(const EncodePlan &p, const uint8_t *img, const uint32_t *perm,
+                        const uint32_t *lo, const uint32_t *hi, int kernel, fic_code *codes,
+                        void *ws, int num_cu, u64 *counters, hipStream_t s, const Tracer *tr)
+{
+    if (kernel == FIC_KERNEL_PLAIN) return run_plain_b<B>(p, img, perm, lo, hi, codes, ws, s, tr);
+    char *w = (char *)ws;
+    uint32_t *ctr = (uint32_t *)(w + p.off_ctr);   // [0] item counter, [1] items, [2..3] bases
+    SearchArgs *slot = (SearchArgs *)(w + p.off_args);
+    hipError_t e = prep_b<B>(p, img, perm, lo, hi, ws, counters, slot, s, tr);
+    if (e == hipSuccess) e = search_b<B>(slot, 1, ctr + 2, ctr, num_cu, counters, s, tr);
+    if (e == hipSuccess) e = finalize_b<B>(p, img, ws, codes, s, tr);
+    return e;
+}
+
+template <int B>
+hipError_t batch_phase(int phase, const EncodePlan &p, const uint8_t *img, const uint32_t *perm,
+                       const uint32_t *lo, const uint32_t *hi, void *ws, u64 *counters,
+                       SearchArgs *slot, fic_code *codes, hipStream_t s, const Tracer *tr)
+{
+    return phase == 0 ? prep_b<B>(p, img, perm, lo, hi, ws, counters, slot, s, tr)
+                      : finalize_b<B>(p, img, ws, codes, s, tr);
+}
+
 }  // namespace
+
+hipError_t init_search_occupancy()
+{
+    hipError_t e = occupancy_of<4>(g_per_cu[0]);
+    if (e == hipSuccess) e = occupancy_of<8>(g_per_cu[1]);
+    if (e == hipSuccess) e = occupancy_of<16>(g_per_cu[2]);
+    return e;
+}
 
 void plan_encode(const Geom &g, int pooled, EncodePlan &p)
 {
@@ -866,6 +988,7 @@ void plan_encode(const Geom &g, int pooled, EncodePlan &p)
     p.off_keys = take((size_t)p.Rp * 8);
     p.off_items = take((size_t)p.max_items * sizeof(WorkItem));
     p.off_ctr = take(256);
+    p.off_args = take(sizeof(SearchArgs));
     p.off_chunkcnt = take((size_t)p.NC * 4);
     p.off_chunkfill = take((size_t)p.NC * 4);
     p.off_grp = take((size_t)p.G * 16);
@@ -887,6 +1010,124 @@ hipError_t run_encode(const EncodePlan &p, const uint8_t *img, const uint32_t *p
     case 16: return run_encode_b<16>(p, img, perm, lo, hi, kernel, codes, ws, num_cu, counters, s, tr);
     default: return hipErrorInvalidValue;
     }
+}
+
+// ------------------------------------------------------------ batch
+// Workspace of a batch: a header (the table of search operands, grouped by
+// range size; per size the item bases and the item counter), then one part
+// per image (fd of ranges and domains, pool, encode workspace). Within a
+// size group the images are ordered by decreasing R * D, so the largest
+// images' items enter the queue first and small images fill the tail.
+namespace {
+constexpr int kSizes[3] = {4, 8, 16};
+int size_group(int b) { return b == 4 ? 0 : b == 8 ? 1 : 2; }
+}
+
+void plan_batch(const BatchJob *jobs, int32_t n, BatchPlan &bp)
+{
+    bp.n = n;
+    bp.slot.assign(n, 0);
+    bp.part.assign(n, BatchPart{});
+    std::vector<int32_t> idx(n);
+    for (int32_t i = 0; i < n; ++i) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) {
+        const int gx = size_group(jobs[x].g.b), gy = size_group(jobs[y].g.b);
+        if (gx != gy) return gx < gy;
+        return jobs[x].g.R * jobs[x].g.D > jobs[y].g.R * jobs[y].g.D;
+    });
+    bp.order = idx;
+    for (int k = 0; k < 3; ++k) { bp.group_first[k] = 0; bp.group_count[k] = 0; }
+    for (int32_t k = 0; k < n; ++k) {
+        const int gi = size_group(jobs[idx[k]].g.b);
+        if (bp.group_count[gi] == 0) bp.group_first[gi] = k;
+        bp.group_count[gi] += 1;
+        bp.slot[idx[k]] = k;
+    }
+    size_t o = 0;
+    auto take = [&](size_t b) { size_t r = o; o += align256(b); return r; };
+    bp.off_tab = take((size_t)n * sizeof(SearchArgs));
+    bp.off_base = take((size_t)3 * (n + 1) * 4);
+    bp.off_ctr = take(3 * 256);
+    bp.items = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        const BatchJob &j = jobs[i];
+        BatchPart &pt = bp.part[i];
+        pt.off_fdr = take((size_t)j.g.R * 8);
+        pt.off_fdd = take((size_t)j.g.D * 8);
+        pt.off_perm = take((size_t)j.g.D * 4);
+        pt.off_lo = take((size_t)j.g.R * 4);
+        pt.off_hi = take((size_t)j.g.R * 4);
+        pt.off_pool = take(j.pooled ? pool_ws_bytes(j.g.R, j.g.D) : 0);
+        plan_encode(j.g, j.pooled ? 1 : 0, pt.plan);
+        pt.off_enc = take(pt.plan.total);
+        bp.items += pt.plan.max_items;
+    }
+    bp.total = o;
+}
+
+hipError_t run_encode_batch(const BatchJob *jobs, const BatchPlan &bp, void *ws, int num_cu,
+                            u64 *counters, hipStream_t s, const Tracer *tr)
+{
+    char *w = (char *)ws;
+    SearchArgs *tab = (SearchArgs *)(w + bp.off_tab);
+    uint32_t *base = (uint32_t *)(w + bp.off_base);
+    uint32_t *ctr = (uint32_t *)(w + bp.off_ctr);
+    hipLaunchKernelGGL(k_fill_u32, dim3(3), dim3(64), 0, s, ctr, (int64_t)(3 * 64), 0u);
+    hipError_t e = hipGetLastError();
+    // classify, pool and search preparation, image by image
+    for (int32_t k = 0; k < bp.n && e == hipSuccess; ++k) {
+        const int32_t i = bp.order[k];
+        const BatchJob &j = jobs[i];
+        const BatchPart &pt = bp.part[i];
+        const Geom &g = j.g;
+        double *fdr = (double *)(w + pt.off_fdr);
+        double *fdd = (double *)(w + pt.off_fdd);
+        uint32_t *perm = (uint32_t *)(w + pt.off_perm);
+        uint32_t *lo = (uint32_t *)(w + pt.off_lo);
+        uint32_t *hi = (uint32_t *)(w + pt.off_hi);
+        if (j.pooled) {
+            e = launch_fd_classify(j.img, g.h, g.w, g.pitch, g.b, g.b, fdr, nullptr, s, tr);
+            if (e == hipSuccess)
+                e = launch_fd_classify(j.img, g.h, g.w, g.pitch, 2 * g.b, g.t, fdd, nullptr, s, tr);
+            if (e == hipSuccess)
+                e = launch_pool(fdr, (int32_t)g.R, fdd, (int32_t)g.D, j.tol, perm, lo, hi,
+                                w + pt.off_pool, s, tr);
+        }
+        if (e != hipSuccess) break;
+        const uint32_t *pp = j.pooled ? perm : nullptr;
+        const uint32_t *pl = j.pooled ? lo : nullptr;
+        const uint32_t *ph = j.pooled ? hi : nullptr;
+        void *ew = w + pt.off_enc;
+        switch (g.b) {
+        case 4: e = batch_phase<4>(0, pt.plan, j.img, pp, pl, ph, ew, counters, tab + k, nullptr, s, tr); break;
+        case 8: e = batch_phase<8>(0, pt.plan, j.img, pp, pl, ph, ew, counters, tab + k, nullptr, s, tr); break;
+        default: e = batch_phase<16>(0, pt.plan, j.img, pp, pl, ph, ew, counters, tab + k, nullptr, s, tr); break;
+        }
+    }
+    // one persistent search per range size over all its images
+    for (int gi = 0; gi < 3 && e == hipSuccess; ++gi) {
+        if (bp.group_count[gi] == 0) continue;
+        const SearchArgs *t = tab + bp.group_first[gi];
+        uint32_t *gb = base + (size_t)gi * (bp.n + 1);
+        uint32_t *gc = ctr + gi * 64;
+        switch (kSizes[gi]) {
+        case 4: e = search_b<4>(t, bp.group_count[gi], gb, gc, num_cu, counters, s, tr); break;
+        case 8: e = search_b<8>(t, bp.group_count[gi], gb, gc, num_cu, counters, s, tr); break;
+        default: e = search_b<16>(t, bp.group_count[gi], gb, gc, num_cu, counters, s, tr); break;
+        }
+    }
+    for (int32_t k = 0; k < bp.n && e == hipSuccess; ++k) {
+        const int32_t i = bp.order[k];
+        const BatchJob &j = jobs[i];
+        const BatchPart &pt = bp.part[i];
+        void *ew = w + pt.off_enc;
+        switch (j.g.b) {
+        case 4: e = batch_phase<4>(1, pt.plan, j.img, nullptr, nullptr, nullptr, ew, counters, nullptr, j.codes, s, tr); break;
+        case 8: e = batch_phase<8>(1, pt.plan, j.img, nullptr, nullptr, nullptr, ew, counters, nullptr, j.codes, s, tr); break;
+        default: e = batch_phase<16>(1, pt.plan, j.img, nullptr, nullptr, nullptr, ew, counters, nullptr, j.codes, s, tr); break;
+        }
+    }
+    return e;
 }
 
 }  // namespace fic

@@ -10,6 +10,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "fic.h"
 
 namespace fic {
@@ -161,6 +163,7 @@ hipError_t radix_sort_pairs(u64 *keys, uint32_t *vals, int64_t n, int key_bits, 
                             hipStream_t s);
 size_t scan_ws_bytes(int64_t m);
 hipError_t scan_u32(uint32_t *a, int64_t m, uint32_t *total, void *ws, hipStream_t s);
+size_t pool_ws_bytes(int64_t nr, int64_t nd);
 hipError_t launch_pool(const double *fd_range, int32_t nr, const double *fd_dom, int32_t nd,
                        double tol, uint32_t *perm, uint32_t *lo, uint32_t *hi, void *ws,
                        hipStream_t s, const Tracer *tr = nullptr);
@@ -173,14 +176,40 @@ struct EncodePlan {
     int32_t chunk, shift;
     int64_t max_items;
     size_t off_A, off_rs, off_order, off_B, off_u, off_eps, off_sdd, off_dom, off_keys,
-        off_items, off_ctr, off_chunkcnt, off_chunkfill, off_grp, off_bmin, off_S, off_sort,
-        off_sortkeys, off_scan, total;
+        off_items, off_ctr, off_args, off_chunkcnt, off_chunkfill, off_grp, off_bmin, off_S,
+        off_sort, off_sortkeys, off_scan, total;
 };
+hipError_t init_search_occupancy();   // once per process, before any search launch
 void plan_encode(const Geom &g, int pooled, EncodePlan &p);
 hipError_t run_encode(const EncodePlan &p, const uint8_t *img, const uint32_t *perm,
                       const uint32_t *lo, const uint32_t *hi, int kernel, fic_code *codes,
                       void *ws, int num_cu, u64 *counters, hipStream_t s,
                       const Tracer *tr = nullptr);
+
+// Batch: one image of it, its workspace part, and the whole layout.
+struct BatchJob {
+    const uint8_t *img;
+    Geom g;
+    double tol;
+    bool pooled;
+    fic_code *codes;
+};
+struct BatchPart {
+    size_t off_fdr, off_fdd, off_perm, off_lo, off_hi, off_pool, off_enc;
+    EncodePlan plan;
+};
+struct BatchPlan {
+    int32_t n;
+    std::vector<int32_t> order;      // preparation / table order of the images
+    std::vector<int32_t> slot;       // table entry of image i
+    std::vector<BatchPart> part;
+    int32_t group_first[3], group_count[3];   // table runs for B = 4, 8, 16
+    size_t off_tab, off_base, off_ctr, total;
+    int64_t items;                   // upper bound on the work items of all images
+};
+void plan_batch(const BatchJob *jobs, int32_t n, BatchPlan &bp);
+hipError_t run_encode_batch(const BatchJob *jobs, const BatchPlan &bp, void *ws, int num_cu,
+                            u64 *counters, hipStream_t s, const Tracer *tr = nullptr);
 
 // decode (decode.hip)
 size_t decode_ws_bytes(const Geom &g);

@@ -238,6 +238,15 @@ __global__ void k_bounds(const double *__restrict__ fdr, int32_t nr,
     hi[r] = (uint32_t)c;
 }
 
+__global__ void k_copy_pairs(const u64 *__restrict__ ks, const uint32_t *__restrict__ vs,
+                             u64 *__restrict__ kd, uint32_t *__restrict__ vd, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    kd[i] = ks[i];
+    vd[i] = vs[i];
+}
+
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
@@ -286,15 +295,20 @@ hipError_t radix_sort_pairs(u64 *keys, uint32_t *vals, int64_t n, int key_bits, 
         u64 *tk = ka; ka = kb; kb = tk;
         uint32_t *tv = va; va = vb; vb = tv;
     }
-    if (ka != keys) {   // odd pass count: copy back
-        hipMemcpyAsync(keys, ka, (size_t)n * 8, hipMemcpyDeviceToDevice, s);
-        hipMemcpyAsync(vals, va, (size_t)n * 4, hipMemcpyDeviceToDevice, s);
-    }
+    if (ka != keys)     // odd pass count: copy back (a kernel, so graphs hold no copy nodes)
+        hipLaunchKernelGGL(k_copy_pairs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ka, va,
+                           keys, vals, n);
     return hipGetLastError();
 }
 
 // Pool workspace: sort keys (n_domain u64), sorted fd (n_domain f64),
 // tol (f64), sort scratch.
+size_t pool_ws_bytes(int64_t nr, int64_t nd)
+{
+    (void)nr;
+    return align256((size_t)nd * 8) * 2 + 256 + sort_ws_bytes(nd);
+}
+
 hipError_t launch_pool(const double *fd_range, int32_t nr, const double *fd_dom, int32_t nd,
                        double tol, uint32_t *perm, uint32_t *lo, uint32_t *hi, void *ws,
                        hipStream_t s, const Tracer *tr)

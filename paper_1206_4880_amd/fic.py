@@ -16,7 +16,8 @@ LIB_PATH = os.path.join(_HERE, "libfic.so")
 
 OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_CAPACITY, ERR_DEVICE = range(6)
 KERNEL_MFMA, KERNEL_PLAIN = 0, 1
-STAGES = ("classify", "pool", "range_prep", "domain_prep", "worklist", "search", "final", "decode")
+STAGES = ("classify", "pool", "range_prep", "domain_prep", "worklist", "search", "final", "decode",
+          "batch")
 CODE_DTYPE = np.dtype([("domain", "<u4"), ("iso", "u1"), ("s_idx", "i1"), ("o_idx", "u1"),
                        ("flags", "u1"), ("err", "<i8")])
 assert CODE_DTYPE.itemsize == 16
@@ -72,6 +73,7 @@ def lib():
         "fic_batch_workspace_bytes": (ctypes.c_size_t, [_i32, ctypes.POINTER(ImageDesc)]),
         "fic_encode_pifs_batch": (_st, [_vp, _i32, ctypes.POINTER(ImageDesc), _vp,
                                         ctypes.c_size_t, _vp]),
+        "fic_set_batch_graph": (_st, [_vp, _i32]),
         "fic_decode_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Geom)]),
         "fic_decode_pifs": (_st, [_vp, _vp, ctypes.POINTER(Geom), _i32, _vp, _vp, _vp,
                                   ctypes.c_size_t, _vp, _vp]),
@@ -88,8 +90,8 @@ EXPORTED = ("fic_create", "fic_destroy", "fic_status_string", "fic_set_counters"
             "fic_timing_enable", "fic_timing_read",
             "fic_num_ranges", "fic_num_domains", "fic_fd_classify", "fic_pool_workspace_bytes",
             "fic_build_domain_pool", "fic_encode_workspace_bytes", "fic_encode_pifs",
-            "fic_batch_workspace_bytes", "fic_encode_pifs_batch", "fic_decode_workspace_bytes",
-            "fic_decode_pifs")
+            "fic_batch_workspace_bytes", "fic_encode_pifs_batch", "fic_set_batch_graph",
+            "fic_decode_workspace_bytes", "fic_decode_pifs")
 
 
 def status_string(status):
@@ -147,6 +149,9 @@ class Context:
     def set_counters(self, counters):
         ptr = counters.data_ptr() if counters is not None else None
         _check(lib().fic_set_counters(self.handle, ptr), "fic_set_counters")
+
+    def set_batch_graph(self, enable):
+        _check(lib().fic_set_batch_graph(self.handle, 1 if enable else 0), "fic_set_batch_graph")
 
 
 _contexts = {}
@@ -271,9 +276,11 @@ def encode(img, range_size, domain_step, tol=None, kernel="mfma"):
     return encode_pifs(img, range_size, domain_step, pool=pool, kernel=kernel), pool
 
 
-def encode_batch(images, jobs, codes=None):
+def encode_batch(images, jobs, codes=None, ws=None, graph=True):
     """Batch encode: images (list of uint8 CUDA tensors), jobs [(B, t, tol)].
-    Returns the list of codes tensors."""
+    Returns the list of codes tensors. `codes` and `ws` (uint8 CUDA tensors)
+    may be given to keep the buffers, and so a recorded graph, across calls;
+    graph=False enqueues the kernels directly."""
     import torch
     n = len(images)
     descs = (ImageDesc * n)()
@@ -290,10 +297,27 @@ def encode_batch(images, jobs, codes=None):
         descs[i].tol = float("inf") if tol is None else float(tol)
         descs[i].codes = c.data_ptr()
     wsb = lib().fic_batch_workspace_bytes(n, descs)
-    buf = _ws.get(wsb, images[0].device)
-    _check(lib().fic_encode_pifs_batch(context(images[0].device.index).handle, n, descs,
-                                       buf.data_ptr(), wsb, _stream()), "fic_encode_pifs_batch")
+    if ws is not None:
+        if ws.numel() < wsb:
+            raise ValueError("batch workspace needs %d bytes" % wsb)
+        buf = ws
+    else:
+        buf = _ws.get(wsb, images[0].device)
+    ctx = context(images[0].device.index)
+    ctx.set_batch_graph(graph)
+    _check(lib().fic_encode_pifs_batch(ctx.handle, n, descs, buf.data_ptr(), wsb, _stream()),
+           "fic_encode_pifs_batch")
     return outs
+
+
+def batch_workspace_bytes(images, jobs):
+    """Workspace bytes of encode_batch for these images and jobs."""
+    n = len(images)
+    descs = (ImageDesc * n)()
+    for i, (img, (b, t, tol)) in enumerate(zip(images, jobs)):
+        descs[i].geom = _geom_of(img, b, t)
+        descs[i].tol = float("inf") if tol is None else float(tol)
+    return int(lib().fic_batch_workspace_bytes(n, descs))
 
 
 def decode_pifs(codes, height, width, range_size, domain_step, max_iters=32, init=None):

@@ -157,6 +157,31 @@ def test_batch_validation(L, hctx):
     assert L.fic_encode_pifs_batch(hctx.handle, 0, descs, 1, wsb, None) == fic.ERR_INVALID_ARG
 
 
+def test_batch_workspace_is_sum_of_parts(L):
+    """Every image of a batch keeps its own workspace part (all are prepared
+    before the shared searches), so the batch needs more than its largest
+    image alone, and adding an image adds its part."""
+    def descs_of(geoms):
+        d = (fic.ImageDesc * len(geoms))()
+        for i, g in enumerate(geoms):
+            d[i].img = 1
+            d[i].geom = g
+            d[i].tol = 0.05
+            d[i].codes = 1
+        return d
+    g1, g2 = fic.make_geom(256, 256, 8, 2), fic.make_geom(128, 128, 4, 2)
+    one = L.fic_batch_workspace_bytes(1, descs_of([g1]))
+    two = L.fic_batch_workspace_bytes(2, descs_of([g1, g2]))
+    assert one > L.fic_encode_workspace_bytes(ctypes.byref(g1), 1)
+    assert two > one + L.fic_encode_workspace_bytes(ctypes.byref(g2), 1)
+
+
+def test_batch_graph_switch(L, hctx):
+    assert L.fic_set_batch_graph(None, 1) == fic.ERR_INVALID_ARG
+    assert L.fic_set_batch_graph(hctx.handle, 0) == fic.OK
+    assert L.fic_set_batch_graph(hctx.handle, 1) == fic.OK
+
+
 def test_workspace_sizes_grow(L):
     a = L.fic_encode_workspace_bytes(ctypes.byref(fic.make_geom(256, 256, 8, 1)), 0)
     b = L.fic_encode_workspace_bytes(ctypes.byref(fic.make_geom(512, 512, 8, 1)), 0)

@@ -223,12 +223,13 @@ def test_workload_2048(fic, orc, job):
     assert_codes(mf, ref, sel=sel, what="2048 %s" % (job,))
 
 
-def test_batch_matches_single(fic, orc):
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_matches_single(fic, orc, graph):
     from synth import batch_descs
     items = batch_descs(count=6)
     imgs = [dev(im) for (im, _, _, _) in items]
     jobs = [(b, t, tol) for (_, b, t, tol) in items]
-    outs = fic.encode_batch(imgs, jobs)
+    outs = fic.encode_batch(imgs, jobs, graph=graph)
     torch.cuda.synchronize()
     for (im, b, t, tol), c in zip(items, outs):
         got = fic.unpack_codes(c)
@@ -238,6 +239,92 @@ def test_batch_matches_single(fic, orc):
         sel = sampled(got.size, 24, seed=3)
         ref = orc.encode(im, b, t, tol=tol, sel=sel)
         assert_codes(got, ref, sel=sel, what="batch %dx%d B=%d" % (im.shape + (b,)))
+
+
+def _single_codes(fic, im, b, t, tol):
+    c, _ = fic.encode(dev(im), b, t, tol=tol, kernel="mfma")
+    torch.cuda.synchronize()
+    return c.cpu().numpy()
+
+
+def test_batch_mixed_sizes_and_idle_image(fic, orc):
+    """Range sizes 4, 8 and 16 in one batch (one persistent search per size),
+    exhaustive and pooled jobs, and a flat image whose ranges need no search
+    (zero work items) between images that have items."""
+    rng = np.random.default_rng(11)
+    from synth import fbm as _f, piecewise_smooth
+    cases = [
+        (_f(128, 128, 0.5, rng), 8, 2, 0.05),
+        (np.full((64, 96), 77, np.uint8), 8, 1, None),
+        (piecewise_smooth(128, rng), 4, 2, None),
+        (_f(128, 128, 0.7, rng), 16, 4, None),
+        (_f(96, 64, 0.3, rng), 4, 1, 0.1),
+        (_f(64, 64, 0.4, rng), 16, 2, 0.05),
+        (_f(160, 96, 0.6, rng), 8, 3, -1.0),
+    ]
+    imgs = [dev(im) for (im, _, _, _) in cases]
+    jobs = [(b, t, tol) for (_, b, t, tol) in cases]
+    for graph in (False, True):
+        outs = fic.encode_batch(imgs, jobs, graph=graph)
+        torch.cuda.synchronize()
+        for (im, b, t, tol), c in zip(cases, outs):
+            got = fic.unpack_codes(c)
+            ref = orc.encode(im, b, t, tol=tol)
+            assert_codes(got, ref, what="mixed batch %dx%d B=%d t=%d tol=%s graph=%s"
+                         % (im.shape + (b, t, tol, graph)))
+
+
+def test_batch_graph_replays(fic):
+    """A recorded batch replayed several times, with other work and host
+    synchronisation between the replays, equals the eager batch every time;
+    a replay after the images change encodes the new contents."""
+    from synth import batch_descs
+    items = batch_descs(count=5, base_seed=4100)
+    imgs = [dev(im) for (im, _, _, _) in items]
+    jobs = [(b, t, tol) for (_, b, t, tol) in items]
+    eager = [c.cpu().numpy() for c in fic.encode_batch(imgs, jobs, graph=False)]
+    torch.cuda.synchronize()
+    wsb = fic.batch_workspace_bytes(imgs, jobs)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    codes = [torch.empty_like(torch.from_numpy(e)).cuda() for e in eager]
+    other = dev(np.random.default_rng(5).integers(0, 256, (64, 64)).astype(np.uint8))
+    for rep in range(4):
+        codes_out = fic.encode_batch(imgs, jobs, codes=codes, ws=ws, graph=True)
+        torch.cuda.synchronize()
+        for i, (c, e) in enumerate(zip(codes_out, eager)):
+            assert np.array_equal(c.cpu().numpy(), e), "replay %d image %d" % (rep, i)
+        fic.encode(other, 8, 1)          # eager work between replays
+        ws.fill_(0xA5)                   # replays must not depend on stale workspace
+        torch.cuda.synchronize()
+    # new contents under the same pointers: the replay encodes them
+    new0 = np.ascontiguousarray(np.flipud(items[0][0]))
+    imgs[0].copy_(torch.from_numpy(new0))
+    out = fic.encode_batch(imgs, jobs, codes=codes, ws=ws, graph=True)
+    torch.cuda.synchronize()
+    b, t, tol = jobs[0]
+    assert np.array_equal(out[0].cpu().numpy(), _single_codes(fic, new0, b, t, tol))
+    for i in range(1, len(items)):
+        assert np.array_equal(out[i].cpu().numpy(), eager[i])
+
+
+def test_batch_full_64(fic, orc):
+    """The 64-image mixed batch (sizes 128..1024, B in {4, 8}, t = 2,
+    tol = 0.05) in one call: every image equals its single-image encode, and
+    sampled ranges of 8 images equal the oracle."""
+    from synth import batch_descs
+    items = batch_descs(count=64)
+    imgs = [dev(im) for (im, _, _, _) in items]
+    jobs = [(b, t, tol) for (_, b, t, tol) in items]
+    outs = fic.encode_batch(imgs, jobs, graph=True)
+    torch.cuda.synchronize()
+    for m, ((im, b, t, tol), c) in enumerate(zip(items, outs)):
+        got = c.cpu().numpy()
+        assert np.array_equal(got, _single_codes(fic, im, b, t, tol)), "image %d" % m
+        if m % 8 == 3:
+            g = fic.unpack_codes(c)
+            sel = sampled(g.size, 16, seed=m)
+            ref = orc.encode(im, b, t, tol=tol, sel=sel)
+            assert_codes(g, ref, sel=sel, what="batch64 image %d" % m)
 
 
 def test_repeat_determinism(fic):
