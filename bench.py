@@ -1,16 +1,20 @@
 """Benchmark of the range-domain matching search on one MI355X.
 
-One step is one pass of the whole hot path over the workload image:
-  fractal dimension of all ranges and domains (differential box counting),
-  the dynamic pool for each tolerance (sort + window bounds),
-  and for every job (exhaustive, then each pooled tolerance) range prep,
-  domain prep, the persistent MFMA search and finalize.
+Single-image workloads (default: 1024x1024 fBm, 8x8 ranges, step 1,
+exhaustive + FD pools 0.02 / 0.1): one step is one pass of the whole hot
+path over the image -- fractal dimension of all ranges and domains
+(differential box counting) per pooled geometry, the dynamic pool for each
+tolerance (sort + window bounds), and for every job range prep, domain prep,
+the persistent MFMA search and finalize.
+The 64-image mixed workload (--workload batch64_mixed): one step is one
+batch call (classify, pool and prep of every image, one persistent search per
+range size, finalize), replayed as a HIP graph.
 Inputs are resident in HBM before the timed region. The JSON line reports
 pair evaluations per second over the whole step (value), encode seconds per
-image per job, a roofline of the dominant kernel (the exhaustive MFMA search,
+image, a roofline of the dominant kernel (the longest MFMA search launch,
 timed by HIP events the library records on its own stream), the plain
-one-thread-per-pair kernel on the same exhaustive search, and the CPU oracle
-timed on a bounded sample on the host cores.
+one-thread-per-pair kernel on the exhaustive search, and the CPU oracle timed
+on a bounded sample of ranges on the host cores.
 """
 import argparse
 import hashlib
@@ -93,47 +97,115 @@ def main():
         return
 
     wl = WORKLOADS[args.workload]
-    img_np = workload_images(args.workload)
+    if wl.name == "batch64_mixed":
+        out = bench_batch(args, fic, wl)
+    else:
+        out = bench_image(args, fic, wl, workload_images(args.workload))
+    print(json.dumps(out))
+
+
+def job_label(b, t, tol, multi):
+    base = "exhaustive" if tol is None else "pool_%g" % tol
+    return ("b%dt%d_" % (b, t) + base) if multi else base
+
+
+def stage_sums(recs, steps):
+    out = {}
+    for (name, ms) in recs:
+        out[name] = out.get(name, 0.0) + ms / steps
+    return out
+
+
+def progress(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def oracle_rate(img_np, b, t, tol, pool_sizes, D, seconds, what):
+    """The oracle (as it stands) on an evenly spaced sample of ranges of about
+    `seconds` of host work. The sample grows geometrically (at most 8x per
+    run) until one run takes half the budget, so its fixed set-up cost can
+    not make the sample explode; the last run is the reported one."""
+    import numpy as np
+    import oracle
+    oracle.build(force=False)
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+    R = len(pool_sizes)
+    count = min(R, 8)
+    while True:
+        sel = np.linspace(0, R - 1, count).astype(np.int64)
+        t0 = time.perf_counter()
+        oracle.encode(img_np, b, t, tol=tol, sel=sel, nthreads=threads)
+        cpu_s = time.perf_counter() - t0
+        progress("oracle sample of %d ranges: %.2f s" % (count, cpu_s))
+        if cpu_s >= 0.5 * seconds or count >= R:
+            break
+        grow = min(8.0, max(2.0, seconds / max(cpu_s, 1e-3)))
+        count = min(R, int(count * grow))
+    cpu_pairs = int(np.asarray(pool_sizes)[sel].sum()) * 8
+    return {"value": round(cpu_pairs / cpu_s, 1), "unit": "pair evals/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "%s: %d of %d ranges (%d pair evaluations, %.1f s)"
+                      % (what, count, R, cpu_pairs, cpu_s)}
+
+
+def roofline_of(kernel, flops, t_s):
+    achieved = flops / t_s / 1e12
+    return {"kernel": kernel, "bound": "mfma", "achieved": round(achieved, 2),
+            "peak": PEAK_FP16_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_FP16_TFLOPS, 4), "traffic": None,
+            "avg_launch_ms": round(t_s * 1e3, 4), "flop_per_launch": int(flops)}
+
+
+def bench_image(args, fic, wl, img_np):
+    import numpy as np
+    import torch
+
     dev = torch.device("cuda:0")
     img = torch.from_numpy(img_np).to(dev)
     H, W = img_np.shape
     jobs = list(wl.jobs)
+    multi = len(set((b, t) for (b, t, _) in jobs)) > 1
     if args.only:
-        jobs = [j for j in jobs if (("exhaustive" if j[2] is None else "pool_%g" % j[2])
-                                    == args.only)]
+        jobs = [j for j in jobs if job_label(*j, multi) == args.only]
         if not jobs:
             raise SystemExit("no job named %s in %s" % (args.only, wl.name))
-    b0, t0 = jobs[0][0], jobs[0][1]
-    if any((b, t) != (b0, t0) for (b, t, _) in jobs):
-        raise SystemExit("bench workloads share one range size and step per image")
+    geos = []
+    for (b, t, tol) in jobs:
+        if tol is not None and (b, t) not in geos:
+            geos.append((b, t))
     ctx = fic.fic.context(0)
-    R = fic.fic.num_ranges(H, W, b0)
-    D = fic.fic.num_domains(H, W, b0, t0)
-    n = b0 * b0
-    codes = [torch.empty((R, 16), dtype=torch.uint8, device=dev) for _ in jobs]
+    R = {b: fic.fic.num_ranges(H, W, b) for (b, _, _) in jobs}
+    D = {(b, t): fic.fic.num_domains(H, W, b, t) for (b, t, _) in jobs}
+    codes = [torch.empty((R[b], 16), dtype=torch.uint8, device=dev) for (b, _, _) in jobs]
 
     def step(kernel="mfma"):
-        fr, _ = fic.fd_classify(img, b0, b0, want_fp32=False)
-        fd, _ = fic.fd_classify(img, 2 * b0, t0, want_fp32=False)
+        fds = {}
+        for (b, t) in geos:
+            fr, _ = fic.fd_classify(img, b, b, want_fp32=False)
+            fd, _ = fic.fd_classify(img, 2 * b, t, want_fp32=False)
+            fds[(b, t)] = (fr, fd)
         pools = {}
-        for (_, _, tol) in jobs:
+        for (b, t, tol) in jobs:
             if tol is not None:
-                pools[tol] = fic.build_domain_pool(fr, fd, tol)
+                pools[(b, t, tol)] = fic.build_domain_pool(*fds[(b, t)], tol)
         for i, (b, t, tol) in enumerate(jobs):
-            fic.encode_pifs(img, b, t, pool=pools.get(tol), kernel=kernel, codes=codes[i])
+            fic.encode_pifs(img, b, t, pool=pools.get((b, t, tol)), kernel=kernel,
+                            codes=codes[i])
         return pools
 
-    # pair counts per job (from one untimed step)
+    # pair counts and pool sizes per job (from one untimed step)
     pools = step()
     torch.cuda.synchronize()
-    pairs = []
+    pairs, sizes = [], []
     for (b, t, tol) in jobs:
         if tol is None:
-            pairs.append(R * D * 8)
+            sizes.append(np.full(R[b], D[(b, t)], dtype=np.int64))
         else:
-            _, lo, hi = pools[tol]
-            pairs.append(int((hi.long() - lo.long()).sum().item()) * 8)
+            _, lo, hi = pools[(b, t, tol)]
+            sizes.append((hi.long() - lo.long()).cpu().numpy())
+        pairs.append(int(sizes[-1].sum()) * 8)
     pairs_step = sum(pairs)
+    progress("%s: %d jobs, %d pair evaluations per step" % (wl.name, len(jobs), pairs_step))
 
     for _ in range(args.warmup):
         step()
@@ -148,66 +220,64 @@ def main():
     recs = ctx.timing_read()
     ctx.timing(False)
     ms_step = (t_end - t_start) * 1e3 / args.steps
+    progress("timed %d steps: %.3f ms per step" % (args.steps, ms_step))
 
-    # stage times: classify x2, pool x n_pool, then per job 5 encode stages
+    # records per step: classify x2 per classified geometry, one pool per
+    # pooled job, then per job range_prep .. final
     per_step = len(recs) // args.steps
-    stage_ms = {}
+    stage_ms = stage_sums(recs, args.steps)
+    n_cls, n_pool = 2 * len(geos), sum(1 for j in jobs if j[2] is not None)
+    cls_ms = {g: 0.0 for g in geos}
+    pool_ms = {}
     job_ms = [dict() for _ in jobs]
     search_ms = [[] for _ in jobs]
+    pooled_jobs = [j for j in jobs if j[2] is not None]
     for s in range(args.steps):
         chunk = recs[s * per_step:(s + 1) * per_step]
+        for k in range(n_cls):
+            cls_ms[geos[k // 2]] += chunk[k][1] / args.steps
+        for k in range(n_pool):
+            pool_ms[pooled_jobs[k]] = pool_ms.get(pooled_jobs[k], 0.0) + \
+                chunk[n_cls + k][1] / args.steps
         ji = -1
-        for (name, ms) in chunk:
-            stage_ms[name] = stage_ms.get(name, 0.0) + ms / args.steps
+        for (name, ms) in chunk[n_cls + n_pool:]:
             if name == "range_prep":
                 ji += 1
-            if ji >= 0:
-                job_ms[ji][name] = job_ms[ji].get(name, 0.0) + ms / args.steps
+            job_ms[ji][name] = job_ms[ji].get(name, 0.0) + ms / args.steps
             if name == "search":
                 search_ms[ji].append(ms)
-    shared_ms = stage_ms.get("classify", 0.0) + stage_ms.get("pool", 0.0)
 
-    def job_label(tol):
-        return "exhaustive" if tol is None else "pool_%g" % tol
-
-    encode_s = {}
-    job_rate = {}
+    encode_s, job_rate = {}, {}
     for i, (b, t, tol) in enumerate(jobs):
         enc_ms = sum(job_ms[i].values())
-        if tol is not None:   # the pooled job also needs the classification and its pool
-            enc_ms += stage_ms.get("classify", 0.0) + stage_ms.get("pool", 0.0) / max(
-                1, sum(1 for j in jobs if j[2] is not None))
-        encode_s[job_label(tol)] = round(enc_ms / 1e3, 6)
-        job_rate[job_label(tol)] = pairs[i] / (sum(search_ms[i]) / len(search_ms[i]) / 1e3)
+        if tol is not None:   # a pooled job also needs its classification and its pool
+            enc_ms += cls_ms[(b, t)] + pool_ms[(b, t, tol)]
+        lab = job_label(b, t, tol, multi)
+        encode_s[lab] = round(enc_ms / 1e3, 6)
+        job_rate[lab] = pairs[i] / (float(np.mean(search_ms[i])) / 1e3)
 
-    # roofline of the dominant kernel: the exhaustive MFMA search
+    # roofline of the dominant kernel: the search launch that takes longest
     dom = max(range(len(jobs)), key=lambda i: np.mean(search_ms[i]))
+    bd, td, told = jobs[dom]
     t_search = float(np.mean(search_ms[dom])) / 1e3
-    flops = pairs[dom] * 2 * n
-    achieved = flops / t_search / 1e12
-    traffic = measured_traffic()
-    roofline = {"kernel": "k_search_mfma<%d> (%s)" % (b0, job_label(jobs[dom][2])),
-                "bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_FP16_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP16_TFLOPS, 4),
-                "traffic": traffic, "avg_launch_ms": round(t_search * 1e3, 4),
-                "flop_per_launch": flops}
+    roofline = roofline_of("k_search_mfma<%d> (%s)" % (bd, job_label(bd, td, told, multi)),
+                           pairs[dom] * 2 * bd * bd, t_search)
+    if wl.name == "fbm1024_b8t1" and dom == 0:
+        roofline["traffic"] = measured_traffic()
 
     # HBM fraction of the classify and domain-prep stages
-    img_bytes = H * W
-    dfd = ((H - 2 * b0) // t0 + 1) * ((W - 2 * b0) // t0 + 1)
-    rfd = R
-    classify_bytes = 2 * img_bytes + 8 * (dfd + rfd)
-    dprep_bytes = img_bytes + D * (2 * n + 4 + 4 + 8 + 4)
     hbm = {}
-    if stage_ms.get("classify"):
-        gbs = classify_bytes / (stage_ms["classify"] / 1e3) / 1e9
+    if geos:
+        cbytes = sum(2 * H * W + 8 * (R[b] + D[(b, t)]) for (b, t) in geos)
+        gbs = cbytes / (sum(cls_ms.values()) / 1e3) / 1e9
         hbm["classify"] = {"GB/s": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4),
-                           "bytes": classify_bytes}
-    dprep_ms = np.mean([jm.get("domain_prep", 0.0) for jm in job_ms])
-    if dprep_ms:
-        gbs = dprep_bytes / (dprep_ms / 1e3) / 1e9
+                           "bytes": cbytes}
+    dbytes = H * W + D[(bd, td)] * (2 * bd * bd + 4 + 4 + 8 + 4)
+    dms = job_ms[dom].get("domain_prep", 0.0)
+    if dms:
+        gbs = dbytes / (dms / 1e3) / 1e9
         hbm["domain_prep"] = {"GB/s": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4),
-                              "bytes": dprep_bytes}
+                              "bytes": dbytes}
 
     out = {
         "metric": METRIC,
@@ -218,13 +288,12 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f16", "data": "synthetic",
         "config": {"workload": wl.name, "description": wl.description,
-                   "image": "%dx%d" % (H, W), "range_size": b0, "domain_step": t0,
-                   "jobs": [job_label(t) for (_, _, t) in jobs],
+                   "image": "%dx%d" % (H, W),
+                   "jobs": [job_label(b, t, tol, multi) for (b, t, tol) in jobs],
                    "pairs_per_step": pairs_step, "pairs_per_job": pairs},
         "encode_s_per_image": encode_s,
         "search_pairs_per_s": {k: round(v, 1) for k, v in job_rate.items()},
         "stage_ms_per_step": {k: round(v, 4) for k, v in stage_ms.items()},
-        "shared_classify_pool_ms": round(shared_ms, 4),
         "roofline": roofline,
         "hbm_stages": hbm,
     }
@@ -236,7 +305,7 @@ def main():
         torch.cuda.synchronize()
         ctx.set_counters(None)
         c = cnt.cpu().numpy()
-        out["screen"] = {"pairs_screened_16x16": int(c[0]), "exact_evaluations": int(c[1]),
+        out["screen"] = {"pairs_screened": int(c[0]), "exact_evaluations": int(c[1]),
                          "work_items": int(c[2]), "seed_evaluations": int(c[3]),
                          "exact_fraction": float(c[1]) / pairs_step}
 
@@ -244,40 +313,106 @@ def main():
         ex = [i for i, j in enumerate(jobs) if j[2] is None]
         if ex:
             i = ex[0]
-            fic.encode_pifs(img, b0, t0, pool=None, kernel="plain", codes=codes[i])   # warm
+            b, t, _ = jobs[i]
+            fic.encode_pifs(img, b, t, pool=None, kernel="plain", codes=codes[i])   # warm
             torch.cuda.synchronize()
             ctx.timing(True)
-            fic.encode_pifs(img, b0, t0, pool=None, kernel="plain", codes=codes[i])
+            fic.encode_pifs(img, b, t, pool=None, kernel="plain", codes=codes[i])
             torch.cuda.synchronize()
             prec = ctx.timing_read()
             ctx.timing(False)
             p_search = sum(ms for (nme, ms) in prec if nme == "search") / 1e3
             p_total = sum(ms for (nme, ms) in prec) / 1e3
+            lab = job_label(b, t, None, multi)
             out["plain"] = {"exhaustive_search_pairs_per_s": round(pairs[i] / p_search, 1),
                             "exhaustive_encode_s": round(p_total, 6),
-                            "mfma_search_speedup": round(job_rate["exhaustive"] /
-                                                         (pairs[i] / p_search), 3)}
+                            "mfma_search_speedup": round(job_rate[lab] / (pairs[i] / p_search),
+                                                         3)}
 
     if not args.no_cpu:
-        import oracle
-        oracle.build(force=False)
-        threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
-        sel_probe = np.array([R // 2], dtype=np.int64)
-        t0p = time.perf_counter()
-        oracle.encode(img_np, b0, t0, sel=sel_probe, nthreads=threads)
-        per_range = max(time.perf_counter() - t0p, 1e-3)
-        count = int(max(1, min(R, args.cpu_seconds / per_range)))
-        sel = np.linspace(0, R - 1, count).astype(np.int64)
-        t1 = time.perf_counter()
-        oracle.encode(img_np, b0, t0, sel=sel, nthreads=threads)
-        cpu_s = time.perf_counter() - t1
-        cpu_pairs = count * D * 8
-        out["cpu_baseline"] = {
-            "value": round(cpu_pairs / cpu_s, 1), "unit": "pair evals/s", "cores": threads,
-            "kind": "oracle",
-            "sample": "exhaustive search of %d of %d ranges of the %s image (%d pair "
-                      "evaluations, %.1f s)" % (count, R, wl.name, cpu_pairs, cpu_s)}
-    print(json.dumps(out))
+        out["cpu_baseline"] = oracle_rate(
+            img_np, bd, td, told, sizes[dom], D[(bd, td)], args.cpu_seconds,
+            "%s, %s" % (wl.name, job_label(bd, td, told, multi)))
+    return out
+
+
+def bench_batch(args, fic, wl):
+    """One step = one fic_encode_pifs_batch of the 64-image mixed workload
+    (replayed as a HIP graph): classify, pool, prep of every image, one
+    persistent search per range size, finalize."""
+    import numpy as np
+    import torch
+    from synth import batch_descs
+
+    items = batch_descs(count=64, base_seed=wl.seed)
+    dev = torch.device("cuda:0")
+    imgs = [torch.from_numpy(np.ascontiguousarray(im)).to(dev) for (im, _, _, _) in items]
+    jobs = [(b, t, tol) for (_, b, t, tol) in items]
+    ctx = fic.fic.context(0)
+    ws = torch.empty(fic.batch_workspace_bytes(imgs, jobs), dtype=torch.uint8, device=dev)
+    codes = [torch.empty(((im.shape[0] // b) * (im.shape[1] // b), 16), dtype=torch.uint8,
+                         device=dev) for (im, b, _, _) in items]
+    # pair counts: the same classification and pool kernels, image by image
+    sizes, pairs_b = [], {}
+    for x, (b, t, tol) in zip(imgs, jobs):
+        fr, _ = fic.fd_classify(x, b, b, want_fp32=False)
+        fd, _ = fic.fd_classify(x, 2 * b, t, want_fp32=False)
+        _, lo, hi = fic.build_domain_pool(fr, fd, tol)
+        sz = (hi.long() - lo.long()).cpu().numpy()
+        sizes.append(sz)
+        pairs_b[b] = pairs_b.get(b, 0) + int(sz.sum()) * 8
+    pairs_step = sum(pairs_b.values())
+    progress("%s: %d images, %d pair evaluations per step" % (wl.name, len(items), pairs_step))
+
+    def step(graph=True):
+        fic.encode_batch(imgs, jobs, codes=codes, ws=ws, graph=graph)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t_start) * 1e3 / args.steps
+    progress("timed %d steps: %.3f ms per step" % (args.steps, ms_step))
+
+    # stage breakdown from one eager (ungraphed) batch with the library's events
+    ctx.timing(True)
+    step(graph=False)
+    torch.cuda.synchronize()
+    recs = ctx.timing_read()
+    ctx.timing(False)
+    stage_ms = stage_sums(recs, 1)
+    searches = [ms for (name, ms) in recs if name == "search"]
+    order = sorted(pairs_b)                 # one search launch per range size, ascending B
+    launches = {b: ms for b, ms in zip(order, searches)}
+    bd = max(launches, key=lambda b: launches[b])
+    roofline = roofline_of("k_search_mfma<%d> (batch, all B=%d images)" % (bd, bd),
+                           pairs_b[bd] * 2 * bd * bd, launches[bd] / 1e3)
+    out = {
+        "metric": METRIC,
+        "value": round(pairs_step / (ms_step / 1e3), 1),
+        "unit": "pair evals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f16", "data": "synthetic",
+        "config": {"workload": wl.name, "description": wl.description, "images": len(items),
+                   "pairs_per_step": pairs_step,
+                   "pairs_per_range_size": {str(b): v for b, v in pairs_b.items()}},
+        "encode_s_per_image": round(ms_step / 1e3 / len(items), 6),
+        "search_ms_per_range_size": {str(b): round(v, 4) for b, v in launches.items()},
+        "eager_stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+        "roofline": roofline,
+    }
+    if not args.no_cpu:
+        big = max(range(len(items)), key=lambda i: int(sizes[i].sum()))
+        im, b, t, tol = items[big]
+        out["cpu_baseline"] = oracle_rate(im, b, t, tol, sizes[big], None, args.cpu_seconds,
+                                          "batch image %d (%dx%d, B=%d, t=%d, tol %g)"
+                                          % ((big,) + im.shape + (b, t, tol)))
+    return out
 
 
 if __name__ == "__main__":

@@ -11,11 +11,11 @@
 //   domain prep  B columns: the 2x2 sums of each domain (in pool order),
 //                centred by an integer level dhat (|.| <= 1020), FP16 (exact);
 //                per column Sdd', eps = sum D - n*dhat and u = sqrt(Sdd')/n.
-//   search       a persistent work queue of (16-range group, column chunk)
-//                items. The group's A rows stay in VGPRs; each 16-column
-//                block costs MW*KS MFMAs, giving C''' = sum (r-rhat)(D-dhat)
+//   search       a persistent work queue of (range group, column chunk)
+//                items. The group's A rows stay in VGPRs; each MR-column
+//                block costs MB*KS MFMAs, giving C''' = sum (r-rhat)(D-dhat)
 //                exactly in FP32, and Srd' = n*C''' - delta*eps exactly.
-//                A 4-instruction FP32 screen per 16x16 block rejects pairs
+//                A few FP32 instructions per output tile screen out pairs
 //                whose continuous optimum cannot reach the range's best F;
 //                survivors get the exact int64 fit and a packed
 //                (F, domain, isometry) key; keys meet in a global atomicMin.
@@ -36,6 +36,13 @@ constexpr int kBminBlock = 1024; // perm entries per block-minimum
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Allowance of the screen in C''' units: n/4 covers |n*C''' - Srd'| <= n^2/4;
+// 16x16 ranges add 64 for the FP32 sum of their 4 exact partial sums.
+template <int B> constexpr float screen_slack()
+{
+    return Cfg<B>::n / 4.0f + (Cfg<B>::NCH > 1 ? 64.0f : 0.0f);
+}
+
 template <int EPL> struct Frag;
 template <> struct Frag<4> { typedef half4_t type; };
 template <> struct Frag<8> { typedef half8_t type; };
@@ -44,9 +51,9 @@ __device__ __forceinline__ float4_t mma(half8_t a, half8_t b, float4_t c)
 {
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
 }
-__device__ __forceinline__ float4_t mma(half4_t a, half4_t b, float4_t c)
+__device__ __forceinline__ float16_t mma32(half8_t a, half8_t b, float16_t c)
 {
-    return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
 }
 
 __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v)
@@ -103,7 +110,8 @@ __global__ __launch_bounds__(256) void k_range_prep(
     RangeStat *__restrict__ rs)
 {
     using C = Cfg<B>;
-    constexpr int n = C::n, KPI = C::KPI, EPL = C::EPL, KS = C::KS, MW = C::MW, GR = 2 * MW;
+    constexpr int n = C::n, MR = C::MR, KPI = C::KPI, EPL = C::EPL, KS = C::KS, MB = C::MB,
+                  GR = C::GR;
     typedef typename Frag<EPL>::type frag_t;
     const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t s = gt >> 3;
@@ -124,7 +132,8 @@ __global__ __launch_bounds__(256) void k_range_prep(
             }
     const int32_t rhat = (sr + n / 2) / n;
     const int64_t grp = s / GR;
-    const int ls = (int)(s % GR), b = ls >> 1, row = 8 * (ls & 1) + q;
+    int blk, row;
+    a_place<B>((int)(s % GR), q, blk, row);
     const int iq = iso_inverse(q);
     // A_q[u][v] = r[T_q^-1 (u, v)] - rhat, so that sum A_q * D = sum r * T_q(D)
     for (int ks = 0; ks < KS; ++ks)
@@ -137,7 +146,7 @@ __global__ __launch_bounds__(256) void k_range_prep(
                 iso_src(iq, B, K / B, K % B, si, sj);
                 f[e] = valid ? (_Float16)(int)(rp[si * pitch + sj] - rhat) : (_Float16)0;
             }
-            ((frag_t *)A)[((grp * MW + b) * KS + ks) * 64 + g * 16 + row] = f;
+            ((frag_t *)A)[((grp * MB + blk) * KS + ks) * 64 + g * MR + row] = f;
         }
     if (q == 0) {
         RangeStat st;
@@ -160,7 +169,7 @@ __global__ __launch_bounds__(256) void k_domain_prep(
     uint32_t *__restrict__ dom)
 {
     using C = Cfg<B>;
-    constexpr int n = C::n, KPI = C::KPI, EPL = C::EPL, KS = C::KS;
+    constexpr int n = C::n, MR = C::MR, KPI = C::KPI, EPL = C::EPL, KS = C::KS;
     typedef typename Frag<EPL>::type frag_t;
     const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t p = gt / B;
@@ -185,16 +194,26 @@ __global__ __launch_bounds__(256) void k_domain_prep(
     }
     const int64_t sdd_ = (int64_t)n * rs2 - rs1 * rs1;
     const int32_t dhat = (int32_t)((rs1 + n / 2) / n);
-    const int64_t cb = p >> 4;
-    const int c = (int)(p & 15);
+    const int64_t cb = p / MR;
+    const int c = (int)(p % MR);
+    // pixel row i holds K = i*B .. i*B + B-1: whole fragments when B >= EPL,
+    // else part of one fragment
+    if constexpr (B >= EPL) {
 #pragma unroll
-    for (int f0 = 0; f0 < B; f0 += EPL) {
-        const int K0 = i * B + f0;
+        for (int f0 = 0; f0 < B; f0 += EPL) {
+            const int K0 = i * B + f0;
+            const int ks = K0 / KPI, g = (K0 % KPI) / EPL;
+            frag_t f;
+#pragma unroll
+            for (int e = 0; e < EPL; ++e) f[e] = (_Float16)(valid ? v[f0 + e] - dhat : 0);
+            ((frag_t *)Bm)[(cb * KS + ks) * 64 + g * MR + c] = f;
+        }
+    } else {
+        const int K0 = i * B;
         const int ks = K0 / KPI, g = (K0 % KPI) / EPL;
-        frag_t f;
+        _Float16 *dst = Bm + ((cb * KS + ks) * 64 + g * MR + c) * EPL + K0 % EPL;
 #pragma unroll
-        for (int e = 0; e < EPL; ++e) f[e] = (_Float16)(valid ? v[f0 + e] - dhat : 0);
-        ((frag_t *)Bm)[(cb * KS + ks) * 64 + g * 16 + c] = f;
+        for (int e = 0; e < B; ++e) dst[e] = (_Float16)(valid ? v[e] - dhat : 0);
     }
     if (i == 0) {
         u[p] = valid ? screen_u(sdd_, n) : 1e30f;   // padding: always masked (p >= hi)
@@ -219,15 +238,23 @@ __global__ void k_blockmin(const uint32_t *__restrict__ perm, int64_t D, uint32_
     if (lane == 0) bmin[blk] = m;
 }
 
-__device__ uint32_t pool_min_index(const uint32_t *perm, const uint32_t *bmin, uint32_t lo,
-                                   uint32_t hi)
+// Lowest domain index in pool positions [lo, hi), by the whole wave: the
+// partial blocks at both ends from perm, the whole blocks from their minima.
+// Every lane returns the result.
+__device__ uint32_t pool_min_wave(const uint32_t *perm, const uint32_t *bmin, uint32_t lo,
+                                  uint32_t hi, int lane)
 {
     if (!perm) return lo;
     uint32_t m = 0xffffffffu;
-    uint32_t i = lo;
-    while (i < hi && (i % kBminBlock) != 0) m = min(m, perm[i++]);
-    while (i + kBminBlock <= hi) { m = min(m, bmin[i / kBminBlock]); i += kBminBlock; }
-    while (i < hi) m = min(m, perm[i++]);
+    const uint32_t kb = (uint32_t)kBminBlock;
+    uint32_t head = (lo + kb - 1) / kb * kb;
+    if (head > hi) head = hi;
+    const uint32_t mid = head + (hi - head) / kb * kb;
+    for (uint32_t i = lo + lane; i < head; i += 64) m = min(m, perm[i]);
+    for (uint32_t b = head / kb + lane; b < mid / kb; b += 64) m = min(m, bmin[b]);
+    for (uint32_t i = mid + lane; i < hi; i += 64) m = min(m, perm[i]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = min(m, (uint32_t)__shfl_xor((int)m, off));
     return m;
 }
 
@@ -269,30 +296,34 @@ __global__ __launch_bounds__(256) void k_seed(const _Float16 *__restrict__ A,
                                               u64 *__restrict__ keys, u64 *counters)
 {
     using C = Cfg<B>;
-    constexpr int n = C::n, KPI = C::KPI, EPL = C::EPL, KS = C::KS, MW = C::MW, GR = 2 * MW;
+    constexpr int n = C::n, MR = C::MR, KPI = C::KPI, EPL = C::EPL, KS = C::KS, MB = C::MB,
+                  GR = C::GR;
     typedef typename Frag<EPL>::type frag_t;
     const int64_t s = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
     if (s >= Rp) return;
     const RangeStat st = rs[s];
-    if (st.flags & (kPad | kEmpty | kFlat)) {
-        if (lane == 0)
-            keys[s] = (st.flags & (kPad | kEmpty))
-                          ? kNoKey
-                          : pack_key(0, pool_min_index(perm, bmin, st.lo, st.hi), 0, shift);
+    if (st.flags & (kPad | kEmpty)) {
+        if (lane == 0) keys[s] = kNoKey;
+        return;
+    }
+    const uint32_t dmin = pool_min_wave(perm, bmin, st.lo, st.hi, lane);
+    if (st.flags & kFlat) {
+        if (lane == 0) keys[s] = pack_key(0, dmin, 0, shift);
         return;
     }
     const int q = lane & 7, cand = lane >> 3;
     const uint32_t p = st.lo + (uint32_t)(((uint64_t)(st.hi - st.lo) * (2 * cand + 1)) / 16);
     const int64_t grp = s / GR;
-    const int ls = (int)(s % GR), b = ls >> 1, row = 8 * (ls & 1) + q;
-    const frag_t *ap = (const frag_t *)A + ((grp * MW + b) * KS) * 64 + row;
-    const frag_t *bp = (const frag_t *)Bm + ((int64_t)(p >> 4) * KS) * 64 + (p & 15);
+    int blk, row;
+    a_place<B>((int)(s % GR), q, blk, row);
+    const frag_t *ap = (const frag_t *)A + ((grp * MB + blk) * KS) * 64 + row;
+    const frag_t *bp = (const frag_t *)Bm + ((int64_t)(p / MR) * KS) * 64 + (p % MR);
     int32_t cx = 0;
     for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
         for (int g = 0; g < KPI / EPL; ++g) {
-            const frag_t fa = ap[ks * 64 + g * 16], fb = bp[ks * 64 + g * 16];
+            const frag_t fa = ap[ks * 64 + g * MR], fb = bp[ks * 64 + g * MR];
 #pragma unroll
             for (int e = 0; e < EPL; ++e) cx += (int32_t)(float)fa[e] * (int32_t)(float)fb[e];
         }
@@ -306,7 +337,10 @@ __global__ __launch_bounds__(256) void k_seed(const _Float16 *__restrict__ A,
         key = o < key ? o : key;
     }
     if (lane == 0) {
-        keys[s] = key;
+        // every pair reaches F = 4096*Srr' at k = 0, so the lowest pool
+        // domain under isometry 0 is a real candidate with that F
+        const u64 dc = pack_key(4096 * st.srr, dmin, 0, shift);
+        keys[s] = key < dc ? key : dc;
         if (counters) atomicAdd(&counters[3], 64ull);
     }
 }
@@ -330,10 +364,11 @@ struct SearchArgs {
 };
 
 // Per group: the union [L, H) of its active ranges' intervals (rounded to
-// 16-column blocks) and their intersection [ilo, ihi) (blocks inside it need
-// no per-range mask). Groups without an active range get L = H = Dp.
+// column blocks of width bw, a power of two) and their intersection
+// [ilo, ihi) (blocks inside it need no per-range mask). Groups without an
+// active range get L = H = Dp.
 __global__ void k_group_bounds(const RangeStat *__restrict__ rs, int64_t G, int GR, uint32_t Dp,
-                               uint4 *__restrict__ grp)
+                               uint32_t bw, uint4 *__restrict__ grp)
 {
     const int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gi >= G) return;
@@ -348,7 +383,8 @@ __global__ void k_group_bounds(const RangeStat *__restrict__ rs, int64_t G, int 
         ilo = max(ilo, st.lo);
         ihi = min(ihi, st.hi);
     }
-    grp[gi] = any ? make_uint4(L & ~15u, (H + 15u) & ~15u, ilo, ihi) : make_uint4(Dp, Dp, 0, 0);
+    grp[gi] = any ? make_uint4(L & ~(bw - 1u), (H + bw - 1u) & ~(bw - 1u), ilo, ihi)
+                  : make_uint4(Dp, Dp, 0, 0);
 }
 
 // Per column chunk c: the run of groups [gf, gl] that touch it (both ends
@@ -434,10 +470,10 @@ __global__ __launch_bounds__(256) void k_item_bases(const SearchArgs *__restrict
 
 template <int B> struct WaveState {
     typedef typename Frag<Cfg<B>::EPL>::type frag_t;
-    frag_t af[Cfg<B>::MW][Cfg<B>::KS];
-    float T[Cfg<B>::MW];
-    uint32_t lo[Cfg<B>::MW], hi[Cfg<B>::MW];
-    u64 best[Cfg<B>::MW];
+    frag_t af[Cfg<B>::MB][Cfg<B>::KS];
+    float T[Cfg<B>::MB];
+    uint32_t lo[Cfg<B>::MB], hi[Cfg<B>::MB];
+    u64 best[Cfg<B>::MB];
     uint32_t grp;
     u64 survivors;
     u64 screened;
@@ -446,11 +482,11 @@ template <int B> struct WaveState {
 // Exact treatment of the elements of one column block that passed the screen.
 template <int B, bool MASK>
 __device__ __forceinline__ void take_survivors(const SearchArgs &a, WaveState<B> &st,
-                                               const float4_t (&acc)[Cfg<B>::MW][Cfg<B>::NCH],
+                                               const float4_t (&acc)[Cfg<B>::MB][Cfg<B>::NCH],
                                                int cb, float u, float slack)
 {
     using C = Cfg<B>;
-    constexpr int n = C::n, MW = C::MW, NCH = C::NCH, GR = 2 * MW;
+    constexpr int n = C::n, MW = C::MB, NCH = C::NCH, GR = C::GR;
     const int lane = threadIdx.x & 63, hl = lane >> 5, col = lane & 15;
     const int isob = ((lane >> 4) & 1) * 4;
     const uint32_t p = (uint32_t)cb * 16 + col;
@@ -502,8 +538,8 @@ __device__ __forceinline__ void screen_block(const SearchArgs &a, WaveState<B> &
                                              float u, int cb)
 {
     using C = Cfg<B>;
-    constexpr int n = C::n, MW = C::MW, NCH = C::NCH, KPC = C::KS / NCH;
-    const float slack = n / 4.0f + (NCH > 1 ? 64.0f : 0.0f);
+    constexpr int n = C::n, MW = C::MB, NCH = C::NCH, KPC = C::KS / NCH;
+    const float slack = screen_slack<B>();
     const int col = threadIdx.x & 15;
     float4_t acc[MW][NCH];
 #pragma unroll
@@ -593,7 +629,7 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma(const SearchArgs *__rest
                                                         u64 *counters)
 {
     using C = Cfg<B>;
-    constexpr int MW = C::MW, KS = C::KS, GR = 2 * MW;
+    constexpr int MW = C::MB, KS = C::KS, GR = C::GR;
     typedef typename WaveState<B>::frag_t frag_t;
     const int lane = threadIdx.x & 63, hl = lane >> 5;
     const uint32_t nitems = base[n_img];
@@ -660,6 +696,298 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma(const SearchArgs *__rest
             atomicAdd(&counters[2], items_done);
         }
     }
+}
+
+// ---------------- 32 x 32 tiles (4x4 ranges, K = 16 = one MFMA)
+// A wave owns GR = 4*MB ranges: row block blk holds the range quad 4*blk ..
+// 4*blk+3 under the 8 isometries. Lane l's 16 outputs of a tile are column
+// l%32 against range 4*blk + 2*(l/32) (v < 8) and that + 1 (v >= 8), under
+// isometry v%8. Per block: MB MFMAs, then per lane and range half one
+// 8-value maximum, one fma and one compare.
+// A 4x4 range meets many near-optimal domains, so cells pass the screen far
+// more often than for larger ranges. A passing cell (range, column) is not
+// fitted in place -- that would run the exact int64 fit on the whole wave
+// for a few lanes -- but appended with its 8 cross terms to a per-wave queue
+// in LDS; when the queue holds a wave's worth, every lane fits one queued
+// cell (out of line, so the hot loop stays small), the best keys (kept in
+// LDS) take an LDS atomic minimum, and the refreshed thresholds come back
+// through LDS.
+constexpr int kQueue = 128;          // queued cells per wave (>= 2 waves' worth)
+
+template <int B> struct Queue32 {
+    float c[8][kQueue];              // the cell's cross term under isometry q
+    uint32_t p[kQueue];              // column
+    uint32_t ls[kQueue];             // range within the wave's group
+    u64 best[Cfg<B>::GR];            // best keys of the wave's ranges
+    float T[Cfg<B>::GR];             // their thresholds
+};
+
+template <class T> __device__ __forceinline__ const __attribute__((address_space(1))) T *
+as_global(const T *p)
+{
+    return (const __attribute__((address_space(1))) T *)p;
+}
+
+template <int B> struct Wave32 {
+    static constexpr int MB = Cfg<B>::MB;
+    half8_t af[MB];
+    float T[MB][2];
+    uint32_t lo[MB][2], hi[MB][2];
+    uint32_t grp;
+    uint32_t qn;                     // queued cells (wave-uniform)
+    u64 survivors, screened;
+};
+
+__device__ __forceinline__ float max8(const float16_t &a, int base)
+{
+    const float x = fmaxf(fmaxf(fabsf(a[base + 0]), fabsf(a[base + 1])), fabsf(a[base + 2]));
+    const float y = fmaxf(fmaxf(fabsf(a[base + 3]), fabsf(a[base + 4])), fabsf(a[base + 5]));
+    return fmaxf(fmaxf(x, y), fmaxf(fabsf(a[base + 6]), fabsf(a[base + 7])));
+}
+
+// Fit the nq queued cells of group grp (one per lane, 64 at a time), fold
+// the keys into the LDS best keys, and write the wave's thresholds to LDS.
+template <int B>
+__device__ __noinline__ void flush32(const SearchArgs *ta, uint32_t grp, uint32_t nq,
+                                     Queue32<B> *qu)
+{
+    constexpr int n = Cfg<B>::n, GR = Cfg<B>::GR;
+    const int lane = threadIdx.x & 63;
+    const SearchArgs a = *ta;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    for (uint32_t b0 = 0; b0 < nq; b0 += 64) {
+        const uint32_t e = b0 + (uint32_t)lane;
+        if (e < nq) {
+            const uint32_t ls = qu->ls[e], p = qu->p[e];
+            const int64_t slot = (int64_t)grp * GR + ls;
+            const int64_t srr = a.rs[slot].srr;
+            const int32_t delta = a.rs[slot].delta;
+            const int64_t sdd = a.sdd[p];
+            const int32_t ep = a.eps[p];
+            const uint32_t d = a.dom[p];
+            u64 cand = kNoKey;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int64_t srd = (int64_t)n * (int64_t)qu->c[q][e] - (int64_t)delta * ep;
+                int k;
+                const int64_t f = fit_f(srr, srd, sdd, k);
+                const u64 key = pack_key(f, d, q, a.shift);
+                cand = key < cand ? key : cand;
+            }
+            atomicMin(&qu->best[ls], cand);
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    if (lane < GR) {
+        const u64 bk = qu->best[lane];
+        qu->T[lane] = bk == kNoKey ? 0.0f
+                                   : screen_t(a.rs[(int64_t)grp * GR + lane].srr,
+                                              (int64_t)(bk >> a.shift));
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
+template <int B>
+__device__ __forceinline__ void flush_and_refresh(const SearchArgs *ta, Wave32<B> &st,
+                                                  Queue32<B> *qu)
+{
+    constexpr int MB = Cfg<B>::MB;
+    const int h = (threadIdx.x >> 5) & 1;
+    flush32<B>(ta, st.grp, st.qn, qu);
+    st.survivors += (threadIdx.x & 63) == 0 ? 8ull * st.qn : 0ull;
+    st.qn = 0;
+#pragma unroll
+    for (int blk = 0; blk < MB; ++blk)
+#pragma unroll
+        for (int hl = 0; hl < 2; ++hl)
+            if (st.T[blk][hl] != __builtin_inff())      // searched ranges only
+                st.T[blk][hl] = qu->T[4 * blk + 2 * h + hl];
+}
+
+template <int B, bool MASK>
+__device__ __forceinline__ void screen32(const SearchArgs &a, const SearchArgs *ta,
+                                         Wave32<B> &st, Queue32<B> *qu, half8_t bf, float u,
+                                         int cb)
+{
+    constexpr int MB = Cfg<B>::MB;
+    const float slack = screen_slack<B>();
+    const int lane = threadIdx.x & 63, h = lane >> 5;
+    float16_t acc[MB];
+#pragma unroll
+    for (int blk = 0; blk < MB; ++blk) {
+        float16_t z;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) z[e] = 0.0f;
+        acc[blk] = mma32(st.af[blk], bf, z);
+    }
+    const uint32_t p = (uint32_t)cb * 32 + (lane & 31);
+    bool pass[MB][2];
+    bool hit = false;
+#pragma unroll
+    for (int blk = 0; blk < MB; ++blk)
+#pragma unroll
+        for (int hl = 0; hl < 2; ++hl) {
+            bool ok = max8(acc[blk], 8 * hl) >= fmaf(st.T[blk][hl], u, -slack);
+            if (MASK) ok = ok && p >= st.lo[blk][hl] && p < st.hi[blk][hl];
+            pass[blk][hl] = ok;
+            hit = hit || ok;
+        }
+    if (!__any(hit)) return;
+    // append the passing cells (at most 64 per row block half)
+#pragma unroll
+    for (int blk = 0; blk < MB; ++blk)
+#pragma unroll
+        for (int hl = 0; hl < 2; ++hl) {
+            const u64 ball = __ballot(pass[blk][hl]);
+            if (ball == 0) continue;
+            const uint32_t cnt = (uint32_t)__popcll(ball);
+            if (st.qn + cnt > (uint32_t)kQueue) flush_and_refresh<B>(ta, st, qu);
+            if (pass[blk][hl]) {
+                const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+                    (uint32_t)(ball >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ball, 0u));
+                const uint32_t pos = st.qn + below;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) qu->c[q][pos] = acc[blk][8 * hl + q];
+                qu->p[pos] = p;
+                qu->ls[pos] = (uint32_t)(4 * blk + 2 * h + hl);
+            }
+            st.qn += cnt;
+        }
+}
+
+// Column blocks [cb_begin, cb_end): the B fragment and u of the block PD
+// ahead are loaded while a block computes (a 4x4 block is cheap, so the
+// loads need a deep queue to hide the L2 latency).
+template <int B, bool MASK>
+__device__ __forceinline__ void scan32(const SearchArgs &a, const SearchArgs *ta, Wave32<B> &st,
+                                       Queue32<B> *qu, int cb_begin, int cb_end)
+{
+    constexpr int PD = 4;
+    if (cb_begin >= cb_end) return;
+    const int lane = threadIdx.x & 63, col = lane & 31;
+    const auto *bbase = as_global((const half8_t *)a.Bm) + lane;
+    const auto *ubase = as_global(a.u) + col;
+    const int last = cb_end - 1;
+    half8_t b0, b1, b2, b3;
+    float u0, u1, u2, u3;
+    b0 = bbase[(int64_t)min(cb_begin + 0, last) * 64];
+    b1 = bbase[(int64_t)min(cb_begin + 1, last) * 64];
+    b2 = bbase[(int64_t)min(cb_begin + 2, last) * 64];
+    b3 = bbase[(int64_t)min(cb_begin + 3, last) * 64];
+    u0 = ubase[(int64_t)min(cb_begin + 0, last) * 32];
+    u1 = ubase[(int64_t)min(cb_begin + 1, last) * 32];
+    u2 = ubase[(int64_t)min(cb_begin + 2, last) * 32];
+    u3 = ubase[(int64_t)min(cb_begin + 3, last) * 32];
+    int cb = cb_begin;
+#define FIC_STEP32(BQ, UQ, I)                                                         \
+    {                                                                                 \
+        const half8_t bc = BQ;                                                        \
+        const float uc = UQ;                                                          \
+        const int nx = min(cb + (I) + PD, last);                                      \
+        BQ = bbase[(int64_t)nx * 64];                                                 \
+        UQ = ubase[(int64_t)nx * 32];                                                 \
+        screen32<B, MASK>(a, ta, st, qu, bc, uc, cb + (I));                           \
+    }
+    for (; cb + PD <= cb_end; cb += PD) {
+        FIC_STEP32(b0, u0, 0)
+        FIC_STEP32(b1, u1, 1)
+        FIC_STEP32(b2, u2, 2)
+        FIC_STEP32(b3, u3, 3)
+    }
+#undef FIC_STEP32
+    if (cb + 0 < cb_end) screen32<B, MASK>(a, ta, st, qu, b0, u0, cb + 0);
+    if (cb + 1 < cb_end) screen32<B, MASK>(a, ta, st, qu, b1, u1, cb + 1);
+    if (cb + 2 < cb_end) screen32<B, MASK>(a, ta, st, qu, b2, u2, cb + 2);
+}
+
+template <int B>
+__global__ __launch_bounds__(256, 2) void k_search_mfma32(const SearchArgs *__restrict__ tab,
+                                                          const uint32_t *__restrict__ base,
+                                                          int32_t n_img, uint32_t *item_ctr,
+                                                          u64 *counters)
+{
+    constexpr int MB = Cfg<B>::MB, GR = Cfg<B>::GR;
+    __shared__ Queue32<B> queues[4];
+    const int lane = threadIdx.x & 63, h = lane >> 5;
+    Queue32<B> *qu = &queues[threadIdx.x >> 6];
+    const uint32_t nitems = base[n_img];
+    Wave32<B> st;
+    st.survivors = 0;
+    st.screened = 0;
+    st.qn = 0;
+    u64 items_done = 0;
+    for (;;) {
+        uint32_t item = 0;
+        if (lane == 0) item = atomicAdd(item_ctr, 1u);
+        item = __builtin_amdgcn_readfirstlane(item);
+        if (item >= nitems) break;
+        int ia = 0, ib = n_img;              // last image whose base <= item
+        while (ib - ia > 1) {
+            const int m = (ia + ib) >> 1;
+            if (base[m] <= item) ia = m; else ib = m;
+        }
+        ia = __builtin_amdgcn_readfirstlane(ia);
+        const SearchArgs *ta = tab + ia;
+        const SearchArgs a = *ta;
+        const WorkItem wi = a.items[item - base[ia]];
+        st.grp = wi.grp;
+        const half8_t *ap = (const half8_t *)a.A + (int64_t)st.grp * MB * 64 + lane;
+#pragma unroll
+        for (int blk = 0; blk < MB; ++blk) st.af[blk] = ap[blk * 64];
+        if (lane < GR) qu->best[lane] = a.keys[(int64_t)st.grp * GR + lane];
+#pragma unroll
+        for (int blk = 0; blk < MB; ++blk)
+#pragma unroll
+            for (int hl = 0; hl < 2; ++hl) {
+                const int64_t slot = (int64_t)st.grp * GR + 4 * blk + 2 * h + hl;
+                const RangeStat rsx = a.rs[slot];
+                const u64 bk = a.keys[slot];
+                st.lo[blk][hl] = rsx.lo;
+                st.hi[blk][hl] = rsx.hi;
+                const bool act = !(rsx.flags & (kPad | kFlat | kEmpty));
+                st.T[blk][hl] = !act ? __builtin_inff()
+                                     : (bk == kNoKey ? 0.0f
+                                                     : screen_t(rsx.srr, (int64_t)(bk >> a.shift)));
+            }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        const uint4 gb = a.grp[st.grp];
+        const int cb0 = (int)(wi.c0 >> 5), cb1 = (int)(wi.c1 >> 5);
+        // column blocks fully inside every active range's pool need no mask
+        int ib0 = (int)((gb.z + 31u) >> 5), ib1 = (int)(gb.w >> 5);
+        ib0 = min(max(ib0, cb0), cb1);
+        ib1 = max(min(ib1, cb1), ib0);
+        st.screened += (u64)(cb1 - cb0) * 32 * GR * 8;
+        scan32<B, true>(a, ta, st, qu, cb0, ib0);
+        scan32<B, false>(a, ta, st, qu, ib0, ib1);
+        scan32<B, true>(a, ta, st, qu, ib1, cb1);
+        if (st.qn) flush_and_refresh<B>(ta, st, qu);
+        if (lane < GR) {
+            const u64 bk = qu->best[lane];
+            if (bk != kNoKey) atomicMin(&a.keys[(int64_t)st.grp * GR + lane], bk);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        items_done += 1;
+    }
+    if (counters) {
+        u64 sv = st.survivors;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) sv += __shfl_xor(sv, off);
+        if (lane == 0) {
+            atomicAdd(&counters[0], st.screened);
+            atomicAdd(&counters[1], sv);
+            atomicAdd(&counters[2], items_done);
+        }
+    }
+}
+
+// The search kernel of a range size: 32x32 tiles for 4x4 ranges, 16x16
+// tiles otherwise.
+template <int B> const void *search_kernel()
+{
+    if constexpr (Cfg<B>::MR == 32)
+        return reinterpret_cast<const void *>(&k_search_mfma32<B>);
+    else
+        return reinterpret_cast<const void *>(&k_search_mfma<B>);
 }
 
 // ------------------------------------------------------------ plain search
@@ -869,7 +1197,7 @@ hipError_t prep_b(const EncodePlan &p, const uint8_t *img, const uint32_t *perm,
     hipLaunchKernelGGL(k_seed<B>, dim3(blocks_for(p.Rp * 64, th)), dim3(th), 0, s, A, Bm, rs, eps,
                        sdd, dom, p.Rp, perm, bmin, p.shift, keys, counters);
     hipLaunchKernelGGL(k_group_bounds, dim3(blocks_for(p.G, th)), dim3(th), 0, s, rs, p.G,
-                       (int)p.GR, (uint32_t)p.Dp, grp);
+                       (int)p.GR, (uint32_t)p.Dp, (uint32_t)Cfg<B>::MR, grp);
     hipLaunchKernelGGL(k_chunk_span, dim3(blocks_for(p.NC, th)), dim3(th), 0, s, grp, p.G, p.NC,
                        chunkcnt, chunkfill);
     // exclusive scan of the per-chunk counts; the total is the item count
@@ -890,8 +1218,7 @@ int g_per_cu[3] = {0, 0, 0};
 template <int B> hipError_t occupancy_of(int &out)
 {
     int v = 0;
-    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &v, reinterpret_cast<const void *>(&k_search_mfma<B>), 256, 0);
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, search_kernel<B>(), 256, 0);
     out = v < 1 ? 1 : v;
     return e;
 }
@@ -907,8 +1234,12 @@ hipError_t search_b(const SearchArgs *tab, int32_t n, uint32_t *base, uint32_t *
     if (per_cu < 1) return hipErrorNotInitialized;
     hipLaunchKernelGGL(k_item_bases, dim3(1), dim3(256), 0, s, tab, n, base);
     trace(tr, FIC_STAGE_SEARCH, 1, s);
-    hipLaunchKernelGGL(k_search_mfma<B>, dim3(per_cu * num_cu), dim3(256), 0, s, tab,
-                       (const uint32_t *)base, n, item_ctr, counters);
+    if constexpr (Cfg<B>::MR == 32)
+        hipLaunchKernelGGL(k_search_mfma32<B>, dim3(per_cu * num_cu), dim3(256), 0, s, tab,
+                           (const uint32_t *)base, n, item_ctr, counters);
+    else
+        hipLaunchKernelGGL(k_search_mfma<B>, dim3(per_cu * num_cu), dim3(256), 0, s, tab,
+                           (const uint32_t *)base, n, item_ctr, counters);
     trace(tr, FIC_STAGE_SEARCH, 0, s);
     return hipGetLastError();
 }
@@ -964,11 +1295,11 @@ void plan_encode(const Geom &g, int pooled, EncodePlan &p)
 {
     p.g = g;
     p.pooled = pooled;
-    const int mw = g.b == 16 ? Cfg<16>::MW : Cfg<8>::MW;
-    p.GR = 2 * mw;
+    p.GR = g.b == 16 ? Cfg<16>::GR : g.b == 8 ? Cfg<8>::GR : Cfg<4>::GR;
+    const int mr = g.b == 16 ? Cfg<16>::MR : g.b == 8 ? Cfg<8>::MR : Cfg<4>::MR;
     p.Rp = (g.R + p.GR - 1) / p.GR * p.GR;
     p.G = p.Rp / p.GR;
-    p.Dp = (g.D + 15) / 16 * 16;
+    p.Dp = (g.D + mr - 1) / mr * mr;
     p.chunk = kChunk;
     p.NC = (p.Dp + kChunk - 1) / kChunk;
     p.max_items = p.G * p.NC;

@@ -20,6 +20,7 @@ typedef unsigned long long u64;
 typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
 typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
+typedef float float16_t __attribute__((ext_vector_type(16)));
 
 constexpr int kWave = 64;
 constexpr u64 kNoKey = ~0ull;
@@ -27,21 +28,50 @@ constexpr u64 kNoKey = ~0ull;
 // ---------------------------------------------------------------------------
 // Operand layout of the matrix-core search, per range size B (n = B*B).
 // The cross term of a (range, isometry) row with a domain column is a dot
-// product over K = n pixels; it runs as 16x16 output blocks.
-//   KPI  K consumed by one MFMA (32 for 16x16x32 f16, 16 for 16x16x16 f16)
-//   EPL  halves each lane contributes per MFMA
-//   KS   MFMAs per 16x16 block (n / KPI)
-//   MW   16-row blocks per wave (each block = 2 ranges x 8 isometries)
-//   NCH  independent FP32 accumulators: a sum of 64 products of a centred
-//        pixel (|.| <= 255) and a centred 2x2 sum (|.| <= 1020) stays below
-//        2^24, so each 64-element chunk is exact; n = 256 keeps 4 of them.
-// Element (ks, g, e) of a lane group g = lane/16 is pixel K = ks*KPI + g*EPL + e
-// of the block in row-major order, for the A (rows) and B (columns) operand
+// product over K = n pixels, run as MR x MR output tiles:
+//   MR   tile side: 16 (v_mfma_f32_16x16x32_f16) for 8x8 and 16x16 ranges;
+//        32 (v_mfma_f32_32x32x16_f16, whose K = 16 is exactly one 4x4
+//        range) for 4x4 ranges
+//   KPI  K consumed by one MFMA; EPL halves per lane per MFMA (MR*KPI/64)
+//   KS   MFMAs per tile (n / KPI)
+//   MB   MR-row blocks per wave; GR ranges per wave. A 16-row block holds
+//        2 ranges x 8 isometries, a 32-row block 4 ranges x 8 isometries.
+//   NCH  independent FP32 accumulators per row block: a sum of 64 products of
+//        a centred pixel (|.| <= 255) and a centred 2x2 sum (|.| <= 1020) stays
+//        below 2^24, so each 64-element chunk is exact; n = 256 keeps 4.
+// Element (ks, kg, e) of lane kg*MR + r is pixel K = ks*KPI + kg*EPL + e of
+// the block in row-major order, for the A (rows) and B (columns) operand
 // alike, so their products pair up pixel by pixel.
 template <int B> struct Cfg;
-template <> struct Cfg<4>  { static constexpr int n = 16,  KPI = 16, EPL = 4, KS = 1, MW = 8, NCH = 1; };
-template <> struct Cfg<8>  { static constexpr int n = 64,  KPI = 32, EPL = 8, KS = 2, MW = 8, NCH = 1; };
-template <> struct Cfg<16> { static constexpr int n = 256, KPI = 32, EPL = 8, KS = 8, MW = 4, NCH = 4; };
+template <> struct Cfg<4> {
+    static constexpr int n = 16, MR = 32, KPI = 16, EPL = 8, KS = 1, MB = 4, NCH = 1, GR = 16;
+};
+template <> struct Cfg<8> {
+    static constexpr int n = 64, MR = 16, KPI = 32, EPL = 8, KS = 2, MB = 8, NCH = 1, GR = 16;
+};
+template <> struct Cfg<16> {
+    static constexpr int n = 256, MR = 16, KPI = 32, EPL = 8, KS = 8, MB = 2, NCH = 4, GR = 4;
+};
+
+// Row of range ls (0..GR-1 of its wave group) under isometry q: row block
+// blk and row inside it.
+//   MR = 16: rows 8*(ls%2) + q. Lane l of the 16x16 output (rows 4*(l/16)
+//            .. +3) sees range ls%2 = l/32 under isometries 4*((l/16)%2) + v.
+//   MR = 32: the output of lane l holds rows 8*(v/4) + 4*(l/32) + v%4,
+//            v = 0..15; the placement below makes v < 8 range 2*(l/32) and
+//            v >= 8 range 2*(l/32) + 1 of the quad, isometry v % 8.
+template <int B>
+__host__ __device__ inline void a_place(int ls, int q, int &blk, int &row)
+{
+    if (Cfg<B>::MR == 32) {
+        const int rl = ls & 3;
+        blk = ls >> 2;
+        row = 8 * (2 * (rl & 1) + (q >> 2)) + 4 * (rl >> 1) + (q & 3);
+    } else {
+        blk = ls >> 1;
+        row = 8 * (ls & 1) + q;
+    }
+}
 
 // Per-range state, in search order ("slot"). 32 bytes.
 struct RangeStat {
