@@ -467,80 +467,112 @@ __global__ __launch_bounds__(256) void k_item_bases(const SearchArgs *__restrict
 }
 
 // ------------------------------------------------------------ MFMA search
+// Both tile shapes screen every (range, column) cell of a block and append
+// the cells that pass to a per-wave queue in LDS, with their exact cross
+// terms; when the queue holds a wave's worth of cells, every lane fits one of
+// them exactly (out of line, so the hot loop stays small and unrolled), the
+// wave's best keys (in LDS) take an LDS atomic minimum, and the refreshed
+// thresholds come back through LDS. Fitting a passing cell in place would run
+// the exact int64 fit on the whole wave for the few lanes that passed.
+constexpr int kQueue = 128;          // queued cells per wave (>= 2 waves' worth)
+
+template <class T> __device__ __forceinline__ const __attribute__((address_space(1))) T *
+as_global(const T *p)
+{
+    return (const __attribute__((address_space(1))) T *)p;
+}
+
+// ---------------- 16 x 16 tiles (8x8 and 16x16 ranges)
+// A wave owns GR = 2*MB ranges: row block b holds ranges 2b and 2b+1 under
+// the 8 isometries. Lane l of a tile sees column l%16 against range
+// 2b + l/32 under isometries 4*((l/16)%2) .. +3, i.e. half of a cell.
+template <int B> struct Queue16 {
+    int32_t c[4][kQueue];            // exact cross terms of the half cell
+    uint32_t p[kQueue];              // column
+    uint32_t lq[kQueue];             // range within the group | isometry base << 8
+    u64 best[Cfg<B>::GR];            // best keys of the wave's ranges
+    float T[Cfg<B>::GR];             // their thresholds
+};
 
 template <int B> struct WaveState {
     typedef typename Frag<Cfg<B>::EPL>::type frag_t;
     frag_t af[Cfg<B>::MB][Cfg<B>::KS];
     float T[Cfg<B>::MB];
     uint32_t lo[Cfg<B>::MB], hi[Cfg<B>::MB];
-    u64 best[Cfg<B>::MB];
     uint32_t grp;
+    uint32_t qn;                     // queued half cells (wave-uniform)
     u64 survivors;
     u64 screened;
 };
 
-// Exact treatment of the elements of one column block that passed the screen.
-template <int B, bool MASK>
-__device__ __forceinline__ void take_survivors(const SearchArgs &a, WaveState<B> &st,
-                                               const float4_t (&acc)[Cfg<B>::MB][Cfg<B>::NCH],
-                                               int cb, float u, float slack)
+// Fit the nq queued half cells of group grp (one per lane, 64 at a time),
+// fold the keys into the LDS best keys, write the thresholds to LDS.
+template <int B>
+__device__ __noinline__ void flush16(const SearchArgs *ta, uint32_t grp, uint32_t nq,
+                                     Queue16<B> *qu)
 {
-    using C = Cfg<B>;
-    constexpr int n = C::n, MW = C::MB, NCH = C::NCH, GR = C::GR;
-    const int lane = threadIdx.x & 63, hl = lane >> 5, col = lane & 15;
-    const int isob = ((lane >> 4) & 1) * 4;
-    const uint32_t p = (uint32_t)cb * 16 + col;
-#pragma unroll
-    for (int b = 0; b < MW; ++b) {
-        float4_t s = acc[b][0];
-#pragma unroll
-        for (int c = 1; c < NCH; ++c) s += acc[b][c];
-        const float m = fmaxf(fmaxf(fabsf(s[0]), fabsf(s[1])), fmaxf(fabsf(s[2]), fabsf(s[3])));
-        bool h = m >= fmaf(st.T[b], u, -slack);
-        if (MASK) h = h && p >= st.lo[b] && p < st.hi[b];
-        if (!__any(h)) continue;
-        const int64_t slot = (int64_t)st.grp * GR + 2 * b + hl;
-        const int64_t srr = a.rs[slot].srr;
-        u64 cand = kNoKey;
-        if (h) {
+    constexpr int n = Cfg<B>::n, GR = Cfg<B>::GR;
+    const int lane = threadIdx.x & 63;
+    const SearchArgs a = *ta;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    for (uint32_t b0 = 0; b0 < nq; b0 += 64) {
+        const uint32_t e = b0 + (uint32_t)lane;
+        if (e < nq) {
+            const uint32_t lq = qu->lq[e], p = qu->p[e];
+            const uint32_t ls = lq & 255u, isob = lq >> 8;
+            const int64_t slot = (int64_t)grp * GR + ls;
+            const int64_t srr = a.rs[slot].srr;
             const int32_t delta = a.rs[slot].delta;
             const int64_t sdd = a.sdd[p];
             const int32_t ep = a.eps[p];
             const uint32_t d = a.dom[p];
+            u64 cand = kNoKey;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                int64_t cx = 0;
-#pragma unroll
-                for (int c = 0; c < NCH; ++c) cx += (int64_t)acc[b][c][v];
-                const int64_t srd = (int64_t)n * cx - (int64_t)delta * ep;
+                const int64_t srd = (int64_t)n * qu->c[v][e] - (int64_t)delta * ep;
                 int k;
                 const int64_t f = fit_f(srr, srd, sdd, k);
-                const u64 key = pack_key(f, d, isob + v, a.shift);
+                const u64 key = pack_key(f, d, (int)isob + v, a.shift);
                 cand = key < cand ? key : cand;
             }
-            st.survivors += 4;
-        }
-#pragma unroll
-        for (int off = 1; off < 32; off <<= 1) {
-            const u64 o = __shfl_xor(cand, off);
-            cand = o < cand ? o : cand;
-        }
-        if (cand < st.best[b]) {
-            st.best[b] = cand;
-            st.T[b] = screen_t(srr, (int64_t)(cand >> a.shift));
+            atomicMin(&qu->best[ls], cand);
         }
     }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    if (lane < GR) {
+        const u64 bk = qu->best[lane];
+        qu->T[lane] = bk == kNoKey ? 0.0f
+                                   : screen_t(a.rs[(int64_t)grp * GR + lane].srr,
+                                              (int64_t)(bk >> a.shift));
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
+template <int B>
+__device__ __forceinline__ void flush_and_refresh16(const SearchArgs *ta, WaveState<B> &st,
+                                                    Queue16<B> *qu)
+{
+    constexpr int MW = Cfg<B>::MB;
+    const int hl = (threadIdx.x >> 5) & 1;
+    flush16<B>(ta, st.grp, st.qn, qu);
+    st.survivors += (threadIdx.x & 63) == 0 ? 4ull * st.qn : 0ull;
+    st.qn = 0;
+#pragma unroll
+    for (int b = 0; b < MW; ++b)
+        if (st.T[b] != __builtin_inff())        // searched ranges only
+            st.T[b] = qu->T[2 * b + hl];
 }
 
 template <int B, bool MASK>
-__device__ __forceinline__ void screen_block(const SearchArgs &a, WaveState<B> &st,
+__device__ __forceinline__ void screen_block(const SearchArgs *ta, WaveState<B> &st,
+                                             Queue16<B> *qu,
                                              const typename WaveState<B>::frag_t (&bf)[Cfg<B>::KS],
                                              float u, int cb)
 {
     using C = Cfg<B>;
-    constexpr int n = C::n, MW = C::MB, NCH = C::NCH, KPC = C::KS / NCH;
+    constexpr int MW = C::MB, NCH = C::NCH, KPC = C::KS / NCH;
     const float slack = screen_slack<B>();
-    const int col = threadIdx.x & 15;
+    const int lane = threadIdx.x & 63, hl = lane >> 5, col = lane & 15;
     float4_t acc[MW][NCH];
 #pragma unroll
     for (int c = 0; c < NCH; ++c)
@@ -551,6 +583,8 @@ __device__ __forceinline__ void screen_block(const SearchArgs &a, WaveState<B> &
                 const float4_t z = {0.f, 0.f, 0.f, 0.f};
                 acc[b][c] = mma(st.af[b][c * KPC + kk], bf[c * KPC + kk], kk ? acc[b][c] : z);
             }
+    const uint32_t p = (uint32_t)cb * 16 + col;
+    bool pass[MW];
     bool hit = false;
 #pragma unroll
     for (int b = 0; b < MW; ++b) {
@@ -559,19 +593,42 @@ __device__ __forceinline__ void screen_block(const SearchArgs &a, WaveState<B> &
         for (int c = 1; c < NCH; ++c) sv += acc[b][c];
         const float m = fmaxf(fmaxf(fabsf(sv[0]), fabsf(sv[1])), fmaxf(fabsf(sv[2]), fabsf(sv[3])));
         bool h = m >= fmaf(st.T[b], u, -slack);
-        if (MASK) {
-            const uint32_t p = (uint32_t)cb * 16 + col;
-            h = h && p >= st.lo[b] && p < st.hi[b];
-        }
+        if (MASK) h = h && p >= st.lo[b] && p < st.hi[b];
+        pass[b] = h;
         hit = hit || h;
     }
-    if (__any(hit)) take_survivors<B, MASK>(a, st, acc, cb, u, slack);
+    if (!__any(hit)) return;
+    // append the passing half cells (at most 64 per row block)
+    const uint32_t isob = ((lane >> 4) & 1) * 4;
+#pragma unroll
+    for (int b = 0; b < MW; ++b) {
+        const u64 ball = __ballot(pass[b]);
+        if (ball == 0) continue;
+        const uint32_t cnt = (uint32_t)__popcll(ball);
+        if (st.qn + cnt > (uint32_t)kQueue) flush_and_refresh16<B>(ta, st, qu);
+        if (pass[b]) {
+            const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+                (uint32_t)(ball >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ball, 0u));
+            const uint32_t pos = st.qn + below;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                int32_t cx = 0;      // each 64-term chunk is exact in FP32
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) cx += (int32_t)acc[b][c][v];
+                qu->c[v][pos] = cx;
+            }
+            qu->p[pos] = p;
+            qu->lq[pos] = (uint32_t)(2 * b + hl) | (isob << 8);
+        }
+        st.qn += cnt;
+    }
 }
 
 // Column blocks [cb_begin, cb_end) against the wave's A rows. The B
 // fragments and u of the block two ahead are loaded while a block computes.
 template <int B, bool MASK>
-__device__ __forceinline__ void scan_blocks(const SearchArgs &a, WaveState<B> &st, int cb_begin,
+__device__ __forceinline__ void scan_blocks(const SearchArgs &a, const SearchArgs *ta,
+                                            WaveState<B> &st, Queue16<B> *qu, int cb_begin,
                                             int cb_end)
 {
     using C = Cfg<B>;
@@ -579,7 +636,8 @@ __device__ __forceinline__ void scan_blocks(const SearchArgs &a, WaveState<B> &s
     typedef typename WaveState<B>::frag_t frag_t;
     if (cb_begin >= cb_end) return;
     const int lane = threadIdx.x & 63, col = lane & 15;
-    const frag_t *bbase = (const frag_t *)a.Bm + lane;
+    const auto *bbase = as_global((const frag_t *)a.Bm) + lane;
+    const auto *ubase = as_global(a.u) + col;
     const int last = cb_end - 1;
     frag_t b0[KS], b1[KS];
     float u0, u1;
@@ -590,8 +648,8 @@ __device__ __forceinline__ void scan_blocks(const SearchArgs &a, WaveState<B> &s
             b0[ks] = bbase[((int64_t)cb_begin * KS + ks) * 64];
             b1[ks] = bbase[((int64_t)c1 * KS + ks) * 64];
         }
-        u0 = a.u[cb_begin * 16 + col];
-        u1 = a.u[c1 * 16 + col];
+        u0 = ubase[(int64_t)cb_begin * 16];
+        u1 = ubase[(int64_t)c1 * 16];
     }
     for (int cb = cb_begin; cb < cb_end; cb += 2) {
         {
@@ -602,8 +660,8 @@ __device__ __forceinline__ void scan_blocks(const SearchArgs &a, WaveState<B> &s
             const int nx = min(cb + 2, last);
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) b0[ks] = bbase[((int64_t)nx * KS + ks) * 64];
-            u0 = a.u[nx * 16 + col];
-            screen_block<B, MASK>(a, st, bc, uc, cb);
+            u0 = ubase[(int64_t)nx * 16];
+            screen_block<B, MASK>(ta, st, qu, bc, uc, cb);
         }
         if (cb + 1 < cb_end) {
             frag_t bc[KS];
@@ -613,8 +671,8 @@ __device__ __forceinline__ void scan_blocks(const SearchArgs &a, WaveState<B> &s
             const int nx = min(cb + 3, last);
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) b1[ks] = bbase[((int64_t)nx * KS + ks) * 64];
-            u1 = a.u[nx * 16 + col];
-            screen_block<B, MASK>(a, st, bc, uc, cb + 1);
+            u1 = ubase[(int64_t)nx * 16];
+            screen_block<B, MASK>(ta, st, qu, bc, uc, cb + 1);
         }
     }
 }
@@ -631,11 +689,14 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma(const SearchArgs *__rest
     using C = Cfg<B>;
     constexpr int MW = C::MB, KS = C::KS, GR = C::GR;
     typedef typename WaveState<B>::frag_t frag_t;
+    __shared__ Queue16<B> queues[4];
     const int lane = threadIdx.x & 63, hl = lane >> 5;
+    Queue16<B> *qu = &queues[threadIdx.x >> 6];
     const uint32_t nitems = base[n_img];
     WaveState<B> st;
     st.survivors = 0;
     st.screened = 0;
+    st.qn = 0;
     u64 items_done = 0;
     for (;;) {
         uint32_t item = 0;
@@ -648,7 +709,8 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma(const SearchArgs *__rest
             if (base[m] <= item) ia = m; else ib = m;
         }
         ia = __builtin_amdgcn_readfirstlane(ia);
-        const SearchArgs a = tab[ia];
+        const SearchArgs *ta = tab + ia;
+        const SearchArgs a = *ta;
         const WorkItem wi = a.items[item - base[ia]];
         st.grp = wi.grp;
         const frag_t *ap = (const frag_t *)a.A + (int64_t)st.grp * MW * KS * 64 + lane;
@@ -656,18 +718,19 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma(const SearchArgs *__rest
         for (int b = 0; b < MW; ++b)
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) st.af[b][ks] = ap[(b * KS + ks) * 64];
+        if (lane < GR) qu->best[lane] = a.keys[(int64_t)st.grp * GR + lane];
 #pragma unroll
         for (int b = 0; b < MW; ++b) {
             const int64_t slot = (int64_t)st.grp * GR + 2 * b + hl;
             const RangeStat rsx = a.rs[slot];
-            st.best[b] = a.keys[slot];
+            const u64 bk = a.keys[slot];
             st.lo[b] = rsx.lo;
             st.hi[b] = rsx.hi;
             const bool act = !(rsx.flags & (kPad | kFlat | kEmpty));
             st.T[b] = !act ? __builtin_inff()
-                           : (st.best[b] == kNoKey ? 0.0f
-                                                   : screen_t(rsx.srr, (int64_t)(st.best[b] >> a.shift)));
+                           : (bk == kNoKey ? 0.0f : screen_t(rsx.srr, (int64_t)(bk >> a.shift)));
         }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         const uint4 gb = a.grp[st.grp];
         const int cb0 = (int)(wi.c0 >> 4), cb1 = (int)(wi.c1 >> 4);
         // column blocks fully inside every active range's pool need no mask
@@ -675,15 +738,15 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma(const SearchArgs *__rest
         ib0 = min(max(ib0, cb0), cb1);
         ib1 = max(min(ib1, cb1), ib0);
         st.screened += (u64)(cb1 - cb0) * 16 * GR * 8;
-        scan_blocks<B, true>(a, st, cb0, ib0);
-        scan_blocks<B, false>(a, st, ib0, ib1);
-        scan_blocks<B, true>(a, st, ib1, cb1);
-        if ((lane & 31) == 0) {
-#pragma unroll
-            for (int b = 0; b < MW; ++b)
-                if (st.best[b] != kNoKey)
-                    atomicMin(&a.keys[(int64_t)st.grp * GR + 2 * b + hl], st.best[b]);
+        scan_blocks<B, true>(a, ta, st, qu, cb0, ib0);
+        scan_blocks<B, false>(a, ta, st, qu, ib0, ib1);
+        scan_blocks<B, true>(a, ta, st, qu, ib1, cb1);
+        if (st.qn) flush_and_refresh16<B>(ta, st, qu);
+        if (lane < GR) {
+            const u64 bk = qu->best[lane];
+            if (bk != kNoKey) atomicMin(&a.keys[(int64_t)st.grp * GR + lane], bk);
         }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         items_done += 1;
     }
     if (counters) {
@@ -702,18 +765,10 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma(const SearchArgs *__rest
 // A wave owns GR = 4*MB ranges: row block blk holds the range quad 4*blk ..
 // 4*blk+3 under the 8 isometries. Lane l's 16 outputs of a tile are column
 // l%32 against range 4*blk + 2*(l/32) (v < 8) and that + 1 (v >= 8), under
-// isometry v%8. Per block: MB MFMAs, then per lane and range half one
-// 8-value maximum, one fma and one compare.
-// A 4x4 range meets many near-optimal domains, so cells pass the screen far
-// more often than for larger ranges. A passing cell (range, column) is not
-// fitted in place -- that would run the exact int64 fit on the whole wave
-// for a few lanes -- but appended with its 8 cross terms to a per-wave queue
-// in LDS; when the queue holds a wave's worth, every lane fits one queued
-// cell (out of line, so the hot loop stays small), the best keys (kept in
-// LDS) take an LDS atomic minimum, and the refreshed thresholds come back
-// through LDS.
-constexpr int kQueue = 128;          // queued cells per wave (>= 2 waves' worth)
-
+// isometry v%8: whole cells. Per block: MB MFMAs, then per lane and range
+// half one 8-value maximum, one fma and one compare. (A 4x4 range meets many
+// near-optimal domains, so its cells pass the screen far more often than
+// those of larger ranges: the queue matters most here.)
 template <int B> struct Queue32 {
     float c[8][kQueue];              // the cell's cross term under isometry q
     uint32_t p[kQueue];              // column
@@ -721,12 +776,6 @@ template <int B> struct Queue32 {
     u64 best[Cfg<B>::GR];            // best keys of the wave's ranges
     float T[Cfg<B>::GR];             // their thresholds
 };
-
-template <class T> __device__ __forceinline__ const __attribute__((address_space(1))) T *
-as_global(const T *p)
-{
-    return (const __attribute__((address_space(1))) T *)p;
-}
 
 template <int B> struct Wave32 {
     static constexpr int MB = Cfg<B>::MB;
