@@ -651,7 +651,10 @@ __device__ __forceinline__ void scan_blocks(const SearchArgs &a, const SearchArg
         u0 = ubase[(int64_t)cb_begin * 16];
         u1 = ubase[(int64_t)c1 * 16];
     }
-    for (int cb = cb_begin; cb < cb_end; cb += 2) {
+    // whole pairs of blocks without a branch between them (a conditional
+    // second step would make the compiler wait for the loads just issued)
+    int cb = cb_begin;
+    for (; cb + 2 <= cb_end; cb += 2) {
         {
             frag_t bc[KS];
 #pragma unroll
@@ -663,7 +666,7 @@ __device__ __forceinline__ void scan_blocks(const SearchArgs &a, const SearchArg
             u0 = ubase[(int64_t)nx * 16];
             screen_block<B, MASK>(ta, st, qu, bc, uc, cb);
         }
-        if (cb + 1 < cb_end) {
+        {
             frag_t bc[KS];
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) bc[ks] = b1[ks];
@@ -675,6 +678,7 @@ __device__ __forceinline__ void scan_blocks(const SearchArgs &a, const SearchArg
             screen_block<B, MASK>(ta, st, qu, bc, uc, cb + 1);
         }
     }
+    if (cb < cb_end) screen_block<B, MASK>(ta, st, qu, b0, u0, cb);
 }
 
 // Items of n_img images (table entries tab[0..n_img), item bases base[]) in
@@ -761,14 +765,14 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma(const SearchArgs *__rest
     }
 }
 
-// ---------------- 32 x 32 tiles (4x4 ranges, K = 16 = one MFMA)
+// ---------------- 32 x 32 tiles (4x4 and 8x8 ranges, K = 16 per MFMA)
 // A wave owns GR = 4*MB ranges: row block blk holds the range quad 4*blk ..
 // 4*blk+3 under the 8 isometries. Lane l's 16 outputs of a tile are column
 // l%32 against range 4*blk + 2*(l/32) (v < 8) and that + 1 (v >= 8), under
-// isometry v%8: whole cells. Per block: MB MFMAs, then per lane and range
+// isometry v%8: whole cells. Per block: MB*KS MFMAs, then per lane and range
 // half one 8-value maximum, one fma and one compare. (A 4x4 range meets many
 // near-optimal domains, so its cells pass the screen far more often than
-// those of larger ranges: the queue matters most here.)
+// those of larger ranges: the queue matters most there.)
 template <int B> struct Queue32 {
     float c[8][kQueue];              // the cell's cross term under isometry q
     uint32_t p[kQueue];              // column
@@ -778,8 +782,8 @@ template <int B> struct Queue32 {
 };
 
 template <int B> struct Wave32 {
-    static constexpr int MB = Cfg<B>::MB;
-    half8_t af[MB];
+    static constexpr int MB = Cfg<B>::MB, KS = Cfg<B>::KS;
+    half8_t af[MB][KS];
     float T[MB][2];
     uint32_t lo[MB][2], hi[MB][2];
     uint32_t grp;
@@ -855,20 +859,26 @@ __device__ __forceinline__ void flush_and_refresh(const SearchArgs *ta, Wave32<B
 
 template <int B, bool MASK>
 __device__ __forceinline__ void screen32(const SearchArgs &a, const SearchArgs *ta,
-                                         Wave32<B> &st, Queue32<B> *qu, half8_t bf, float u,
-                                         int cb)
+                                         Wave32<B> &st, Queue32<B> *qu,
+                                         const half8_t (&bf)[Cfg<B>::KS], float u, int cb)
 {
-    constexpr int MB = Cfg<B>::MB;
+    constexpr int MB = Cfg<B>::MB, KS = Cfg<B>::KS;
     const float slack = screen_slack<B>();
     const int lane = threadIdx.x & 63, h = lane >> 5;
     float16_t acc[MB];
 #pragma unroll
-    for (int blk = 0; blk < MB; ++blk) {
-        float16_t z;
+    for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
-        for (int e = 0; e < 16; ++e) z[e] = 0.0f;
-        acc[blk] = mma32(st.af[blk], bf, z);
-    }
+        for (int blk = 0; blk < MB; ++blk) {
+            float16_t z;
+            if (ks == 0) {
+#pragma unroll
+                for (int e = 0; e < 16; ++e) z[e] = 0.0f;
+            } else {
+                z = acc[blk];
+            }
+            acc[blk] = mma32(st.af[blk][ks], bf[ks], z);
+        }
     const uint32_t p = (uint32_t)cb * 32 + (lane & 31);
     bool pass[MB][2];
     bool hit = false;
@@ -904,49 +914,56 @@ __device__ __forceinline__ void screen32(const SearchArgs &a, const SearchArgs *
         }
 }
 
-// Column blocks [cb_begin, cb_end): the B fragment and u of the block PD
-// ahead are loaded while a block computes (a 4x4 block is cheap, so the
-// loads need a deep queue to hide the L2 latency).
+// Column blocks [cb_begin, cb_end): the B fragments and u of the block PD
+// ahead are loaded while a block computes (a 4x4 block is cheap, so its loads
+// need a deeper queue to hide the L2 latency). Whole groups of PD blocks run
+// without a branch between them: a conditional step would make the compiler
+// wait for the loads just issued.
 template <int B, bool MASK>
 __device__ __forceinline__ void scan32(const SearchArgs &a, const SearchArgs *ta, Wave32<B> &st,
                                        Queue32<B> *qu, int cb_begin, int cb_end)
 {
-    constexpr int PD = 4;
+    constexpr int KS = Cfg<B>::KS, PD = KS == 1 ? 4 : 2;
     if (cb_begin >= cb_end) return;
     const int lane = threadIdx.x & 63, col = lane & 31;
     const auto *bbase = as_global((const half8_t *)a.Bm) + lane;
     const auto *ubase = as_global(a.u) + col;
     const int last = cb_end - 1;
-    half8_t b0, b1, b2, b3;
-    float u0, u1, u2, u3;
-    b0 = bbase[(int64_t)min(cb_begin + 0, last) * 64];
-    b1 = bbase[(int64_t)min(cb_begin + 1, last) * 64];
-    b2 = bbase[(int64_t)min(cb_begin + 2, last) * 64];
-    b3 = bbase[(int64_t)min(cb_begin + 3, last) * 64];
-    u0 = ubase[(int64_t)min(cb_begin + 0, last) * 32];
-    u1 = ubase[(int64_t)min(cb_begin + 1, last) * 32];
-    u2 = ubase[(int64_t)min(cb_begin + 2, last) * 32];
-    u3 = ubase[(int64_t)min(cb_begin + 3, last) * 32];
+    half8_t b0[KS], b1[KS], b2[KS], b3[KS];
+    float u0, u1, u2 = 0.0f, u3 = 0.0f;
+    auto load = [&](half8_t (&bq)[KS], float &uq, int c) {
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) bq[ks] = bbase[((int64_t)c * KS + ks) * 64];
+        uq = ubase[(int64_t)c * 32];
+    };
+    load(b0, u0, min(cb_begin + 0, last));
+    load(b1, u1, min(cb_begin + 1, last));
+    if constexpr (PD == 4) {
+        load(b2, u2, min(cb_begin + 2, last));
+        load(b3, u3, min(cb_begin + 3, last));
+    }
     int cb = cb_begin;
-#define FIC_STEP32(BQ, UQ, I)                                                         \
-    {                                                                                 \
-        const half8_t bc = BQ;                                                        \
-        const float uc = UQ;                                                          \
-        const int nx = min(cb + (I) + PD, last);                                      \
-        BQ = bbase[(int64_t)nx * 64];                                                 \
-        UQ = ubase[(int64_t)nx * 32];                                                 \
-        screen32<B, MASK>(a, ta, st, qu, bc, uc, cb + (I));                           \
-    }
+    auto step = [&](half8_t (&bq)[KS], float &uq, int i) {
+        half8_t bc[KS];
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) bc[ks] = bq[ks];
+        const float uc = uq;
+        load(bq, uq, min(cb + i + PD, last));
+        screen32<B, MASK>(a, ta, st, qu, bc, uc, cb + i);
+    };
     for (; cb + PD <= cb_end; cb += PD) {
-        FIC_STEP32(b0, u0, 0)
-        FIC_STEP32(b1, u1, 1)
-        FIC_STEP32(b2, u2, 2)
-        FIC_STEP32(b3, u3, 3)
+        step(b0, u0, 0);
+        step(b1, u1, 1);
+        if constexpr (PD == 4) {
+            step(b2, u2, 2);
+            step(b3, u3, 3);
+        }
     }
-#undef FIC_STEP32
     if (cb + 0 < cb_end) screen32<B, MASK>(a, ta, st, qu, b0, u0, cb + 0);
-    if (cb + 1 < cb_end) screen32<B, MASK>(a, ta, st, qu, b1, u1, cb + 1);
-    if (cb + 2 < cb_end) screen32<B, MASK>(a, ta, st, qu, b2, u2, cb + 2);
+    if constexpr (PD == 4) {
+        if (cb + 1 < cb_end) screen32<B, MASK>(a, ta, st, qu, b1, u1, cb + 1);
+        if (cb + 2 < cb_end) screen32<B, MASK>(a, ta, st, qu, b2, u2, cb + 2);
+    }
 }
 
 template <int B>
@@ -955,7 +972,7 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma32(const SearchArgs *__re
                                                           int32_t n_img, uint32_t *item_ctr,
                                                           u64 *counters)
 {
-    constexpr int MB = Cfg<B>::MB, GR = Cfg<B>::GR;
+    constexpr int MB = Cfg<B>::MB, KS = Cfg<B>::KS, GR = Cfg<B>::GR;
     __shared__ Queue32<B> queues[4];
     const int lane = threadIdx.x & 63, h = lane >> 5;
     Queue32<B> *qu = &queues[threadIdx.x >> 6];
@@ -980,9 +997,11 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma32(const SearchArgs *__re
         const SearchArgs a = *ta;
         const WorkItem wi = a.items[item - base[ia]];
         st.grp = wi.grp;
-        const half8_t *ap = (const half8_t *)a.A + (int64_t)st.grp * MB * 64 + lane;
+        const half8_t *ap = (const half8_t *)a.A + (int64_t)st.grp * MB * KS * 64 + lane;
 #pragma unroll
-        for (int blk = 0; blk < MB; ++blk) st.af[blk] = ap[blk * 64];
+        for (int blk = 0; blk < MB; ++blk)
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) st.af[blk][ks] = ap[(blk * KS + ks) * 64];
         if (lane < GR) qu->best[lane] = a.keys[(int64_t)st.grp * GR + lane];
 #pragma unroll
         for (int blk = 0; blk < MB; ++blk)
