@@ -33,6 +33,7 @@ struct fic_ctx {
     bool use_graph;
     std::vector<Graph> graphs;
     hipStream_t cap;     // capture stream, created with the first graph
+    fic::BatchStreams side;   // batch preparation streams (side.ns == 0 until created)
 };
 
 namespace {
@@ -150,6 +151,44 @@ std::vector<unsigned char> batch_key(int32_t n, const fic_image_desc *d, const v
     return k;
 }
 
+constexpr int kSideStreams = 4;   // the hardware queues a process gets by default
+
+// The context's batch side streams and events, created on first use
+// (default priority). Returns null when they cannot be created.
+const fic::BatchStreams *side_streams(fic_ctx *c)
+{
+    if (c->side.ns > 0) return &c->side;
+    fic::BatchStreams b;
+    b.ns = 0;
+    if (hipEventCreateWithFlags(&b.fork, hipEventDisableTiming) != hipSuccess) return nullptr;
+    for (int q = 0; q < kSideStreams; ++q) {
+        if (hipStreamCreateWithFlags(&b.side[q], hipStreamNonBlocking) != hipSuccess) break;
+        if (hipEventCreateWithFlags(&b.join[q], hipEventDisableTiming) != hipSuccess) {
+            hipStreamDestroy(b.side[q]);
+            break;
+        }
+        b.ns = q + 1;
+    }
+    if (b.ns < kSideStreams) {
+        for (int q = 0; q < b.ns; ++q) { hipEventDestroy(b.join[q]); hipStreamDestroy(b.side[q]); }
+        hipEventDestroy(b.fork);
+        return nullptr;
+    }
+    c->side = b;
+    return &c->side;
+}
+
+void drop_side_streams(fic_ctx *c)
+{
+    if (c->side.ns == 0) return;
+    for (int q = 0; q < c->side.ns; ++q) {
+        hipEventDestroy(c->side.join[q]);
+        hipStreamDestroy(c->side.side[q]);
+    }
+    hipEventDestroy(c->side.fork);
+    c->side.ns = 0;
+}
+
 void drop_graphs(fic_ctx *c)
 {
     for (auto &g : c->graphs) hipGraphExecDestroy(g.exec);
@@ -204,6 +243,7 @@ fic_status fic_create(int32_t device, fic_ctx **out)
     c->tracer.mark = mark_stage;
     c->use_graph = true;
     c->cap = nullptr;
+    c->side.ns = 0;
     if (device >= 0) {
         int n = 0;
         if (hipGetDeviceCount(&n) != hipSuccess || device >= n) {
@@ -237,6 +277,7 @@ fic_status fic_destroy(fic_ctx *ctx)
         for (auto e : ctx->spare) hipEventDestroy(e);
         if (ctx->open_ev) hipEventDestroy(ctx->open_ev);
         drop_graphs(ctx);
+        drop_side_streams(ctx);
         if (ctx->cap) hipStreamDestroy(ctx->cap);
     }
     delete ctx;
@@ -383,9 +424,11 @@ fic_status fic_encode_pifs_batch(fic_ctx *ctx, int32_t n_images, const fic_image
     fic_status st = enter(ctx);
     if (st != FIC_OK) return st;
     hipStream_t s = (hipStream_t)stream;
+    const fic::BatchStreams *side = side_streams(ctx);
+    if (!side) return FIC_ERR_DEVICE;
     if (!ctx->use_graph)
         return dev_status(fic::run_encode_batch(jobs.data(), bp, ws, ctx->num_cu, ctx->counters, s,
-                                                tracer_of(ctx)));
+                                                tracer_of(ctx), side));
     std::vector<unsigned char> key = batch_key(n_images, descs, ws, ws_bytes, ctx->counters);
     size_t hit = ctx->graphs.size();
     for (size_t i = 0; i < ctx->graphs.size(); ++i)
@@ -399,7 +442,7 @@ fic_status fic_encode_pifs_batch(fic_ctx *ctx, int32_t n_images, const fic_image
         if (hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
             return FIC_ERR_DEVICE;
         const hipError_t e = fic::run_encode_batch(jobs.data(), bp, ws, ctx->num_cu, ctx->counters,
-                                                   ctx->cap, nullptr);
+                                                   ctx->cap, nullptr, side);
         hipGraph_t graph = nullptr;
         const hipError_t e2 = hipStreamEndCapture(ctx->cap, &graph);
         hipGraphExec_t exec = nullptr;

@@ -689,6 +689,8 @@ __device__ __forceinline__ void scan_blocks(const SearchArgs &a, const SearchArg
 // Items of n_img images (table entries tab[0..n_img), item bases base[]) in
 // one queue: a wave claims an item, finds its image by binary search over
 // the bases, and loads that image's operands.
+// 8 row blocks of 8x8 ranges fill 2 waves/SIMD (237 VGPRs); fewer blocks at
+// more waves per SIMD re-read B more and measure slower.
 template <int B>
 __global__ __launch_bounds__(256, 2) void k_search_mfma(const SearchArgs *__restrict__ tab,
                                                         const uint32_t *__restrict__ base,
@@ -1471,7 +1473,7 @@ void plan_batch(const BatchJob *jobs, int32_t n, BatchPlan &bp)
 }
 
 hipError_t run_encode_batch(const BatchJob *jobs, const BatchPlan &bp, void *ws, int num_cu,
-                            u64 *counters, hipStream_t s, const Tracer *tr)
+                            u64 *counters, hipStream_t s, const Tracer *tr, const BatchStreams *bs)
 {
     char *w = (char *)ws;
     SearchArgs *tab = (SearchArgs *)(w + bp.off_tab);
@@ -1479,10 +1481,18 @@ hipError_t run_encode_batch(const BatchJob *jobs, const BatchPlan &bp, void *ws,
     uint32_t *ctr = (uint32_t *)(w + bp.off_ctr);
     hipLaunchKernelGGL(k_fill_u32, dim3(3), dim3(64), 0, s, ctr, (int64_t)(3 * 64), 0u);
     hipError_t e = hipGetLastError();
+    // The images' preparations are independent small launches: spread them
+    // over the side streams, round robin in the table order.
+    const int ns = bs ? bs->ns : 0;
+    if (ns > 0 && e == hipSuccess) {
+        e = hipEventRecord(bs->fork, s);
+        for (int q = 0; q < ns && e == hipSuccess; ++q) e = hipStreamWaitEvent(bs->side[q], bs->fork, 0);
+    }
     // classify, pool and search preparation, image by image
     for (int32_t k = 0; k < bp.n && e == hipSuccess; ++k) {
         const int32_t i = bp.order[k];
         const BatchJob &j = jobs[i];
+        const hipStream_t ps = ns > 0 ? bs->side[k % ns] : s;
         const BatchPart &pt = bp.part[i];
         const Geom &g = j.g;
         double *fdr = (double *)(w + pt.off_fdr);
@@ -1491,12 +1501,12 @@ hipError_t run_encode_batch(const BatchJob *jobs, const BatchPlan &bp, void *ws,
         uint32_t *lo = (uint32_t *)(w + pt.off_lo);
         uint32_t *hi = (uint32_t *)(w + pt.off_hi);
         if (j.pooled) {
-            e = launch_fd_classify(j.img, g.h, g.w, g.pitch, g.b, g.b, fdr, nullptr, s, tr);
+            e = launch_fd_classify(j.img, g.h, g.w, g.pitch, g.b, g.b, fdr, nullptr, ps, tr);
             if (e == hipSuccess)
-                e = launch_fd_classify(j.img, g.h, g.w, g.pitch, 2 * g.b, g.t, fdd, nullptr, s, tr);
+                e = launch_fd_classify(j.img, g.h, g.w, g.pitch, 2 * g.b, g.t, fdd, nullptr, ps, tr);
             if (e == hipSuccess)
                 e = launch_pool(fdr, (int32_t)g.R, fdd, (int32_t)g.D, j.tol, perm, lo, hi,
-                                w + pt.off_pool, s, tr);
+                                w + pt.off_pool, ps, tr);
         }
         if (e != hipSuccess) break;
         const uint32_t *pp = j.pooled ? perm : nullptr;
@@ -1504,10 +1514,14 @@ hipError_t run_encode_batch(const BatchJob *jobs, const BatchPlan &bp, void *ws,
         const uint32_t *ph = j.pooled ? hi : nullptr;
         void *ew = w + pt.off_enc;
         switch (g.b) {
-        case 4: e = batch_phase<4>(0, pt.plan, j.img, pp, pl, ph, ew, counters, tab + k, nullptr, s, tr); break;
-        case 8: e = batch_phase<8>(0, pt.plan, j.img, pp, pl, ph, ew, counters, tab + k, nullptr, s, tr); break;
-        default: e = batch_phase<16>(0, pt.plan, j.img, pp, pl, ph, ew, counters, tab + k, nullptr, s, tr); break;
+        case 4: e = batch_phase<4>(0, pt.plan, j.img, pp, pl, ph, ew, counters, tab + k, nullptr, ps, tr); break;
+        case 8: e = batch_phase<8>(0, pt.plan, j.img, pp, pl, ph, ew, counters, tab + k, nullptr, ps, tr); break;
+        default: e = batch_phase<16>(0, pt.plan, j.img, pp, pl, ph, ew, counters, tab + k, nullptr, ps, tr); break;
         }
+    }
+    if (ns > 0) {
+        for (int q = 0; q < ns && e == hipSuccess; ++q) e = hipEventRecord(bs->join[q], bs->side[q]);
+        for (int q = 0; q < ns && e == hipSuccess; ++q) e = hipStreamWaitEvent(s, bs->join[q], 0);
     }
     // one persistent search per range size over all its images
     for (int gi = 0; gi < 3 && e == hipSuccess; ++gi) {

@@ -237,9 +237,20 @@ struct BatchPlan {
     size_t off_tab, off_base, off_ctr, total;
     int64_t items;                   // upper bound on the work items of all images
 };
+// Side streams for the per-image preparation of a batch: forked from the
+// calling stream by one event and joined back before the searches (under
+// stream capture this records parallel branches).
+constexpr int kMaxSideStreams = 8;
+struct BatchStreams {
+    int ns;
+    hipStream_t side[kMaxSideStreams];
+    hipEvent_t fork;
+    hipEvent_t join[kMaxSideStreams];
+};
 void plan_batch(const BatchJob *jobs, int32_t n, BatchPlan &bp);
 hipError_t run_encode_batch(const BatchJob *jobs, const BatchPlan &bp, void *ws, int num_cu,
-                            u64 *counters, hipStream_t s, const Tracer *tr = nullptr);
+                            u64 *counters, hipStream_t s, const Tracer *tr = nullptr,
+                            const BatchStreams *bs = nullptr);
 
 // decode (decode.hip)
 size_t decode_ws_bytes(const Geom &g);
