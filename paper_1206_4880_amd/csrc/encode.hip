@@ -479,7 +479,7 @@ __global__ __launch_bounds__(256) void k_item_bases(const SearchArgs *__restrict
 // wave's best keys (in LDS) take an LDS atomic minimum, and the refreshed
 // thresholds come back through LDS. Fitting a passing cell in place would run
 // the exact int64 fit on the whole wave for the few lanes that passed.
-constexpr int kQueue = 128;          // queued cells per wave (>= 2 waves' worth)
+constexpr int kQueue = 256;          // queued cells per wave (flushed with > 3 waves' worth)
 
 template <class T> __device__ __forceinline__ const __attribute__((address_space(1))) T *
 as_global(const T *p)
@@ -497,6 +497,8 @@ template <int B> struct Queue16 {
     uint32_t lq[kQueue];             // range within the group | isometry base << 8
     u64 best[Cfg<B>::GR];            // best keys of the wave's ranges
     float T[Cfg<B>::GR];             // their thresholds
+    int64_t srr[Cfg<B>::GR];         // their Srr'
+    int32_t delta[Cfg<B>::GR];       // their delta = sum r - n*rhat
 };
 
 template <int B> struct WaveState {
@@ -510,34 +512,53 @@ template <int B> struct WaveState {
     u64 screened;
 };
 
-// Fit the nq queued half cells of group grp (one per lane, 64 at a time),
-// fold the keys into the LDS best keys, write the thresholds to LDS.
+// Fit the nq queued half cells (one per lane and round of 64), fold the keys
+// into the LDS best keys, write the thresholds to LDS. The column loads of
+// all rounds are issued before the first fit, so their latency is paid once
+// per flush; the range constants come from LDS.
 template <int B>
-__device__ __noinline__ void flush16(const SearchArgs *ta, uint32_t grp, uint32_t nq,
-                                     Queue16<B> *qu)
+__device__ __noinline__ void flush16(const SearchArgs *ta, uint32_t nq, Queue16<B> *qu)
 {
-    constexpr int n = Cfg<B>::n, GR = Cfg<B>::GR;
+    constexpr int n = Cfg<B>::n, GR = Cfg<B>::GR, RQ = kQueue / 64;
     const int lane = threadIdx.x & 63;
     const SearchArgs a = *ta;
+    const auto *gsdd = as_global(a.sdd);
+    const auto *geps = as_global(a.eps);
+    const auto *gdom = as_global(a.dom);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    for (uint32_t b0 = 0; b0 < nq; b0 += 64) {
-        const uint32_t e = b0 + (uint32_t)lane;
+    uint32_t pe[RQ], lqe[RQ], dm[RQ];
+    int64_t sd[RQ];
+    int32_t ep[RQ];
+#pragma unroll
+    for (int r = 0; r < RQ; ++r) {
+        const uint32_t e = (uint32_t)(r * 64 + lane);
+        pe[r] = 0; lqe[r] = 0; dm[r] = 0; sd[r] = 0; ep[r] = 0;
         if (e < nq) {
-            const uint32_t lq = qu->lq[e], p = qu->p[e];
-            const uint32_t ls = lq & 255u, isob = lq >> 8;
-            const int64_t slot = (int64_t)grp * GR + ls;
-            const int64_t srr = a.rs[slot].srr;
-            const int32_t delta = a.rs[slot].delta;
-            const int64_t sdd = a.sdd[p];
-            const int32_t ep = a.eps[p];
-            const uint32_t d = a.dom[p];
+            pe[r] = qu->p[e];
+            lqe[r] = qu->lq[e];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RQ; ++r)
+        if ((uint32_t)(r * 64 + lane) < nq) {
+            sd[r] = gsdd[pe[r]];
+            ep[r] = geps[pe[r]];
+            dm[r] = gdom[pe[r]];
+        }
+#pragma unroll
+    for (int r = 0; r < RQ; ++r) {
+        const uint32_t e = (uint32_t)(r * 64 + lane);
+        if (e < nq) {
+            const uint32_t ls = lqe[r] & 255u, isob = lqe[r] >> 8;
+            const int64_t srr = qu->srr[ls];
+            const int32_t delta = qu->delta[ls];
             u64 cand = kNoKey;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int64_t srd = (int64_t)n * qu->c[v][e] - (int64_t)delta * ep;
+                const int64_t srd = (int64_t)n * qu->c[v][e] - (int64_t)delta * ep[r];
                 int k;
-                const int64_t f = fit_f(srr, srd, sdd, k);
-                const u64 key = pack_key(f, d, (int)isob + v, a.shift);
+                const int64_t f = fit_f(srr, srd, sd[r], k);
+                const u64 key = pack_key(f, dm[r], (int)isob + v, a.shift);
                 cand = key < cand ? key : cand;
             }
             atomicMin(&qu->best[ls], cand);
@@ -546,9 +567,7 @@ __device__ __noinline__ void flush16(const SearchArgs *ta, uint32_t grp, uint32_
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     if (lane < GR) {
         const u64 bk = qu->best[lane];
-        qu->T[lane] = bk == kNoKey ? 0.0f
-                                   : screen_t(a.rs[(int64_t)grp * GR + lane].srr,
-                                              (int64_t)(bk >> a.shift));
+        qu->T[lane] = bk == kNoKey ? 0.0f : screen_t(qu->srr[lane], (int64_t)(bk >> a.shift));
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
@@ -559,7 +578,7 @@ __device__ __forceinline__ void flush_and_refresh16(const SearchArgs *ta, WaveSt
 {
     constexpr int MW = Cfg<B>::MB;
     const int hl = (threadIdx.x >> 5) & 1;
-    flush16<B>(ta, st.grp, st.qn, qu);
+    flush16<B>(ta, st.qn, qu);
     st.survivors += (threadIdx.x & 63) == 0 ? 4ull * st.qn : 0ull;
     st.qn = 0;
 #pragma unroll
@@ -729,7 +748,12 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma(const SearchArgs *__rest
         for (int b = 0; b < MW; ++b)
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) st.af[b][ks] = ap[(b * KS + ks) * 64];
-        if (lane < GR) qu->best[lane] = a.keys[(int64_t)st.grp * GR + lane];
+        if (lane < GR) {
+            const int64_t slot = (int64_t)st.grp * GR + lane;
+            qu->best[lane] = a.keys[slot];
+            qu->srr[lane] = a.rs[slot].srr;
+            qu->delta[lane] = a.rs[slot].delta;
+        }
 #pragma unroll
         for (int b = 0; b < MW; ++b) {
             const int64_t slot = (int64_t)st.grp * GR + 2 * b + hl;
@@ -786,6 +810,8 @@ template <int B> struct Queue32 {
     uint32_t ls[kQueue];             // range within the wave's group
     u64 best[Cfg<B>::GR];            // best keys of the wave's ranges
     float T[Cfg<B>::GR];             // their thresholds
+    int64_t srr[Cfg<B>::GR];         // their Srr'
+    int32_t delta[Cfg<B>::GR];       // their delta = sum r - n*rhat
 };
 
 template <int B> struct Wave32 {
@@ -805,33 +831,51 @@ __device__ __forceinline__ float max8(const float16_t &a, int base)
     return fmaxf(fmaxf(x, y), fmaxf(fabsf(a[base + 6]), fabsf(a[base + 7])));
 }
 
-// Fit the nq queued cells of group grp (one per lane, 64 at a time), fold
-// the keys into the LDS best keys, and write the wave's thresholds to LDS.
+// Fit the nq queued cells (one per lane and round of 64) as flush16 does,
+// over all 8 isometries of each cell.
 template <int B>
-__device__ __noinline__ void flush32(const SearchArgs *ta, uint32_t grp, uint32_t nq,
-                                     Queue32<B> *qu)
+__device__ __noinline__ void flush32(const SearchArgs *ta, uint32_t nq, Queue32<B> *qu)
 {
-    constexpr int n = Cfg<B>::n, GR = Cfg<B>::GR;
+    constexpr int n = Cfg<B>::n, GR = Cfg<B>::GR, RQ = kQueue / 64;
     const int lane = threadIdx.x & 63;
     const SearchArgs a = *ta;
+    const auto *gsdd = as_global(a.sdd);
+    const auto *geps = as_global(a.eps);
+    const auto *gdom = as_global(a.dom);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    for (uint32_t b0 = 0; b0 < nq; b0 += 64) {
-        const uint32_t e = b0 + (uint32_t)lane;
+    uint32_t pe[RQ], le[RQ], dm[RQ];
+    int64_t sd[RQ];
+    int32_t ep[RQ];
+#pragma unroll
+    for (int r = 0; r < RQ; ++r) {
+        const uint32_t e = (uint32_t)(r * 64 + lane);
+        pe[r] = 0; le[r] = 0; dm[r] = 0; sd[r] = 0; ep[r] = 0;
         if (e < nq) {
-            const uint32_t ls = qu->ls[e], p = qu->p[e];
-            const int64_t slot = (int64_t)grp * GR + ls;
-            const int64_t srr = a.rs[slot].srr;
-            const int32_t delta = a.rs[slot].delta;
-            const int64_t sdd = a.sdd[p];
-            const int32_t ep = a.eps[p];
-            const uint32_t d = a.dom[p];
+            pe[r] = qu->p[e];
+            le[r] = qu->ls[e];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RQ; ++r)
+        if ((uint32_t)(r * 64 + lane) < nq) {
+            sd[r] = gsdd[pe[r]];
+            ep[r] = geps[pe[r]];
+            dm[r] = gdom[pe[r]];
+        }
+#pragma unroll
+    for (int r = 0; r < RQ; ++r) {
+        const uint32_t e = (uint32_t)(r * 64 + lane);
+        if (e < nq) {
+            const uint32_t ls = le[r];
+            const int64_t srr = qu->srr[ls];
+            const int32_t delta = qu->delta[ls];
             u64 cand = kNoKey;
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
-                const int64_t srd = (int64_t)n * (int64_t)qu->c[q][e] - (int64_t)delta * ep;
+                const int64_t srd = (int64_t)n * (int64_t)qu->c[q][e] - (int64_t)delta * ep[r];
                 int k;
-                const int64_t f = fit_f(srr, srd, sdd, k);
-                const u64 key = pack_key(f, d, q, a.shift);
+                const int64_t f = fit_f(srr, srd, sd[r], k);
+                const u64 key = pack_key(f, dm[r], q, a.shift);
                 cand = key < cand ? key : cand;
             }
             atomicMin(&qu->best[ls], cand);
@@ -840,9 +884,7 @@ __device__ __noinline__ void flush32(const SearchArgs *ta, uint32_t grp, uint32_
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     if (lane < GR) {
         const u64 bk = qu->best[lane];
-        qu->T[lane] = bk == kNoKey ? 0.0f
-                                   : screen_t(a.rs[(int64_t)grp * GR + lane].srr,
-                                              (int64_t)(bk >> a.shift));
+        qu->T[lane] = bk == kNoKey ? 0.0f : screen_t(qu->srr[lane], (int64_t)(bk >> a.shift));
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
@@ -853,7 +895,7 @@ __device__ __forceinline__ void flush_and_refresh(const SearchArgs *ta, Wave32<B
 {
     constexpr int MB = Cfg<B>::MB;
     const int h = (threadIdx.x >> 5) & 1;
-    flush32<B>(ta, st.grp, st.qn, qu);
+    flush32<B>(ta, st.qn, qu);
     st.survivors += (threadIdx.x & 63) == 0 ? 8ull * st.qn : 0ull;
     st.qn = 0;
 #pragma unroll
@@ -1009,7 +1051,12 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma32(const SearchArgs *__re
         for (int blk = 0; blk < MB; ++blk)
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) st.af[blk][ks] = ap[(blk * KS + ks) * 64];
-        if (lane < GR) qu->best[lane] = a.keys[(int64_t)st.grp * GR + lane];
+        if (lane < GR) {
+            const int64_t slot = (int64_t)st.grp * GR + lane;
+            qu->best[lane] = a.keys[slot];
+            qu->srr[lane] = a.rs[slot].srr;
+            qu->delta[lane] = a.rs[slot].delta;
+        }
 #pragma unroll
         for (int blk = 0; blk < MB; ++blk)
 #pragma unroll
