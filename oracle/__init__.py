@@ -10,6 +10,7 @@ fractal dimensions); this module only compiles it with gcc and marshals numpy
 arrays. ``bruteforce.py`` holds the pixel-level grid search used to pin it.
 """
 import ctypes
+import math
 import os
 import subprocess
 
@@ -68,6 +69,12 @@ def lib():
         L.fico_decode.argtypes = ([_i32p] * 4 + [ctypes.c_int32] * 5
                                   + [ctypes.c_void_p, _u8p, ctypes.POINTER(ctypes.c_int32),
                                      ctypes.c_int32])
+        L.fico_decode_quadtree.restype = ctypes.c_int32
+        L.fico_decode_quadtree.argtypes = ([_i32p] * 4 + [_u8p, ctypes.c_int32, ctypes.c_int32]
+                                           + [_i32p] * 4 + [_u8p, ctypes.c_int32, ctypes.c_int32]
+                                           + [ctypes.c_int32] * 3
+                                           + [ctypes.c_void_p, _u8p,
+                                              ctypes.POINTER(ctypes.c_int32), ctypes.c_int32])
         _lib = L
     return _lib
 
@@ -178,6 +185,69 @@ def decode(codes, h, w, b, t, max_iters=32, init=None, nthreads=0):
     rc = lib().fico_decode(*arr, h, w, b, t, int(max_iters),
                            ini.ctypes.data if ini is not None else None,
                            out, ctypes.byref(it), int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle: invalid geometry")
+    return out, int(it.value)
+
+
+def split_threshold(b1, rms):
+    """Largest level-1 error E = 4096*n*SSE that is not split: E is split
+    when its mean squared error SSE/n exceeds rms^2, i.e. E > 4096*n^2*rms^2,
+    floored to an integer (E is one). fp64, in this operation order."""
+    n1 = b1 * b1
+    t = rms * rms * (4096.0 * n1 * n1)
+    if not t < 9.0e18:
+        return (1 << 63) - 1
+    return int(math.floor(t))
+
+
+def encode_quadtree(img, b1, t1, tol1, b2, t2, tol2, rms, nthreads=0):
+    """Two-level partition (Fisher's quadtree, the paper's ref. [12], at two
+    levels): every b1 x b1 range is coded; a range whose E exceeds
+    split_threshold(b1, rms) is split, flagged (bit 1), and its four
+    b2 x b2 sub-ranges are coded at level 2 (their own pool or exhaustive
+    search over the level-2 domains); the other level-2 codes are "not
+    coded": domain 0, isometry 0, k = 0, j = 0, flags bit 2, E = 0.
+    Returns (level-1 codes, level-2 codes) as dicts like encode()."""
+    if b1 != 2 * b2:
+        raise ValueError("level-2 ranges are the quadrants of level-1 ranges")
+    im = _img(img)
+    h, w = im.shape
+    c1 = encode(im, b1, t1, tol=tol1, nthreads=nthreads)
+    split = c1["err"] > split_threshold(b1, rms)
+    c1["flags"] = c1["flags"] | np.where(split, 2, 0).astype(np.int32)
+    rc1, rc2 = w // b1, w // b2
+    kids = []
+    for r in np.flatnonzero(split):
+        ry, rx = divmod(int(r), rc1)
+        for a in (0, 1):
+            for c in (0, 1):
+                kids.append((2 * ry + a) * rc2 + 2 * rx + c)
+    kids = np.array(sorted(kids), dtype=np.int64)
+    n2 = num_ranges(h, w, b2)
+    c2 = {k: np.zeros(n2, dtype=np.int32) for k in ("dom", "iso", "k", "j", "flags")}
+    for k in ("err", "f", "pool"):
+        c2[k] = np.zeros(n2, dtype=np.int64)
+    c2["flags"][:] = 4
+    if kids.size:
+        sub = encode(im, b2, t2, tol=tol2, sel=kids, nthreads=nthreads)
+        for k in ("dom", "iso", "k", "j", "flags", "err", "f", "pool"):
+            c2[k][kids] = sub[k]
+    return c1, c2
+
+
+def decode_quadtree(c1, c2, h, w, b1, t1, b2, t2, max_iters=32, init=None, nthreads=0):
+    """Decoded image of a two-level code set and the number of sweeps run."""
+    a1 = [np.ascontiguousarray(c1[k], dtype=np.int32) for k in ("dom", "iso", "k", "j")]
+    a2 = [np.ascontiguousarray(c2[k], dtype=np.int32) for k in ("dom", "iso", "k", "j")]
+    split1 = np.ascontiguousarray((np.asarray(c1["flags"]) & 2) != 0, dtype=np.uint8)
+    coded2 = np.ascontiguousarray((np.asarray(c2["flags"]) & 4) == 0, dtype=np.uint8)
+    out = np.empty((h, w), dtype=np.uint8)
+    it = ctypes.c_int32(0)
+    ini = _img(init) if init is not None else None
+    rc = lib().fico_decode_quadtree(*a1, split1, b1, t1, *a2, coded2, b2, t2, h, w,
+                                    int(max_iters), ini.ctypes.data if ini is not None else None,
+                                    out, ctypes.byref(it), int(nthreads))
     if rc != 0:
         raise ValueError("oracle: invalid geometry")
     return out, int(it.value)

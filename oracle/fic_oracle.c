@@ -406,8 +406,8 @@ static int64_t floor_div(int64_t a, int64_t d)
 /* One simultaneous (Jacobi) sweep: every range pixel becomes the rounded
    value of its map applied to the current image. Returns #changed pixels. */
 static int64_t decode_sweep(const int32_t *dom, const int32_t *iso, const int32_t *kq,
-                            const int32_t *jq, int32_t h, int32_t w, int32_t b, int32_t t,
-                            const uint8_t *cur, uint8_t *nxt)
+                            const int32_t *jq, const uint8_t *skip, int32_t h, int32_t w,
+                            int32_t b, int32_t t, const uint8_t *cur, uint8_t *nxt)
 {
     int32_t n = b * b, rcols = w / b, dcols = dom_cols(w, b, t);
     int64_t nr = fico_num_ranges(h, w, b), changed = 0;
@@ -415,6 +415,7 @@ static int64_t decode_sweep(const int32_t *dom, const int32_t *iso, const int32_
 #pragma omp parallel for schedule(static) reduction(+ : changed)
 #endif
     for (int64_t r = 0; r < nr; ++r) {
+        if (skip && skip[r]) continue;   /* its pixels belong to the other level */
         int64_t dsum[1024], tdsum[1024];
         int32_t dy = (dom[r] / dcols) * t, dx = (dom[r] % dcols) * t;
         int64_t sd = 0;
@@ -458,7 +459,7 @@ int32_t fico_decode(const int32_t *dom, const int32_t *iso, const int32_t *kq,
     if (init) memcpy(a, init, np); else memset(a, 128, np);
     int32_t it = 0;
     for (; it < max_iters; ) {
-        int64_t ch = decode_sweep(dom, iso, kq, jq, h, w, b, t, a, bb);
+        int64_t ch = decode_sweep(dom, iso, kq, jq, NULL, h, w, b, t, a, bb);
         uint8_t *tmp = a; a = bb; bb = tmp;
         ++it;
         if (ch == 0) break;
@@ -466,5 +467,42 @@ int32_t fico_decode(const int32_t *dom, const int32_t *iso, const int32_t *kq,
     memcpy(out, a, np);
     *iters_done = it;
     free(a); free(bb);
+    return 0;
+}
+
+/* Two-level (quadtree) decode: each simultaneous sweep applies the level-1
+   maps of the ranges that were not split (split1[r] == 0) and the level-2
+   maps of the sub-ranges that were coded (coded2[r] != 0); together they
+   cover every pixel once. Same stop rule as fico_decode. */
+int32_t fico_decode_quadtree(const int32_t *dom1, const int32_t *iso1, const int32_t *k1,
+                             const int32_t *j1, const uint8_t *split1, int32_t b1, int32_t t1,
+                             const int32_t *dom2, const int32_t *iso2, const int32_t *k2,
+                             const int32_t *j2, const uint8_t *coded2, int32_t b2, int32_t t2,
+                             int32_t h, int32_t w, int32_t max_iters, const uint8_t *init,
+                             uint8_t *out, int32_t *iters_done, int32_t nthreads)
+{
+    if (b1 <= 0 || b2 <= 0 || b1 != 2 * b2 || t1 <= 0 || t2 <= 0 || h % b1 || w % b1 ||
+        h < 2 * b1 || w < 2 * b1)
+        return -1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+    size_t np = (size_t)h * w;
+    int64_t n2 = fico_num_ranges(h, w, b2);
+    uint8_t *skip2 = (uint8_t *)malloc((size_t)n2);
+    for (int64_t r = 0; r < n2; ++r) skip2[r] = coded2[r] ? 0 : 1;
+    uint8_t *a = (uint8_t *)malloc(np), *bb = (uint8_t *)malloc(np);
+    if (init) memcpy(a, init, np); else memset(a, 128, np);
+    int32_t it = 0;
+    for (; it < max_iters; ) {
+        int64_t ch = decode_sweep(dom1, iso1, k1, j1, split1, h, w, b1, t1, a, bb);
+        ch += decode_sweep(dom2, iso2, k2, j2, skip2, h, w, b2, t2, a, bb);
+        uint8_t *tmp = a; a = bb; bb = tmp;
+        ++it;
+        if (ch == 0) break;
+    }
+    memcpy(out, a, np);
+    *iters_done = it;
+    free(a); free(bb); free(skip2);
     return 0;
 }

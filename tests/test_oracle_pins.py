@@ -357,3 +357,78 @@ def test_window_is_closed(oracle_lib):
     got = oracle_lib.encode(img, 4, 2, tol=0.1, fds=(fr, fd))
     assert np.all(got["pool"] == 2)
     assert set(np.unique(got["dom"])) <= {3, 7}
+
+
+# ----------------------------------------------------------- quadtree (ref. [12])
+def _qt_image(seed, n=64):
+    from synth import fbm
+    return fbm(n, n, 0.6, np.random.default_rng(seed))
+
+
+def test_quadtree_without_split_is_the_level1_encode(oracle_lib):
+    """rms = inf: no range is split; level 1 is the plain encode and the
+    two-level decode is the single-level decode."""
+    import oracle
+    img = _qt_image(21)
+    c1, c2 = oracle.encode_quadtree(img, 8, 2, 0.1, 4, 2, 0.1, rms=float("inf"))
+    ref = oracle.encode(img, 8, 2, tol=0.1)
+    for k in ("dom", "iso", "k", "j", "flags", "err"):
+        assert np.array_equal(c1[k], ref[k]), k
+    assert np.all(c2["flags"] == 4) and np.all(c2["err"] == 0)
+    a, ia = oracle.decode_quadtree(c1, c2, 64, 64, 8, 2, 4, 2, max_iters=12)
+    b, ib = oracle.decode(ref, 64, 64, 8, 2, max_iters=12)
+    assert np.array_equal(a, b) and ia == ib
+
+
+def test_quadtree_all_split_is_the_level2_encode(oracle_lib):
+    """rms = 0 on an image where every range has E > 0: every range splits;
+    level 2 is the full level-2 encode and the decode is its decode."""
+    import oracle
+    rng = np.random.default_rng(22)
+    img = rng.integers(0, 256, (64, 64)).astype(np.uint8)
+    c1, c2 = oracle.encode_quadtree(img, 8, 1, None, 4, 2, None, rms=0.0)
+    assert np.all(c1["err"] > 0) and np.all((c1["flags"] & 2) != 0)
+    ref = oracle.encode(img, 4, 2)
+    for k in ("dom", "iso", "k", "j", "flags", "err"):
+        assert np.array_equal(c2[k], ref[k]), k
+    a, ia = oracle.decode_quadtree(c1, c2, 64, 64, 8, 1, 4, 2, max_iters=10)
+    b, ib = oracle.decode(ref, 64, 64, 4, 2, max_iters=10)
+    assert np.array_equal(a, b) and ia == ib
+
+
+@pytest.mark.parametrize("rms", [11.0, 13.7, 16.0])
+def test_quadtree_split_rule_and_children(oracle_lib, rms):
+    """A range splits exactly when its mean squared error E/(4096 n^2)
+    exceeds rms^2; the coded level-2 ranges are exactly those whose parent
+    (the level-1 range holding their pixels) split."""
+    import oracle
+    img = _qt_image(23)
+    c1, c2 = oracle.encode_quadtree(img, 8, 2, 0.05, 4, 2, 0.05, rms=rms)
+    mse = c1["err"].astype(np.float64) / (4096.0 * 64 * 64)
+    split = (c1["flags"] & 2) != 0
+    assert np.array_equal(split, mse > rms * rms)
+    assert 0 < split.sum() < split.size      # a partial split exercises the geometry
+    rc1, rc2 = 64 // 8, 64 // 4
+    r2 = np.arange(c2["flags"].size)
+    parent = (r2 // rc2 // 2) * rc1 + (r2 % rc2) // 2
+    coded = (c2["flags"] & 4) == 0
+    assert np.array_equal(coded, split[parent])
+    assert np.all(c2["err"][~coded] == 0) and np.all(c2["dom"][~coded] == 0)
+
+
+def test_quadtree_sweep_is_the_union_of_level_sweeps(oracle_lib):
+    """One two-level sweep from a start image equals, pixel by pixel, one
+    level-1 sweep on the unsplit ranges and one level-2 sweep on the coded
+    sub-ranges, each from the same start image."""
+    import oracle
+    img = _qt_image(24)
+    c1, c2 = oracle.encode_quadtree(img, 8, 2, 0.05, 4, 2, 0.05, rms=15.3)
+    assert 0 < ((c1["flags"] & 2) != 0).sum() < 64
+    start = np.random.default_rng(5).integers(0, 256, (64, 64)).astype(np.uint8)
+    q, _ = oracle.decode_quadtree(c1, c2, 64, 64, 8, 2, 4, 2, max_iters=1, init=start)
+    s1, _ = oracle.decode(c1, 64, 64, 8, 2, max_iters=1, init=start)
+    s2, _ = oracle.decode(c2, 64, 64, 4, 2, max_iters=1, init=start)
+    split = ((c1["flags"] & 2) != 0).reshape(8, 8)
+    from_l2 = np.kron(split, np.ones((8, 8), dtype=bool))
+    expect = np.where(from_l2, s2, s1)
+    assert np.array_equal(q, expect)
