@@ -99,6 +99,8 @@ def main():
     wl = WORKLOADS[args.workload]
     if wl.name == "batch64_mixed":
         out = bench_batch(args, fic, wl)
+    elif wl.rms is not None:
+        out = bench_quadtree(args, fic, wl, workload_images(args.workload))
     else:
         out = bench_image(args, fic, wl, workload_images(args.workload))
     print(json.dumps(out))
@@ -333,6 +335,81 @@ def bench_image(args, fic, wl, img_np):
         out["cpu_baseline"] = oracle_rate(
             img_np, bd, td, told, sizes[dom], D[(bd, td)], args.cpu_seconds,
             "%s, %s" % (wl.name, job_label(bd, td, told, multi)))
+    return out
+
+
+def bench_quadtree(args, fic, wl, img_np):
+    """One step = one two-level encode (fic_encode_quadtree): classify, pool
+    and search the 16x16 ranges, split, classify, pool and search the
+    quadrants of the split ranges. Pair evaluations count level 1 in full and
+    level 2 only for the coded quadrants."""
+    import numpy as np
+    import torch
+
+    dev = torch.device("cuda:0")
+    img = torch.from_numpy(img_np).to(dev)
+    H, W = img_np.shape
+    (b1, t1, tol1), (b2, t2, tol2) = wl.jobs
+    ctx = fic.fic.context(0)
+    c1, c2 = fic.encode_quadtree(img, b1, t1, tol1, b2, t2, tol2, wl.rms)
+
+    def step():
+        fic.encode_quadtree(img, b1, t1, tol1, b2, t2, tol2, wl.rms, codes=(c1, c2))
+
+    torch.cuda.synchronize()
+    sizes = []
+    for (b, t, tol) in wl.jobs:
+        fr, _ = fic.fd_classify(img, b, b, want_fp32=False)
+        fd, _ = fic.fd_classify(img, 2 * b, t, want_fp32=False)
+        _, lo, hi = fic.build_domain_pool(fr, fd, tol)
+        sizes.append((hi.long() - lo.long()).cpu().numpy())
+    coded = (fic.unpack_codes(c2)["flags"] & 4) == 0
+    split = int(((fic.unpack_codes(c1)["flags"] & 2) != 0).sum())
+    pairs = [int(sizes[0].sum()) * 8, int(sizes[1][coded].sum()) * 8]
+    pairs_step = sum(pairs)
+    progress("%s: %d of %d ranges split, %d pair evaluations per step"
+             % (wl.name, split, sizes[0].size, pairs_step))
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t_start) * 1e3 / args.steps
+    recs = ctx.timing_read()
+    ctx.timing(False)
+    progress("timed %d steps: %.3f ms per step" % (args.steps, ms_step))
+    stage_ms = stage_sums(recs, args.steps)
+    searches = [ms for (name, ms) in recs if name == "search"]
+    lv_ms = [float(np.mean(searches[0::2])), float(np.mean(searches[1::2]))]
+    dom = 0 if lv_ms[0] >= lv_ms[1] else 1
+    bd = wl.jobs[dom][0]
+    roofline = roofline_of("k_search_mfma<%d> (level %d)" % (bd, dom + 1),
+                           pairs[dom] * 2 * bd * bd, lv_ms[dom] / 1e3)
+    out = {
+        "metric": METRIC,
+        "value": round(pairs_step / (ms_step / 1e3), 1),
+        "unit": "pair evals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f16", "data": "synthetic",
+        "config": {"workload": wl.name, "description": wl.description,
+                   "image": "%dx%d" % (H, W), "rms_split": wl.rms,
+                   "split_ranges": split, "level1_ranges": int(sizes[0].size),
+                   "pairs_per_step": pairs_step, "pairs_per_level": pairs},
+        "encode_s_per_image": round(ms_step / 1e3, 6),
+        "search_ms_per_level": [round(v, 4) for v in lv_ms],
+        "search_pairs_per_s_per_level": [round(p / (m / 1e3), 1) for p, m in zip(pairs, lv_ms)],
+        "stage_ms_per_step": {k: round(v, 4) for k, v in stage_ms.items()},
+        "roofline": roofline,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = oracle_rate(img_np, b1, t1, tol1, sizes[0], None, args.cpu_seconds,
+                                          "%s, level 1 (b%dt%d pool %g)" % (wl.name, b1, t1, tol1))
     return out
 
 

@@ -15,6 +15,8 @@
  *                          quantized contrast / brightness; exhaustive or pooled.
  *   fic_encode_pifs_batch  the same for many images of different sizes.
  *   fic_decode_pifs        Sec. 1: iterate the maps from a start image.
+ *   fic_encode_quadtree /  a two-level range partition (ref. [12]) on top of
+ *   fic_decode_quadtree    the same search and decoder.
  *
  * Quantities (exact integers; n = B*B; D = 2x2 sums of the domain, 0..1020):
  *   contrast   s = k/16, k in [-16, 15]        (5 bits)
@@ -78,7 +80,8 @@ typedef struct {
     int8_t   s_idx;    /* k, s = k/16                                         */
     uint8_t  o_idx;    /* j, o = 2j                                           */
     uint8_t  flags;    /* bit 0: empty pool, DC-only code (domain 0, iso 0,
-                          k = 0)                                              */
+                          k = 0); bit 1: split (two-level encode); bit 2:
+                          not coded (two-level encode, parent not split)     */
     int64_t  err;      /* E = 4096 * n * SSE                                  */
 } fic_code;
 
@@ -239,6 +242,43 @@ fic_status fic_decode_pifs(fic_ctx *ctx, const fic_code *codes, const fic_geom *
                            int32_t max_iters, const uint8_t *init, uint8_t *out,
                            void *scratch, size_t scratch_bytes, int32_t *iters_done,
                            void *stream);
+
+/* ------------------------------------------------------------------------
+ * fic_encode_quadtree -- two-level partition of the range grid (the quadtree
+ * of Fisher's book, the paper's ref. [12], at two levels). The paper does
+ * not specify it; the rule here:
+ *   - every level-1 range (g1: B1 in {8, 16}) is coded as fic_encode_pifs
+ *     does (pool from tol1 as in fic_image_desc, or exhaustive);
+ *   - a level-1 code is split when its mean squared error exceeds
+ *     rms_split^2, i.e. when E > floor(4096 * n1^2 * rms_split^2) (fp64 in
+ *     the order rms*rms*(4096*n1*n1)); its flags get bit 1 and its four
+ *     quadrants, the level-2 ranges (g2: B2 = B1/2, same height, width and
+ *     pitch, its own domain step) holding its pixels, are coded as
+ *     fic_encode_pifs does over the whole level-2 domain lattice (pool from
+ *     tol2 or exhaustive);
+ *   - every other level-2 code is "not coded": domain 0, iso 0, k = 0, j = 0,
+ *     flags bit 2, E = 0.
+ *   img     (dev) uint8 image; codes1 (dev) fic_code[R1]; codes2 (dev)
+ *           fic_code[R2], raster order on each grid.
+ *   rms_split >= 0 (gray levels); +INF never splits, 0 splits every code
+ *           with E > 0. NaN or negative is rejected.
+ *   ws      (dev) >= fic_quadtree_workspace_bytes(g1, tol1, g2, tol2).
+ * ---------------------------------------------------------------------- */
+size_t fic_quadtree_workspace_bytes(const fic_geom *g1, double tol1, const fic_geom *g2,
+                                    double tol2);
+fic_status fic_encode_quadtree(fic_ctx *ctx, const uint8_t *img, const fic_geom *g1, double tol1,
+                               const fic_geom *g2, double tol2, double rms_split,
+                               fic_code *codes1, fic_code *codes2, void *ws, size_t ws_bytes,
+                               void *stream);
+
+/* fic_decode_quadtree -- fic_decode_pifs for a two-level code set: each
+   sweep applies the level-1 codes without flag bit 1 and the level-2 codes
+   without flag bit 2, all from the previous image (every pixel once).
+   scratch (dev) >= fic_decode_workspace_bytes(g1). */
+fic_status fic_decode_quadtree(fic_ctx *ctx, const fic_code *codes1, const fic_geom *g1,
+                               const fic_code *codes2, const fic_geom *g2, int32_t max_iters,
+                               const uint8_t *init, uint8_t *out, void *scratch,
+                               size_t scratch_bytes, int32_t *iters_done, void *stream);
 
 #ifdef __cplusplus
 }

@@ -8,6 +8,7 @@
 #include <new>
 #include <string.h>
 #include <math.h>
+#include <stdint.h>
 #include <vector>
 
 #include "fic_internal.h"
@@ -466,6 +467,67 @@ fic_status fic_encode_pifs_batch(fic_ctx *ctx, int32_t n_images, const fic_image
     const hipError_t e = hipGraphLaunch(ctx->graphs.back().exec, s);
     fic::trace(tr, FIC_STAGE_BATCH, 0, s);
     return dev_status(e);
+}
+
+// ---------------------------------------------------------------- quadtree
+namespace {
+bool quad_geoms_ok(const fic_geom *g1, const fic_geom *g2)
+{
+    if (!geom_ok(g1) || !geom_ok(g2)) return false;
+    if (g1->range_size != 2 * g2->range_size) return false;
+    return g1->height == g2->height && g1->width == g2->width && g1->pitch == g2->pitch;
+}
+bool pooled_of(double tol) { return isfinite(tol) || tol < 0; }
+}  // namespace
+
+size_t fic_quadtree_workspace_bytes(const fic_geom *g1, double tol1, const fic_geom *g2,
+                                    double tol2)
+{
+    if (!quad_geoms_ok(g1, g2) || isnan(tol1) || isnan(tol2)) return 0;
+    fic::QuadPlan qp;
+    fic::plan_quadtree(to_geom(g1), tol1, to_geom(g2), tol2, qp);
+    return qp.total;
+}
+
+fic_status fic_encode_quadtree(fic_ctx *ctx, const uint8_t *img, const fic_geom *g1, double tol1,
+                               const fic_geom *g2, double tol2, double rms_split,
+                               fic_code *codes1, fic_code *codes2, void *ws, size_t ws_bytes,
+                               void *stream)
+{
+    if (!ctx || !img || !codes1 || !codes2 || !ws) return FIC_ERR_INVALID_ARG;
+    if (!quad_geoms_ok(g1, g2) || isnan(tol1) || isnan(tol2)) return FIC_ERR_INVALID_ARG;
+    if (isnan(rms_split) || rms_split < 0) return FIC_ERR_INVALID_ARG;
+    const Geom gg1 = to_geom(g1), gg2 = to_geom(g2);
+    if (!key_fits(gg1) || !key_fits(gg2)) return FIC_ERR_CAPACITY;
+    fic::QuadPlan qp;
+    fic::plan_quadtree(gg1, tol1, gg2, tol2, qp);
+    if (ws_bytes < qp.total) return FIC_ERR_WORKSPACE;
+    // E is split when E > 4096 * n^2 * rms^2 (fp64, in this operation order),
+    // i.e. when it exceeds that bound floored to an integer.
+    const double n1 = (double)gg1.n;
+    const double t = rms_split * rms_split * (4096.0 * n1 * n1);
+    const int64_t emax = t < 9.0e18 ? (int64_t)floor(t) : INT64_MAX;
+    fic_status st = enter(ctx);
+    if (st != FIC_OK) return st;
+    return dev_status(fic::run_quadtree(qp, img, emax, codes1, codes2, ws, ctx->num_cu,
+                                        ctx->counters, (hipStream_t)stream, tracer_of(ctx)));
+}
+
+fic_status fic_decode_quadtree(fic_ctx *ctx, const fic_code *codes1, const fic_geom *g1,
+                               const fic_code *codes2, const fic_geom *g2, int32_t max_iters,
+                               const uint8_t *init, uint8_t *out, void *scratch,
+                               size_t scratch_bytes, int32_t *iters_done, void *stream)
+{
+    if (!ctx || !codes1 || !codes2 || !out || !scratch || !iters_done) return FIC_ERR_INVALID_ARG;
+    if (!quad_geoms_ok(g1, g2)) return FIC_ERR_INVALID_ARG;
+    if (max_iters < 0 || max_iters > fic::decode_max_iters()) return FIC_ERR_INVALID_ARG;
+    const Geom gg1 = to_geom(g1), gg2 = to_geom(g2);
+    if (scratch_bytes < fic::decode_ws_bytes(gg1)) return FIC_ERR_WORKSPACE;
+    fic_status st = enter(ctx);
+    if (st != FIC_OK) return st;
+    return dev_status(fic::run_decode_quadtree(gg1, codes1, gg2, codes2, max_iters, init, out,
+                                               scratch, iters_done, (hipStream_t)stream,
+                                               tracer_of(ctx)));
 }
 
 size_t fic_decode_workspace_bytes(const fic_geom *g)

@@ -28,8 +28,11 @@ __global__ void k_decode_init(const uint8_t *__restrict__ init, int64_t np, uint
     if (i == 0) *iters = 0;
 }
 
+// Codes whose flags meet skip_flags write nothing (in a two-level decode
+// their pixels belong to the other level).
 template <int B>
 __global__ __launch_bounds__(256) void k_decode_sweep(const fic_code *__restrict__ codes, Geom g,
+                                                      uint8_t skip_flags,
                                                       const uint8_t *__restrict__ cur,
                                                       uint8_t *__restrict__ nxt,
                                                       uint32_t *__restrict__ changed,
@@ -45,12 +48,12 @@ __global__ __launch_bounds__(256) void k_decode_sweep(const fic_code *__restrict
     if (tid == 0) nchg = 0;
     __syncthreads();
     fic_code c;
-    c.domain = 0; c.iso = 0; c.s_idx = 0; c.o_idx = 0;
+    c.domain = 0; c.iso = 0; c.s_idx = 0; c.o_idx = 0; c.flags = 0;
     if (r < g.R) c = codes[r];
+    const bool inside = r < g.R && !(c.flags & skip_flags);
     // a code naming a domain or isometry outside the lattice is not applied
     // (its range decodes to 0) rather than read outside the image
-    const bool valid = r < g.R && c.domain < (uint64_t)g.D && c.iso < 8;
-    const bool inside = r < g.R;
+    const bool valid = inside && c.domain < (uint64_t)g.D && c.iso < 8;
     int dv = 0;
     int u = i / B, v = i % B;
     if (valid) {
@@ -114,8 +117,8 @@ hipError_t run_b(const Geom &g, const fic_code *codes, int32_t max_iters, const 
     for (int it = 0; it < max_iters; ++it) {
         const uint8_t *src = (it & 1) ? b1 : b0;
         uint8_t *dst = (it & 1) ? b0 : b1;
-        hipLaunchKernelGGL(k_decode_sweep<B>, dim3(nb), dim3(256), 0, s, codes, g, src, dst,
-                           flags + it, done);
+        hipLaunchKernelGGL(k_decode_sweep<B>, dim3(nb), dim3(256), 0, s, codes, g, (uint8_t)0,
+                           src, dst, flags + it, done);
         hipLaunchKernelGGL(k_decode_check, dim3(1), dim3(64), 0, s, it, flags, done, iters);
     }
     hipLaunchKernelGGL(k_decode_out, dim3((unsigned)((np + th - 1) / th)), dim3(th), 0, s, b0, b1,
@@ -124,7 +127,60 @@ hipError_t run_b(const Geom &g, const fic_code *codes, int32_t max_iters, const 
     return hipGetLastError();
 }
 
+template <int B>
+void sweep_b(const Geom &g, const fic_code *codes, uint8_t skip, const uint8_t *src, uint8_t *dst,
+             uint32_t *changed, const uint32_t *done, hipStream_t s)
+{
+    constexpr int RPB = 256 / (B * B);
+    const unsigned nb = (unsigned)((g.R + RPB - 1) / RPB);
+    hipLaunchKernelGGL(k_decode_sweep<B>, dim3(nb), dim3(256), 0, s, codes, g, skip, src, dst,
+                       changed, done);
+}
+
+void sweep(const Geom &g, const fic_code *codes, uint8_t skip, const uint8_t *src, uint8_t *dst,
+           uint32_t *changed, const uint32_t *done, hipStream_t s)
+{
+    switch (g.b) {
+    case 4: sweep_b<4>(g, codes, skip, src, dst, changed, done, s); break;
+    case 8: sweep_b<8>(g, codes, skip, src, dst, changed, done, s); break;
+    default: sweep_b<16>(g, codes, skip, src, dst, changed, done, s); break;
+    }
+}
+
 }  // namespace
+
+// Two-level decode: each sweep applies the level-1 codes that were not split
+// (flag bit 1) and the level-2 codes that were coded (no flag bit 2), from
+// the same image; together they write every pixel once.
+hipError_t run_decode_quadtree(const Geom &g1, const fic_code *codes1, const Geom &g2,
+                               const fic_code *codes2, int32_t max_iters, const uint8_t *init,
+                               uint8_t *out, void *ws, int32_t *iters, hipStream_t s,
+                               const Tracer *tr)
+{
+    trace(tr, FIC_STAGE_DECODE, 1, s);
+    const int64_t np = (int64_t)g1.h * g1.w;
+    char *w = (char *)ws;
+    uint8_t *b0 = (uint8_t *)w;
+    uint8_t *b1 = (uint8_t *)(w + align256(np));
+    uint32_t *flags = (uint32_t *)(w + 2 * align256(np));
+    uint32_t *done = flags + kMaxIters;
+    const int th = 256;
+    const int64_t nfl = kMaxIters + 1;
+    const int64_t nthr = np > nfl ? np : nfl;
+    hipLaunchKernelGGL(k_decode_init, dim3((unsigned)((nthr + th - 1) / th)), dim3(th), 0, s, init,
+                       np, b0, flags, (int32_t)nfl, iters);
+    for (int it = 0; it < max_iters; ++it) {
+        const uint8_t *src = (it & 1) ? b1 : b0;
+        uint8_t *dst = (it & 1) ? b0 : b1;
+        sweep(g1, codes1, 2, src, dst, flags + it, done, s);
+        sweep(g2, codes2, 4, src, dst, flags + it, done, s);
+        hipLaunchKernelGGL(k_decode_check, dim3(1), dim3(64), 0, s, it, flags, done, iters);
+    }
+    hipLaunchKernelGGL(k_decode_out, dim3((unsigned)((np + th - 1) / th)), dim3(th), 0, s, b0, b1,
+                       np, iters, out);
+    trace(tr, FIC_STAGE_DECODE, 0, s);
+    return hipGetLastError();
+}
 
 size_t decode_ws_bytes(const Geom &g)
 {

@@ -25,6 +25,7 @@
 #include "fic_internal.h"
 
 #include <algorithm>
+#include <cmath>
 #include <vector>
 
 namespace fic {
@@ -78,12 +79,12 @@ __global__ void k_fill_u64(u64 *p, int64_t n, u64 v)
 // both grow with the range's dimension, so along this order the first and
 // last column of every group never decrease, and the groups that touch a
 // column chunk form one contiguous run (the work list needs no atomics).
-// Exhaustive search only moves the flat ranges to the end.
+// Exhaustive search only moves the flat (and unselected) ranges to the end.
 template <int B>
 __global__ void k_range_keys(const uint8_t *__restrict__ img, int32_t pitch, int32_t rcols, int64_t R,
                              const uint32_t *__restrict__ lo, const uint32_t *__restrict__ hi,
-                             uint32_t D, int dbits, u64 *__restrict__ keys,
-                             uint32_t *__restrict__ vals)
+                             const uint8_t *__restrict__ sel, uint32_t D, int dbits,
+                             u64 *__restrict__ keys, uint32_t *__restrict__ vals)
 {
     constexpr int n = B * B;
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -99,7 +100,7 @@ __global__ void k_range_keys(const uint8_t *__restrict__ img, int32_t pitch, int
         }
     const bool flat = (int64_t)n * sq - (int64_t)sr * sr == 0;
     const uint32_t l = lo ? lo[r] : 0u, h = hi ? hi[r] : D;
-    const bool idle = flat || l >= h;
+    const bool idle = flat || l >= h || (sel && !sel[r]);
     u64 key;
     if (!lo) key = idle ? 1ull : 0ull;
     else key = idle ? (1ull << (2 * dbits)) - 1ull : (((u64)l << dbits) | (u64)h);
@@ -111,8 +112,8 @@ template <int B>
 __global__ __launch_bounds__(256) void k_range_prep(
     const uint8_t *__restrict__ img, int32_t pitch, int32_t rcols, int64_t R, int64_t Rp,
     const uint32_t *__restrict__ order, const uint32_t *__restrict__ lo,
-    const uint32_t *__restrict__ hi, uint32_t D, _Float16 *__restrict__ A,
-    RangeStat *__restrict__ rs)
+    const uint32_t *__restrict__ hi, const uint8_t *__restrict__ sel, uint32_t D,
+    _Float16 *__restrict__ A, RangeStat *__restrict__ rs)
 {
     using C = Cfg<B>;
     constexpr int n = C::n, MR = C::MR, KPI = C::KPI, EPL = C::EPL, KS = C::KS, MB = C::MB,
@@ -161,7 +162,9 @@ __global__ __launch_bounds__(256) void k_range_prep(
         st.ridx = ridx;
         st.lo = valid ? (lo ? lo[ridx] : 0u) : 0u;
         st.hi = valid ? (hi ? hi[ridx] : D) : 0u;
-        st.flags = !valid ? kPad : ((st.srr == 0 ? kFlat : 0u) | (st.lo >= st.hi ? kEmpty : 0u));
+        st.flags = !valid ? kPad
+                          : ((st.srr == 0 ? kFlat : 0u) | (st.lo >= st.hi ? kEmpty : 0u) |
+                             (sel && !sel[ridx] ? kSkip : 0u));
         rs[s] = st;
     }
 }
@@ -308,7 +311,7 @@ __global__ __launch_bounds__(256) void k_seed(const _Float16 *__restrict__ A,
     const int lane = threadIdx.x & 63;
     if (s >= Rp) return;
     const RangeStat st = rs[s];
-    if (st.flags & (kPad | kEmpty)) {
+    if (st.flags & (kPad | kEmpty | kSkip)) {
         if (lane == 0) keys[s] = kNoKey;
         return;
     }
@@ -381,7 +384,7 @@ __global__ void k_group_bounds(const RangeStat *__restrict__ rs, int64_t G, int 
     bool any = false;
     for (int r = 0; r < GR; ++r) {
         const RangeStat st = rs[gi * GR + r];
-        if (st.flags & (kPad | kFlat | kEmpty)) continue;
+        if (st.flags & kIdle) continue;
         any = true;
         L = min(L, st.lo);
         H = max(H, st.hi);
@@ -761,7 +764,7 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma(const SearchArgs *__rest
             const u64 bk = a.keys[slot];
             st.lo[b] = rsx.lo;
             st.hi[b] = rsx.hi;
-            const bool act = !(rsx.flags & (kPad | kFlat | kEmpty));
+            const bool act = !(rsx.flags & kIdle);
             st.T[b] = !act ? __builtin_inff()
                            : (bk == kNoKey ? 0.0f : screen_t(rsx.srr, (int64_t)(bk >> a.shift)));
         }
@@ -1066,7 +1069,7 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma32(const SearchArgs *__re
                 const u64 bk = a.keys[slot];
                 st.lo[blk][hl] = rsx.lo;
                 st.hi[blk][hl] = rsx.hi;
-                const bool act = !(rsx.flags & (kPad | kFlat | kEmpty));
+                const bool act = !(rsx.flags & kIdle);
                 st.T[blk][hl] = !act ? __builtin_inff()
                                      : (bk == kNoKey ? 0.0f
                                                      : screen_t(rsx.srr, (int64_t)(bk >> a.shift)));
@@ -1191,12 +1194,19 @@ __global__ __launch_bounds__(256) void k_search_plain(
 template <int B>
 __global__ void k_finalize(const uint8_t *__restrict__ img, Geom g,
                            const uint32_t *__restrict__ order, const u64 *__restrict__ keys,
-                           int shift, fic_code *__restrict__ codes)
+                           const uint8_t *__restrict__ sel, int shift,
+                           fic_code *__restrict__ codes)
 {
     constexpr int n = B * B;
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= g.R) return;
     const uint32_t ridx = order ? order[s] : (uint32_t)s;
+    if (sel && !sel[ridx]) {             // not coded: flag bit 2, everything else 0
+        fic_code c;
+        c.domain = 0; c.iso = 0; c.s_idx = 0; c.o_idx = 0; c.flags = 4; c.err = 0;
+        codes[ridx] = c;
+        return;
+    }
     const int ry = (int)(ridx / g.rcols) * B, rx = (int)(ridx % g.rcols) * B;
     int32_t sr = 0;
     int64_t sq = 0;
@@ -1236,6 +1246,24 @@ __global__ void k_finalize(const uint8_t *__restrict__ img, Geom g,
 
 inline unsigned blocks_for(int64_t n, int th) { return (unsigned)((n + th - 1) / th); }
 
+// Two-level partition: a level-1 range whose E exceeds emax is split -- its
+// code gets flag bit 1 and its four quadrants (the level-2 ranges holding its
+// pixels) are selected for level 2; every level-2 range is written.
+__global__ void k_split(fic_code *__restrict__ codes1, int64_t R1, int32_t rcols1,
+                        int32_t rcols2, int64_t emax, uint8_t *__restrict__ sel2)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R1) return;
+    const bool split = codes1[r].err > emax;
+    if (split) codes1[r].flags |= 2;
+    const int64_t ry = r / rcols1, rx = r % rcols1;
+    const uint8_t v = split ? 1 : 0;
+    sel2[(2 * ry) * rcols2 + 2 * rx] = v;
+    sel2[(2 * ry) * rcols2 + 2 * rx + 1] = v;
+    sel2[(2 * ry + 1) * rcols2 + 2 * rx] = v;
+    sel2[(2 * ry + 1) * rcols2 + 2 * rx + 1] = v;
+}
+
 // Plain search: 2x2 sums, then one thread per (range, position, isometry).
 template <int B>
 hipError_t run_plain_b(const EncodePlan &p, const uint8_t *img, const uint32_t *perm,
@@ -1262,7 +1290,7 @@ hipError_t run_plain_b(const EncodePlan &p, const uint8_t *img, const uint32_t *
     trace(tr, FIC_STAGE_SEARCH, 0, s);
     trace(tr, FIC_STAGE_FINAL, 1, s);
     hipLaunchKernelGGL(k_finalize<B>, dim3(blocks_for(g.R, th)), dim3(th), 0, s, img, g,
-                       (const uint32_t *)nullptr, keys, p.shift, codes);
+                       (const uint32_t *)nullptr, keys, p.sel, p.shift, codes);
     trace(tr, FIC_STAGE_FINAL, 0, s);
     return hipGetLastError();
 }
@@ -1301,7 +1329,7 @@ hipError_t prep_b(const EncodePlan &p, const uint8_t *img, const uint32_t *perm,
         while (((int64_t)1 << dbits) <= g.D) ++dbits;
         u64 *sk = (u64 *)(w + p.off_sortkeys);
         hipLaunchKernelGGL(k_range_keys<B>, dim3(blocks_for(g.R, th)), dim3(th), 0, s, img, g.pitch,
-                           g.rcols, g.R, lo, hi, (uint32_t)g.D, dbits, sk, order);
+                           g.rcols, g.R, lo, hi, p.sel, (uint32_t)g.D, dbits, sk, order);
         hipError_t e = radix_sort_pairs(sk, order, g.R, p.pooled ? 2 * dbits : 8, w + p.off_sort, s);
         if (e != hipSuccess) return e;
     }
@@ -1309,7 +1337,8 @@ hipError_t prep_b(const EncodePlan &p, const uint8_t *img, const uint32_t *perm,
         hipLaunchKernelGGL(k_blockmin, dim3(blocks_for((g.D + kBminBlock - 1) / kBminBlock * 64, th)),
                            dim3(th), 0, s, perm, g.D, bmin);
     hipLaunchKernelGGL(k_range_prep<B>, dim3(blocks_for(p.Rp * 8, th)), dim3(th), 0, s, img, g.pitch,
-                       g.rcols, g.R, p.Rp, (const uint32_t *)order, lo, hi, (uint32_t)g.D, A, rs);
+                       g.rcols, g.R, p.Rp, (const uint32_t *)order, lo, hi, p.sel, (uint32_t)g.D, A,
+                       rs);
     trace(tr, FIC_STAGE_RANGE_PREP, 0, s);
     trace(tr, FIC_STAGE_DOMAIN_PREP, 1, s);
     hipLaunchKernelGGL(k_domain_prep<B>, dim3(blocks_for(p.Dp * B, th)), dim3(th), 0, s, img,
@@ -1374,8 +1403,8 @@ hipError_t finalize_b(const EncodePlan &p, const uint8_t *img, void *ws, fic_cod
     char *w = (char *)ws;
     trace(tr, FIC_STAGE_FINAL, 1, s);
     hipLaunchKernelGGL(k_finalize<B>, dim3(blocks_for(p.g.R, 256)), dim3(256), 0, s, img, p.g,
-                       (const uint32_t *)(w + p.off_order), (const u64 *)(w + p.off_keys), p.shift,
-                       codes);
+                       (const uint32_t *)(w + p.off_order), (const u64 *)(w + p.off_keys), p.sel,
+                       p.shift, codes);
     trace(tr, FIC_STAGE_FINAL, 0, s);
     return hipGetLastError();
 }
@@ -1452,6 +1481,7 @@ void plan_encode(const Geom &g, int pooled, EncodePlan &p)
     p.off_sort = take(sort_ws_bytes(p.Rp));
     p.off_scan = take(scan_ws_bytes(p.NC));
     p.total = o;
+    p.sel = nullptr;
 }
 
 hipError_t run_encode(const EncodePlan &p, const uint8_t *img, const uint32_t *perm,
@@ -1594,6 +1624,82 @@ hipError_t run_encode_batch(const BatchJob *jobs, const BatchPlan &bp, void *ws,
         }
     }
     return e;
+}
+
+// ------------------------------------------------------------ quadtree
+// Workspace: per level the FD, pool and encode parts of a batch image, then
+// the level-2 selection.
+void plan_quadtree(const Geom &g1, double tol1, const Geom &g2, double tol2, QuadPlan &qp)
+{
+    BatchJob j[2];
+    j[0].img = nullptr; j[0].g = g1; j[0].tol = tol1; j[0].codes = nullptr;
+    j[1].img = nullptr; j[1].g = g2; j[1].tol = tol2; j[1].codes = nullptr;
+    for (int l = 0; l < 2; ++l) j[l].pooled = std::isfinite(j[l].tol) || j[l].tol < 0;
+    BatchPlan bp;
+    plan_batch(j, 2, bp);
+    size_t o = bp.total;
+    qp.lv[0] = j[0];
+    qp.lv[1] = j[1];
+    qp.part[0] = bp.part[0];
+    qp.part[1] = bp.part[1];
+    qp.off_sel = o;
+    o += align256((size_t)g2.R);
+    qp.total = o;
+}
+
+namespace {
+template <int B>
+hipError_t encode_level(const BatchJob &j, const BatchPart &pt, const uint8_t *img, char *w,
+                        const uint8_t *sel, fic_code *codes, int num_cu, u64 *counters,
+                        hipStream_t s, const Tracer *tr)
+{
+    const Geom &g = j.g;
+    double *fdr = (double *)(w + pt.off_fdr);
+    double *fdd = (double *)(w + pt.off_fdd);
+    uint32_t *perm = (uint32_t *)(w + pt.off_perm);
+    uint32_t *lo = (uint32_t *)(w + pt.off_lo);
+    uint32_t *hi = (uint32_t *)(w + pt.off_hi);
+    hipError_t e = hipSuccess;
+    if (j.pooled) {
+        e = launch_fd_classify(img, g.h, g.w, g.pitch, g.b, g.b, fdr, nullptr, s, tr);
+        if (e == hipSuccess)
+            e = launch_fd_classify(img, g.h, g.w, g.pitch, 2 * g.b, g.t, fdd, nullptr, s, tr);
+        if (e == hipSuccess)
+            e = launch_pool(fdr, (int32_t)g.R, fdd, (int32_t)g.D, j.tol, perm, lo, hi,
+                            w + pt.off_pool, s, tr);
+        if (e != hipSuccess) return e;
+    }
+    EncodePlan p = pt.plan;
+    p.sel = sel;
+    return run_encode_b<B>(p, img, j.pooled ? perm : nullptr, j.pooled ? lo : nullptr,
+                           j.pooled ? hi : nullptr, FIC_KERNEL_MFMA, codes, w + pt.off_enc, num_cu,
+                           counters, s, tr);
+}
+}  // namespace
+
+hipError_t run_quadtree(const QuadPlan &qp, const uint8_t *img, int64_t emax, fic_code *codes1,
+                        fic_code *codes2, void *ws, int num_cu, u64 *counters, hipStream_t s,
+                        const Tracer *tr)
+{
+    char *w = (char *)ws;
+    uint8_t *sel2 = (uint8_t *)(w + qp.off_sel);
+    const Geom &g1 = qp.lv[0].g, &g2 = qp.lv[1].g;
+    hipError_t e;
+    switch (g1.b) {
+    case 8: e = encode_level<8>(qp.lv[0], qp.part[0], img, w, nullptr, codes1, num_cu, counters, s, tr); break;
+    case 16: e = encode_level<16>(qp.lv[0], qp.part[0], img, w, nullptr, codes1, num_cu, counters, s, tr); break;
+    default: return hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_split, dim3(blocks_for(g1.R, 256)), dim3(256), 0, s, codes1, g1.R,
+                       g1.rcols, g2.rcols, emax, sel2);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    switch (g2.b) {
+    case 4: return encode_level<4>(qp.lv[1], qp.part[1], img, w, sel2, codes2, num_cu, counters, s, tr);
+    case 8: return encode_level<8>(qp.lv[1], qp.part[1], img, w, sel2, codes2, num_cu, counters, s, tr);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace fic

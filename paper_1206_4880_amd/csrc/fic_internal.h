@@ -80,9 +80,10 @@ struct RangeStat {
     int32_t delta;   // sum r - n*rhat, rhat = the centring level of the A rows
     uint32_t ridx;   // raster range index
     uint32_t lo, hi; // pool = columns [lo, hi) of the domain order
-    uint32_t flags;  // kFlat | kPad | kEmpty
+    uint32_t flags;  // kFlat | kPad | kEmpty | kSkip
 };
-constexpr uint32_t kFlat = 1u, kPad = 2u, kEmpty = 4u;
+constexpr uint32_t kFlat = 1u, kPad = 2u, kEmpty = 4u, kSkip = 8u;   // kSkip: not selected
+constexpr uint32_t kIdle = kFlat | kPad | kEmpty | kSkip;             // never searched
 
 struct WorkItem { uint32_t grp, c0, c1, pad; };
 
@@ -208,6 +209,9 @@ struct EncodePlan {
     size_t off_A, off_rs, off_order, off_B, off_u, off_eps, off_sdd, off_dom, off_keys,
         off_items, off_ctr, off_args, off_chunkcnt, off_chunkfill, off_grp, off_bmin, off_S,
         off_sort, off_sortkeys, off_scan, total;
+    // (dev) per range, raster order: 0 = not coded (its code gets flag bit 2);
+    // null = every range. Set by the caller after plan_encode.
+    const uint8_t *sel;
 };
 hipError_t init_search_occupancy();   // once per process, before any search launch
 void plan_encode(const Geom &g, int pooled, EncodePlan &p);
@@ -248,6 +252,18 @@ struct BatchStreams {
     hipEvent_t join[kMaxSideStreams];
 };
 void plan_batch(const BatchJob *jobs, int32_t n, BatchPlan &bp);
+
+// Two-level (quadtree) encode: level-1 ranges B1, level-2 ranges B2 = B1/2
+// coded only inside level-1 ranges whose E exceeds emax.
+struct QuadPlan {
+    BatchJob lv[2];                  // img, geometry, tol, pooled per level (codes set per call)
+    BatchPart part[2];
+    size_t off_sel, total;
+};
+void plan_quadtree(const Geom &g1, double tol1, const Geom &g2, double tol2, QuadPlan &qp);
+hipError_t run_quadtree(const QuadPlan &qp, const uint8_t *img, int64_t emax, fic_code *codes1,
+                        fic_code *codes2, void *ws, int num_cu, u64 *counters, hipStream_t s,
+                        const Tracer *tr = nullptr);
 hipError_t run_encode_batch(const BatchJob *jobs, const BatchPlan &bp, void *ws, int num_cu,
                             u64 *counters, hipStream_t s, const Tracer *tr = nullptr,
                             const BatchStreams *bs = nullptr);
@@ -258,5 +274,9 @@ int32_t decode_max_iters();
 hipError_t run_decode(const Geom &g, const fic_code *codes, int32_t max_iters,
                       const uint8_t *init, uint8_t *out, void *ws, int32_t *iters,
                       hipStream_t s, const Tracer *tr = nullptr);
+hipError_t run_decode_quadtree(const Geom &g1, const fic_code *codes1, const Geom &g2,
+                               const fic_code *codes2, int32_t max_iters, const uint8_t *init,
+                               uint8_t *out, void *ws, int32_t *iters, hipStream_t s,
+                               const Tracer *tr = nullptr);
 
 }  // namespace fic

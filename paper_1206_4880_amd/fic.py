@@ -74,6 +74,13 @@ def lib():
         "fic_encode_pifs_batch": (_st, [_vp, _i32, ctypes.POINTER(ImageDesc), _vp,
                                         ctypes.c_size_t, _vp]),
         "fic_set_batch_graph": (_st, [_vp, _i32]),
+        "fic_quadtree_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Geom), ctypes.c_double,
+                                                           ctypes.POINTER(Geom), ctypes.c_double]),
+        "fic_encode_quadtree": (_st, [_vp, _vp, ctypes.POINTER(Geom), ctypes.c_double,
+                                      ctypes.POINTER(Geom), ctypes.c_double, ctypes.c_double,
+                                      _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+        "fic_decode_quadtree": (_st, [_vp, _vp, ctypes.POINTER(Geom), _vp, ctypes.POINTER(Geom),
+                                      _i32, _vp, _vp, _vp, ctypes.c_size_t, _vp, _vp]),
         "fic_decode_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Geom)]),
         "fic_decode_pifs": (_st, [_vp, _vp, ctypes.POINTER(Geom), _i32, _vp, _vp, _vp,
                                   ctypes.c_size_t, _vp, _vp]),
@@ -91,7 +98,8 @@ EXPORTED = ("fic_create", "fic_destroy", "fic_status_string", "fic_set_counters"
             "fic_num_ranges", "fic_num_domains", "fic_fd_classify", "fic_pool_workspace_bytes",
             "fic_build_domain_pool", "fic_encode_workspace_bytes", "fic_encode_pifs",
             "fic_batch_workspace_bytes", "fic_encode_pifs_batch", "fic_set_batch_graph",
-            "fic_decode_workspace_bytes", "fic_decode_pifs")
+            "fic_decode_workspace_bytes", "fic_decode_pifs", "fic_quadtree_workspace_bytes",
+            "fic_encode_quadtree", "fic_decode_quadtree")
 
 
 def status_string(status):
@@ -335,6 +343,50 @@ def decode_pifs(codes, height, width, range_size, domain_step, max_iters=32, ini
                                  int(max_iters), init.data_ptr() if init is not None else None,
                                  out.data_ptr(), scratch.data_ptr(), wsb, iters.data_ptr(),
                                  _stream()), "fic_decode_pifs")
+    return out, iters
+
+
+def encode_quadtree(img, b1, t1, tol1, b2, t2, tol2, rms, codes=None, ws=None):
+    """Two-level encode (see fic_encode_quadtree): returns (codes1, codes2)
+    as uint8 (R, 16) tensors. tol None = exhaustive at that level."""
+    import torch
+    _need_cuda_u8(img)
+    g1, g2 = _geom_of(img, b1, t1), _geom_of(img, b2, t2)
+    tl1 = float("inf") if tol1 is None else float(tol1)
+    tl2 = float("inf") if tol2 is None else float(tol2)
+    r1 = int(lib().fic_num_ranges(ctypes.byref(g1)))
+    r2 = int(lib().fic_num_ranges(ctypes.byref(g2)))
+    if codes is None:
+        codes = (torch.empty((r1, 16), dtype=torch.uint8, device=img.device),
+                 torch.empty((r2, 16), dtype=torch.uint8, device=img.device))
+    wsb = lib().fic_quadtree_workspace_bytes(ctypes.byref(g1), tl1, ctypes.byref(g2), tl2)
+    if wsb == 0:
+        raise ValueError("invalid two-level geometry")
+    buf = ws if ws is not None else _ws.get(wsb, img.device)
+    _check(lib().fic_encode_quadtree(context(img.device.index).handle, img.data_ptr(),
+                                     ctypes.byref(g1), tl1, ctypes.byref(g2), tl2, float(rms),
+                                     codes[0].data_ptr(), codes[1].data_ptr(), buf.data_ptr(),
+                                     wsb, _stream()), "fic_encode_quadtree")
+    return codes
+
+
+def decode_quadtree(codes1, codes2, height, width, b1, t1, b2, t2, max_iters=32, init=None):
+    """(image tensor, iterations tensor) decoded from a two-level code set."""
+    import torch
+    g1 = make_geom(height, width, b1, t1)
+    g2 = make_geom(height, width, b2, t2)
+    dev = codes1.device
+    out = torch.empty((height, width), dtype=torch.uint8, device=dev)
+    iters = torch.zeros(1, dtype=torch.int32, device=dev)
+    wsb = lib().fic_decode_workspace_bytes(ctypes.byref(g1))
+    scratch = torch.empty(max(wsb, 1), dtype=torch.uint8, device=dev)
+    if init is not None:
+        _need_cuda_u8(init)
+    _check(lib().fic_decode_quadtree(context(dev.index).handle, codes1.data_ptr(), ctypes.byref(g1),
+                                     codes2.data_ptr(), ctypes.byref(g2), int(max_iters),
+                                     init.data_ptr() if init is not None else None,
+                                     out.data_ptr(), scratch.data_ptr(), wsb, iters.data_ptr(),
+                                     _stream()), "fic_decode_quadtree")
     return out, iters
 
 

@@ -18,6 +18,7 @@ class Workload:
     description: str
     seed: int
     jobs: tuple = field(default_factory=tuple)   # ((B, t, tol), ...)
+    rms: float = None    # two-level workloads: split above this RMS error (gray levels)
 
 
 def _fbm_img(size, hurst, seed):
@@ -50,6 +51,12 @@ WORKLOADS = {
         "2048x2048 fBm H=0.6; 16x16 ranges / 32x32 domains step 4 and "
         "8x8 ranges / 16x16 domains step 2; FD pool tol 0.05",
         5, ((16, 4, 0.05), (8, 2, 0.05))),
+    "fbm2048_quadtree": Workload(
+        "fbm2048_quadtree",
+        "2048x2048 fBm H=0.6; two-level partition: 16x16 ranges / 32x32 domains step 4, "
+        "ranges above 1.9 gray levels RMS split into 8x8 ranges / 16x16 domains step 2; "
+        "FD pool tol 0.05 at both levels",
+        5, ((16, 4, 0.05), (8, 2, 0.05)), 1.9),
 }
 
 
@@ -63,7 +70,7 @@ def workload_images(name):
         return add_rectangles(img, 20, rng)
     if name == "fbm1024_b8t1":
         return _fbm_img(1024, 0.3, 3)
-    if name == "fbm2048_twolevel":
+    if name in ("fbm2048_twolevel", "fbm2048_quadtree"):
         return _fbm_img(2048, 0.6, 5)
     raise KeyError(name)
 

@@ -187,3 +187,38 @@ def test_workspace_sizes_grow(L):
     b = L.fic_encode_workspace_bytes(ctypes.byref(fic.make_geom(512, 512, 8, 1)), 0)
     assert 0 < a < b
     assert L.fic_encode_workspace_bytes(ctypes.byref(fic.make_geom(30, 30, 8, 1)), 0) == 0
+
+
+def test_quadtree_validation(L, hctx):
+    g1, g2 = fic.make_geom(128, 128, 16, 4), fic.make_geom(128, 128, 8, 2)
+    ws = L.fic_quadtree_workspace_bytes(ctypes.byref(g1), 0.05, ctypes.byref(g2), 0.05)
+    assert ws > (L.fic_encode_workspace_bytes(ctypes.byref(g1), 1)
+                 + L.fic_encode_workspace_bytes(ctypes.byref(g2), 1))
+
+    def E(a=g1, b=g2, rms=8.0, wsb=ws, tol1=0.05, img=1):
+        return L.fic_encode_quadtree(hctx.handle, img, ctypes.byref(a), tol1, ctypes.byref(b),
+                                     0.05, rms, 1, 1, 1, wsb, None)
+    assert E() == fic.ERR_DEVICE
+    assert E(rms=float("inf")) == fic.ERR_DEVICE
+    assert E(rms=0.0) == fic.ERR_DEVICE
+    assert E(rms=-1.0) == fic.ERR_INVALID_ARG
+    assert E(rms=float("nan")) == fic.ERR_INVALID_ARG
+    assert E(tol1=float("nan")) == fic.ERR_INVALID_ARG
+    assert E(wsb=ws - 1) == fic.ERR_WORKSPACE
+    assert E(img=None) == fic.ERR_INVALID_ARG
+    # level 2 must be the quadrants of level 1 on the same image
+    assert E(b=fic.make_geom(128, 128, 4, 2)) == fic.ERR_INVALID_ARG
+    assert E(b=fic.make_geom(128, 64, 8, 2)) == fic.ERR_INVALID_ARG
+    assert E(a=fic.make_geom(128, 128, 8, 2), b=fic.make_geom(128, 128, 4, 1),
+             wsb=1 << 40) == fic.ERR_DEVICE
+    assert L.fic_quadtree_workspace_bytes(ctypes.byref(g1), 0.05,
+                                          ctypes.byref(fic.make_geom(128, 128, 4, 2)), 0.05) == 0
+    dws = L.fic_decode_workspace_bytes(ctypes.byref(g1))
+
+    def D(it=32, wsb=dws, b=g2):
+        return L.fic_decode_quadtree(hctx.handle, 1, ctypes.byref(g1), 1, ctypes.byref(b), it,
+                                     None, 1, 1, wsb, 1, None)
+    assert D() == fic.ERR_DEVICE
+    assert D(it=-1) == fic.ERR_INVALID_ARG
+    assert D(wsb=dws - 1) == fic.ERR_WORKSPACE
+    assert D(b=fic.make_geom(128, 128, 16, 4)) == fic.ERR_INVALID_ARG

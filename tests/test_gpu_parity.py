@@ -362,3 +362,84 @@ def test_decode(fic, orc, case):
     torch.cuda.synchronize()
     ref2, r2 = orc.decode(ref_codes, n, n, b, t, max_iters=3, init=start)
     assert np.array_equal(out2.cpu().numpy(), ref2) and int(it2.item()) == r2
+
+
+# ----------------------------------------------------------- quadtree
+def _qt_compare(fic, orc, img, b1, t1, tol1, b2, t2, tol2, rms, what):
+    c1, c2 = fic.encode_quadtree(dev(img), b1, t1, tol1, b2, t2, tol2, rms)
+    torch.cuda.synchronize()
+    g1, g2 = fic.unpack_codes(c1), fic.unpack_codes(c2)
+    r1, r2 = orc.encode_quadtree(img, b1, t1, tol1, b2, t2, tol2, rms)
+    assert_codes(g1, r1, what=what + " level 1")
+    assert_codes(g2, r2, what=what + " level 2")
+    return c1, c2, r1, r2
+
+
+@pytest.mark.parametrize("case", [
+    # (image kind, size, B1, t1, tol1, B2, t2, tol2, rms)
+    ("fbm", 64, 8, 2, 0.05, 4, 2, 0.05, 15.3),
+    ("fbm", 128, 16, 4, None, 8, 2, None, 9.0),
+    ("poly", 128, 16, 2, 0.05, 8, 2, 0.1, 6.0),
+    ("fbm", 96, 8, 1, -1.0, 4, 1, None, 12.0),
+    ("noise", 64, 8, 2, None, 4, 2, 0.1, 0.0),
+    ("fbm", 64, 16, 4, 0.05, 8, 4, 0.05, float("inf")),
+])
+def test_quadtree_codes(fic, orc, case):
+    kind, n, b1, t1, tol1, b2, t2, tol2, rms = case
+    rng = np.random.default_rng(n + b1 + int(rms if np.isfinite(rms) else 99))
+    if kind == "fbm":
+        img = fbm(n, 0.6, n + 7)
+    elif kind == "poly":
+        from synth import piecewise_smooth
+        img = piecewise_smooth(n, rng)
+    else:
+        img = rng.integers(0, 256, (n, n)).astype(np.uint8)
+    _qt_compare(fic, orc, img, b1, t1, tol1, b2, t2, tol2, rms, "quadtree %s" % (case,))
+
+
+@pytest.mark.parametrize("case", [(64, 8, 2, 4, 2, 15.3), (128, 16, 4, 8, 2, 9.0)])
+def test_quadtree_decode(fic, orc, case):
+    n, b1, t1, b2, t2, rms = case
+    img = fbm(n, 0.6, n + 7)
+    c1, c2, r1, r2 = _qt_compare(fic, orc, img, b1, t1, 0.05, b2, t2, 0.05, rms,
+                                 "quadtree decode %s" % (case,))
+    split = (fic.unpack_codes(c1)["flags"] & 2) != 0
+    assert 0 < split.sum() < split.size
+    out, iters = fic.decode_quadtree(c1, c2, n, n, b1, t1, b2, t2, max_iters=32)
+    torch.cuda.synchronize()
+    ref, it = orc.decode_quadtree(r1, r2, n, n, b1, t1, b2, t2, max_iters=32)
+    assert np.array_equal(out.cpu().numpy(), ref) and int(iters.item()) == it
+    start = np.random.default_rng(3).integers(0, 256, (n, n)).astype(np.uint8)
+    out2, it2 = fic.decode_quadtree(c1, c2, n, n, b1, t1, b2, t2, max_iters=2, init=dev(start))
+    torch.cuda.synchronize()
+    ref2, r2i = orc.decode_quadtree(r1, r2, n, n, b1, t1, b2, t2, max_iters=2, init=start)
+    assert np.array_equal(out2.cpu().numpy(), ref2) and int(it2.item()) == r2i
+
+
+def test_quadtree_workload_2048(fic, orc):
+    """2048x2048 fBm, 16x16 ranges (step 4) over 8x8 ranges (step 2), FD pools
+    0.05, split above 1.9 gray levels RMS (about a quarter of the ranges):
+    split decisions on every range from the GPU's own exact E, and sampled
+    codes of both levels against the oracle."""
+    from synth import WORKLOADS, workload_images
+    wl = WORKLOADS["fbm2048_quadtree"]
+    img = workload_images("fbm2048_quadtree")
+    c1, c2 = fic.encode_quadtree(dev(img), 16, 4, 0.05, 8, 2, 0.05, wl.rms)
+    torch.cuda.synchronize()
+    g1, g2 = fic.unpack_codes(c1), fic.unpack_codes(c2)
+    emax = orc.split_threshold(16, wl.rms)
+    split = (g1["flags"] & 2) != 0
+    assert np.array_equal(split, g1["err"] > emax)
+    assert 0 < split.sum() < split.size
+    rc1, rc2 = 2048 // 16, 2048 // 8
+    r2 = np.arange(g2.size)
+    coded = (g2["flags"] & 4) == 0
+    assert np.array_equal(coded, split[(r2 // rc2 // 2) * rc1 + (r2 % rc2) // 2])
+    sel1 = sampled(g1.size, 24, seed=5)
+    ref1 = orc.encode(img, 16, 4, tol=0.05, sel=sel1)
+    ref1["flags"] = ref1["flags"] | np.where(ref1["err"] > emax, 2, 0)
+    assert_codes(g1, ref1, sel=sel1, what="2048 quadtree level 1")
+    kids = np.flatnonzero(coded)
+    sel2 = np.sort(np.random.default_rng(6).choice(kids, size=24, replace=False))
+    ref2 = orc.encode(img, 8, 2, tol=0.05, sel=sel2)
+    assert_codes(g2, ref2, sel=sel2, what="2048 quadtree level 2")
