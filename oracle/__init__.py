@@ -253,6 +253,67 @@ def decode_quadtree(c1, c2, h, w, b1, t1, b2, t2, max_iters=32, init=None, nthre
     return out, int(it.value)
 
 
+def decode_scaled(codes, h, w, b, t, scale, max_iters=32, init=None, nthreads=0):
+    """Decode at scale times the encoded size (resolution independence): the
+    same maps on the lattice scaled by `scale` (ranges scale*b, domain step
+    scale*t, the same domain indices), i.e. decode() with that geometry."""
+    return decode(codes, h * scale, w * scale, b * scale, t * scale, max_iters, init, nthreads)
+
+
+def code_bits(num_domains):
+    """Bits of one packed code: the domain index (ceil(log2 D) bits, at least
+    1), the isometry (3), the contrast index k + 16 (5) and the brightness
+    index j (7) -- the fields Sec. 1 stores per range."""
+    dbits = max(1, int(num_domains - 1).bit_length())
+    return dbits, dbits + 15
+
+
+def pack_codes(codes, num_domains):
+    """The codes of all ranges, in raster order, as one little-endian bit
+    string in uint32 words: range r's fields start at bit r*W, each field
+    least significant bit first, in the order domain, isometry, k + 16, j."""
+    dbits, W = code_bits(num_domains)
+    dom, iso = np.asarray(codes["dom"]), np.asarray(codes["iso"])
+    kk, jj = np.asarray(codes["k"]), np.asarray(codes["j"])
+    R = dom.size
+    nwords = (R * W + 31) // 32
+    words = [0] * nwords
+    for r in range(R):
+        fields = [(int(dom[r]), dbits), (int(iso[r]), 3), (int(kk[r]) + 16, 5), (int(jj[r]), 7)]
+        pos = r * W
+        for value, width in fields:
+            for bit in range(width):
+                if (value >> bit) & 1:
+                    words[(pos + bit) // 32] |= 1 << ((pos + bit) % 32)
+            pos += width
+    return np.array(words, dtype=np.uint32)
+
+
+def unpack_codes(words, num_ranges, num_domains):
+    """Inverse of pack_codes: dom, iso, k, j per range."""
+    dbits, W = code_bits(num_domains)
+    words = [int(x) for x in np.asarray(words, dtype=np.uint32)]
+    out = {k: np.zeros(num_ranges, dtype=np.int32) for k in ("dom", "iso", "k", "j")}
+    for r in range(num_ranges):
+        pos = r * W
+        vals = []
+        for width in (dbits, 3, 5, 7):
+            v = 0
+            for bit in range(width):
+                if (words[(pos + bit) // 32] >> ((pos + bit) % 32)) & 1:
+                    v |= 1 << bit
+            vals.append(v)
+            pos += width
+        out["dom"][r], out["iso"][r], out["k"][r], out["j"][r] = vals[0], vals[1], vals[2] - 16, vals[3]
+    return out
+
+
+def compression_ratio(h, w, num_ranges, num_domains):
+    """8-bit pixels against the packed codes (words rounded up)."""
+    _, W = code_bits(num_domains)
+    return (8.0 * h * w) / (32 * ((num_ranges * W + 31) // 32))
+
+
 def psnr(a, b):
     """Peak signal-to-noise ratio for 8-bit images, fp64 (inf when equal)."""
     d = a.astype(np.float64) - b.astype(np.float64)

@@ -432,3 +432,66 @@ def test_quadtree_sweep_is_the_union_of_level_sweeps(oracle_lib):
     from_l2 = np.kron(split, np.ones((8, 8), dtype=bool))
     expect = np.where(from_l2, s2, s1)
     assert np.array_equal(q, expect)
+
+
+# ----------------------------------------------------------- code bitstream
+def test_pack_codes_hand_example():
+    """Two ranges on a lattice of 5 domains (3 domain bits, 18 bits a code).
+    Range 0: domain 5, isometry 3, k = -16, j = 127; range 1: domain 2,
+    isometry 6, k = 15, j = 1. Worked by hand (fields least significant bit
+    first): range 0 sets bits 0, 2 (domain), 3, 4 (isometry), none for
+    k + 16 = 0, 11..17 (j); range 1 starts at bit 18 and sets bit 19
+    (domain), 22, 23 (isometry), 24..28 (k + 16 = 31), 29 (j): word 0 =
+    0x1D + 0x3F800 + 0x80000 + 0xC00000 + 0x1F000000 + 0x20000000 =
+    0x3FCBF81D, word 1 = 0 (bits 32..35 hold j's zero high bits)."""
+    import oracle
+    codes = {"dom": [5, 2], "iso": [3, 6], "k": [-16, 15], "j": [127, 1]}
+    words = oracle.pack_codes(codes, 5)
+    assert words.dtype == np.uint32 and words.size == 2
+    assert int(words[0]) == 0x3FCBF81D and int(words[1]) == 0
+
+
+def test_pack_roundtrip_and_ratio():
+    import oracle
+    rng = np.random.default_rng(31)
+    for D in (1, 2, 3, 1000, 1018081):
+        R = 333
+        codes = {"dom": rng.integers(0, D, R), "iso": rng.integers(0, 8, R),
+                 "k": rng.integers(-16, 16, R), "j": rng.integers(0, 128, R)}
+        back = oracle.unpack_codes(oracle.pack_codes(codes, D), R, D)
+        for k in codes:
+            assert np.array_equal(back[k], codes[k]), (D, k)
+    # 1024x1024, 8x8 ranges, 1,018,081 domains: 20 + 15 = 35 bits a range
+    assert oracle.code_bits(1018081) == (20, 35)
+    assert abs(oracle.compression_ratio(1024, 1024, 16384, 1018081) - 8 * 1024 * 1024 / (16384 * 35)) < 1e-3
+
+
+# ----------------------------------------------------------- decoding at 2x
+def test_decode_scaled_dc_codes_are_pixel_doubled():
+    """Codes with k = 0 are constant maps (value 2j): at twice the size each
+    range is the same constant on a block twice as wide."""
+    import oracle
+    rng = np.random.default_rng(51)
+    h = w = 64
+    for b, t in ((4, 2), (8, 1), (16, 4)):
+        R, D = oracle.num_ranges(h, w, b), oracle.num_domains(h, w, b, t)
+        codes = {"dom": rng.integers(0, D, R), "iso": rng.integers(0, 8, R),
+                 "k": np.zeros(R, dtype=np.int64), "j": rng.integers(0, 128, R)}
+        o1, _ = oracle.decode(codes, h, w, b, t, max_iters=3)
+        o2, _ = oracle.decode_scaled(codes, h, w, b, t, 2, max_iters=3)
+        assert np.array_equal(o2, np.kron(o1, np.ones((2, 2), dtype=np.uint8)))
+
+
+@pytest.mark.parametrize("b,t,n", [(4, 2, 64), (8, 2, 64), (16, 4, 128)])
+def test_decode_scaled_attractor_matches(b, t, n):
+    """Resolution independence: the attractor decoded at twice the size,
+    averaged over 2x2 pixels, is the attractor at the encoded size up to
+    rounding (within 45 dB)."""
+    import oracle
+    from synth import fbm
+    img = fbm(n, n, 0.6, np.random.default_rng(40 + b))
+    c = oracle.encode(img, b, t, tol=0.1)
+    o1, _ = oracle.decode(c, n, n, b, t)
+    o2, _ = oracle.decode_scaled(c, n, n, b, t, 2)
+    down = np.round(o2.reshape(n, 2, n, 2).astype(np.float64).mean(axis=(1, 3))).astype(np.uint8)
+    assert oracle.psnr(down, o1) > 45.0
