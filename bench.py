@@ -300,6 +300,12 @@ def bench_image(args, fic, wl, img_np):
         "stage_ms_per_step": {k: round(v, 4) for k, v in stage_ms.items()},
         "roofline": roofline,
         "hbm_stages": hbm,
+        "bitstream": {"%dx%d_b%dt%d" % (H, W, b, t): {
+            "bits_per_range": int(fic.fic.lib().fic_packed_words(
+                fic.fic.make_geom(H, W, b, t)) * 32 // R[b]),
+            "packed_bytes": int(fic.fic.lib().fic_packed_words(fic.fic.make_geom(H, W, b, t))) * 4,
+            "compression_ratio": round(8.0 * H * W / (32 * int(fic.fic.lib().fic_packed_words(
+                fic.fic.make_geom(H, W, b, t)))), 3)} for (b, t) in sorted(set((b, t) for (b, t, _) in jobs))},
     }
 
     if args.counters:

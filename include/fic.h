@@ -227,6 +227,26 @@ fic_status fic_encode_pifs_batch(fic_ctx *ctx, int32_t n_images,
 fic_status fic_set_batch_graph(fic_ctx *ctx, int32_t enable);
 
 /* ------------------------------------------------------------------------
+ * fic_pack_codes / fic_unpack_codes -- the stored code as a bit string
+ * (Sec. 1: per range the domain, the isometry, the contrast and the
+ * brightness). Range r's fields start at bit r*W of a little-endian string
+ * of 32-bit words, each field least significant bit first, in the order
+ * domain index (ceil(log2 D) bits, at least 1), isometry (3), k + 16 (5),
+ * j (7); W is their sum (35 bits at 1024^2, 8x8 ranges, step 1). Flags and
+ * errors are not stored: unpacked codes have flags 0 and err 0.
+ *   words (dev) uint32[nwords], nwords >= fic_packed_words(g); pack clears
+ *         the words it uses and FIC_ERR_WORKSPACE when nwords is short;
+ *         unpack answers FIC_ERR_INVALID_ARG then.
+ *   codes (dev) fic_code[fic_num_ranges(g)].
+ * Compression ratio of an image = 8*h*w / (32*fic_packed_words(g)).
+ * ---------------------------------------------------------------------- */
+int64_t fic_packed_words(const fic_geom *g);
+fic_status fic_pack_codes(fic_ctx *ctx, const fic_code *codes, const fic_geom *g,
+                          uint32_t *words, int64_t nwords, void *stream);
+fic_status fic_unpack_codes(fic_ctx *ctx, const uint32_t *words, int64_t nwords,
+                            const fic_geom *g, fic_code *codes, void *stream);
+
+/* ------------------------------------------------------------------------
  * fic_decode_pifs -- Sec. 1, decoding by iteration of the stored maps.
  * Simultaneous sweeps from `init` (dev, h x w, pitch w; NULL = all 128):
  *   pixel = clamp(floor((k*(n*(T_q D')_i - sum D') + 128*n*j + 32*n) / (64n)),
@@ -235,6 +255,10 @@ fic_status fic_set_batch_graph(fic_ctx *ctx, int32_t enable);
  * the first sweep that changes no pixel, or after max_iters sweeps.
  *   codes (dev) fic_code[fic_num_ranges(g)]; out (dev) uint8 h x w (pitch w)
  *   scratch (dev) >= fic_decode_workspace_bytes(g)
+ * Decoding at a larger size (the maps do not depend on the pixel grid): the
+ * codes of geometry (h, w, B, t) decode at twice the size with geometry
+ * (2h, 2w, 2B, 2t) -- the same domain indices; g->range_size may therefore
+ * also be 32 here (16x16 codes at twice the size).
  *   iters_done (dev) int32: sweeps run.
  * ---------------------------------------------------------------------- */
 size_t fic_decode_workspace_bytes(const fic_geom *g);

@@ -90,6 +90,19 @@ bool geom_ok(const fic_geom *g)
     return true;
 }
 
+// Decoding also takes 32x32 ranges: 16x16 codes applied at twice the size.
+bool decode_geom_ok(const fic_geom *g)
+{
+    if (!g) return false;
+    if (g->range_size == 32) {
+        fic_geom h = *g;
+        h.range_size = 16;
+        if (h.height % 32 || h.width % 32 || h.height < 64 || h.width < 64) return false;
+        return geom_ok(&h);
+    }
+    return geom_ok(g);
+}
+
 Geom to_geom(const fic_geom *g)
 {
     Geom r;
@@ -530,9 +543,36 @@ fic_status fic_decode_quadtree(fic_ctx *ctx, const fic_code *codes1, const fic_g
                                                tracer_of(ctx)));
 }
 
+int64_t fic_packed_words(const fic_geom *g)
+{
+    return geom_ok(g) ? fic::packed_words(to_geom(g)) : 0;
+}
+
+fic_status fic_pack_codes(fic_ctx *ctx, const fic_code *codes, const fic_geom *g, uint32_t *words,
+                          int64_t nwords, void *stream)
+{
+    if (!ctx || !codes || !words || !geom_ok(g)) return FIC_ERR_INVALID_ARG;
+    const Geom gg = to_geom(g);
+    if (nwords < fic::packed_words(gg)) return FIC_ERR_WORKSPACE;
+    fic_status st = enter(ctx);
+    if (st != FIC_OK) return st;
+    return dev_status(fic::run_pack(gg, codes, words, (hipStream_t)stream));
+}
+
+fic_status fic_unpack_codes(fic_ctx *ctx, const uint32_t *words, int64_t nwords, const fic_geom *g,
+                            fic_code *codes, void *stream)
+{
+    if (!ctx || !codes || !words || !geom_ok(g)) return FIC_ERR_INVALID_ARG;
+    const Geom gg = to_geom(g);
+    if (nwords < fic::packed_words(gg)) return FIC_ERR_INVALID_ARG;
+    fic_status st = enter(ctx);
+    if (st != FIC_OK) return st;
+    return dev_status(fic::run_unpack(gg, words, codes, (hipStream_t)stream));
+}
+
 size_t fic_decode_workspace_bytes(const fic_geom *g)
 {
-    if (!geom_ok(g)) return 0;
+    if (!decode_geom_ok(g)) return 0;
     return fic::decode_ws_bytes(to_geom(g));
 }
 
@@ -540,7 +580,8 @@ fic_status fic_decode_pifs(fic_ctx *ctx, const fic_code *codes, const fic_geom *
                            int32_t max_iters, const uint8_t *init, uint8_t *out, void *scratch,
                            size_t scratch_bytes, int32_t *iters_done, void *stream)
 {
-    if (!ctx || !codes || !out || !scratch || !iters_done || !geom_ok(g)) return FIC_ERR_INVALID_ARG;
+    if (!ctx || !codes || !out || !scratch || !iters_done || !decode_geom_ok(g))
+        return FIC_ERR_INVALID_ARG;
     if (max_iters < 0 || max_iters > fic::decode_max_iters()) return FIC_ERR_INVALID_ARG;
     const Geom gg = to_geom(g);
     if (scratch_bytes < fic::decode_ws_bytes(gg)) return FIC_ERR_WORKSPACE;

@@ -30,15 +30,19 @@ __global__ void k_decode_init(const uint8_t *__restrict__ init, int64_t np, uint
 
 // Codes whose flags meet skip_flags write nothing (in a two-level decode
 // their pixels belong to the other level).
+// 256 threads a block (one per pixel of 256/n ranges); 1024 for 32x32 ranges
+// (16x16 codes decoded at twice the size).
+template <int B> constexpr int sweep_threads() { return B == 32 ? 1024 : 256; }
+
 template <int B>
-__global__ __launch_bounds__(256) void k_decode_sweep(const fic_code *__restrict__ codes, Geom g,
+__global__ __launch_bounds__(sweep_threads<B>()) void k_decode_sweep(const fic_code *__restrict__ codes, Geom g,
                                                       uint8_t skip_flags,
                                                       const uint8_t *__restrict__ cur,
                                                       uint8_t *__restrict__ nxt,
                                                       uint32_t *__restrict__ changed,
                                                       const uint32_t *__restrict__ done)
 {
-    constexpr int n = B * B, RPB = 256 / n;   // ranges per block
+    constexpr int n = B * B, RPB = sweep_threads<B>() / n;   // ranges per block
     __shared__ int32_t sums[RPB];
     __shared__ uint32_t nchg;
     if (*done) return;
@@ -112,13 +116,13 @@ hipError_t run_b(const Geom &g, const fic_code *codes, int32_t max_iters, const 
     const int64_t nthr = np > nfl ? np : nfl;
     hipLaunchKernelGGL(k_decode_init, dim3((unsigned)((nthr + th - 1) / th)), dim3(th), 0, s, init,
                        np, b0, flags, (int32_t)nfl, iters);
-    constexpr int RPB = 256 / (B * B);
+    constexpr int RPB = sweep_threads<B>() / (B * B);
     const unsigned nb = (unsigned)((g.R + RPB - 1) / RPB);
     for (int it = 0; it < max_iters; ++it) {
         const uint8_t *src = (it & 1) ? b1 : b0;
         uint8_t *dst = (it & 1) ? b0 : b1;
-        hipLaunchKernelGGL(k_decode_sweep<B>, dim3(nb), dim3(256), 0, s, codes, g, (uint8_t)0,
-                           src, dst, flags + it, done);
+        hipLaunchKernelGGL(k_decode_sweep<B>, dim3(nb), dim3(sweep_threads<B>()), 0, s, codes, g,
+                           (uint8_t)0, src, dst, flags + it, done);
         hipLaunchKernelGGL(k_decode_check, dim3(1), dim3(64), 0, s, it, flags, done, iters);
     }
     hipLaunchKernelGGL(k_decode_out, dim3((unsigned)((np + th - 1) / th)), dim3(th), 0, s, b0, b1,
@@ -131,10 +135,10 @@ template <int B>
 void sweep_b(const Geom &g, const fic_code *codes, uint8_t skip, const uint8_t *src, uint8_t *dst,
              uint32_t *changed, const uint32_t *done, hipStream_t s)
 {
-    constexpr int RPB = 256 / (B * B);
+    constexpr int RPB = sweep_threads<B>() / (B * B);
     const unsigned nb = (unsigned)((g.R + RPB - 1) / RPB);
-    hipLaunchKernelGGL(k_decode_sweep<B>, dim3(nb), dim3(256), 0, s, codes, g, skip, src, dst,
-                       changed, done);
+    hipLaunchKernelGGL(k_decode_sweep<B>, dim3(nb), dim3(sweep_threads<B>()), 0, s, codes, g, skip,
+                       src, dst, changed, done);
 }
 
 void sweep(const Geom &g, const fic_code *codes, uint8_t skip, const uint8_t *src, uint8_t *dst,
@@ -198,6 +202,7 @@ hipError_t run_decode(const Geom &g, const fic_code *codes, int32_t max_iters,
     case 4: return run_b<4>(g, codes, max_iters, init, out, ws, iters, s, tr);
     case 8: return run_b<8>(g, codes, max_iters, init, out, ws, iters, s, tr);
     case 16: return run_b<16>(g, codes, max_iters, init, out, ws, iters, s, tr);
+    case 32: return run_b<32>(g, codes, max_iters, init, out, ws, iters, s, tr);
     default: return hipErrorInvalidValue;
     }
 }

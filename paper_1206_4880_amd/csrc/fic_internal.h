@@ -268,6 +268,12 @@ hipError_t run_encode_batch(const BatchJob *jobs, const BatchPlan &bp, void *ws,
                             u64 *counters, hipStream_t s, const Tracer *tr = nullptr,
                             const BatchStreams *bs = nullptr);
 
+// packed code bit string (bitstream.hip)
+int code_dbits(int64_t D);
+int64_t packed_words(const Geom &g);
+hipError_t run_pack(const Geom &g, const fic_code *codes, uint32_t *words, hipStream_t s);
+hipError_t run_unpack(const Geom &g, const uint32_t *words, fic_code *codes, hipStream_t s);
+
 // decode (decode.hip)
 size_t decode_ws_bytes(const Geom &g);
 int32_t decode_max_iters();

@@ -81,6 +81,9 @@ def lib():
                                       _vp, _vp, _vp, ctypes.c_size_t, _vp]),
         "fic_decode_quadtree": (_st, [_vp, _vp, ctypes.POINTER(Geom), _vp, ctypes.POINTER(Geom),
                                       _i32, _vp, _vp, _vp, ctypes.c_size_t, _vp, _vp]),
+        "fic_packed_words": (ctypes.c_int64, [ctypes.POINTER(Geom)]),
+        "fic_pack_codes": (_st, [_vp, _vp, ctypes.POINTER(Geom), _vp, ctypes.c_int64, _vp]),
+        "fic_unpack_codes": (_st, [_vp, _vp, ctypes.c_int64, ctypes.POINTER(Geom), _vp, _vp]),
         "fic_decode_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Geom)]),
         "fic_decode_pifs": (_st, [_vp, _vp, ctypes.POINTER(Geom), _i32, _vp, _vp, _vp,
                                   ctypes.c_size_t, _vp, _vp]),
@@ -99,7 +102,8 @@ EXPORTED = ("fic_create", "fic_destroy", "fic_status_string", "fic_set_counters"
             "fic_build_domain_pool", "fic_encode_workspace_bytes", "fic_encode_pifs",
             "fic_batch_workspace_bytes", "fic_encode_pifs_batch", "fic_set_batch_graph",
             "fic_decode_workspace_bytes", "fic_decode_pifs", "fic_quadtree_workspace_bytes",
-            "fic_encode_quadtree", "fic_decode_quadtree")
+            "fic_encode_quadtree", "fic_decode_quadtree", "fic_packed_words", "fic_pack_codes",
+            "fic_unpack_codes")
 
 
 def status_string(status):
@@ -328,10 +332,14 @@ def batch_workspace_bytes(images, jobs):
     return int(lib().fic_batch_workspace_bytes(n, descs))
 
 
-def decode_pifs(codes, height, width, range_size, domain_step, max_iters=32, init=None):
-    """(image tensor, iterations tensor) decoded from codes on the device."""
+def decode_pifs(codes, height, width, range_size, domain_step, max_iters=32, init=None, scale=1):
+    """(image tensor, iterations tensor) decoded from codes on the device.
+    scale=2 decodes the same codes at twice the encoded height and width."""
     import torch
-    g = make_geom(height, width, range_size, domain_step)
+    if scale not in (1, 2):
+        raise ValueError("scale is 1 or 2")
+    height, width = height * scale, width * scale
+    g = make_geom(height, width, range_size * scale, domain_step * scale)
     dev = codes.device
     out = torch.empty((height, width), dtype=torch.uint8, device=dev)
     iters = torch.zeros(1, dtype=torch.int32, device=dev)
@@ -388,6 +396,30 @@ def decode_quadtree(codes1, codes2, height, width, b1, t1, b2, t2, max_iters=32,
                                      out.data_ptr(), scratch.data_ptr(), wsb, iters.data_ptr(),
                                      _stream()), "fic_decode_quadtree")
     return out, iters
+
+
+def pack_codes(codes, height, width, range_size, domain_step):
+    """The packed bit string (uint32 CUDA tensor) of a codes tensor."""
+    import torch
+    g = make_geom(height, width, range_size, domain_step)
+    nw = int(lib().fic_packed_words(ctypes.byref(g)))
+    words = torch.empty(max(nw, 1), dtype=torch.int32, device=codes.device)
+    _check(lib().fic_pack_codes(context(codes.device.index).handle, codes.data_ptr(),
+                                ctypes.byref(g), words.data_ptr(), nw, _stream()),
+           "fic_pack_codes")
+    return words[:nw]
+
+
+def unpack_bitstream(words, height, width, range_size, domain_step):
+    """Codes tensor (flags and errors 0) from a packed bit string."""
+    import torch
+    g = make_geom(height, width, range_size, domain_step)
+    nr = int(lib().fic_num_ranges(ctypes.byref(g)))
+    codes = torch.empty((nr, 16), dtype=torch.uint8, device=words.device)
+    _check(lib().fic_unpack_codes(context(words.device.index).handle, words.data_ptr(),
+                                  words.numel(), ctypes.byref(g), codes.data_ptr(), _stream()),
+           "fic_unpack_codes")
+    return codes
 
 
 def unpack_codes(codes):

@@ -222,3 +222,29 @@ def test_quadtree_validation(L, hctx):
     assert D(it=-1) == fic.ERR_INVALID_ARG
     assert D(wsb=dws - 1) == fic.ERR_WORKSPACE
     assert D(b=fic.make_geom(128, 128, 16, 4)) == fic.ERR_INVALID_ARG
+
+
+def test_pack_validation_and_sizes(L, hctx, oracle_lib):
+    import oracle
+    g = fic.make_geom(1024, 1024, 8, 1)
+    nw = L.fic_packed_words(ctypes.byref(g))
+    R, D = oracle.num_ranges(1024, 1024, 8), oracle.num_domains(1024, 1024, 8, 1)
+    assert nw == (R * oracle.code_bits(D)[1] + 31) // 32 == (16384 * 35 + 31) // 32
+    assert L.fic_pack_codes(hctx.handle, 1, ctypes.byref(g), 1, nw, None) == fic.ERR_DEVICE
+    assert L.fic_pack_codes(hctx.handle, 1, ctypes.byref(g), 1, nw - 1, None) == fic.ERR_WORKSPACE
+    assert L.fic_pack_codes(hctx.handle, None, ctypes.byref(g), 1, nw, None) == fic.ERR_INVALID_ARG
+    assert L.fic_unpack_codes(hctx.handle, 1, nw, ctypes.byref(g), 1, None) == fic.ERR_DEVICE
+    assert L.fic_unpack_codes(hctx.handle, 1, nw - 1, ctypes.byref(g), 1, None) == fic.ERR_INVALID_ARG
+    assert L.fic_packed_words(ctypes.byref(fic.make_geom(30, 30, 8, 1))) == 0
+
+
+def test_decode_accepts_twice_size_geometry(L, hctx):
+    """16x16 codes decode at twice the size with 32x32 ranges; the encoder
+    does not take 32x32 ranges."""
+    g32 = fic.make_geom(256, 256, 32, 8)
+    ws = L.fic_decode_workspace_bytes(ctypes.byref(g32))
+    assert ws > 0
+    assert L.fic_decode_pifs(hctx.handle, 1, ctypes.byref(g32), 8, None, 1, 1, ws, 1,
+                             None) == fic.ERR_DEVICE
+    assert L.fic_encode_workspace_bytes(ctypes.byref(g32), 0) == 0
+    assert L.fic_decode_workspace_bytes(ctypes.byref(fic.make_geom(32, 32, 32, 8))) == 0

@@ -443,3 +443,44 @@ def test_quadtree_workload_2048(fic, orc):
     sel2 = np.sort(np.random.default_rng(6).choice(kids, size=24, replace=False))
     ref2 = orc.encode(img, 8, 2, tol=0.05, sel=sel2)
     assert_codes(g2, ref2, sel=sel2, what="2048 quadtree level 2")
+
+
+# ----------------------------------------------------------- bitstream, 2x decode
+@pytest.mark.parametrize("case", [("fbm1024_b8t1", 8, 1, None), ("fbm512rect_b8t2", 8, 2, 0.05),
+                                  ("small", 4, 2, 0.1), ("small16", 16, 4, None)])
+def test_pack_codes_bit_exact(fic, orc, case):
+    name, b, t, tol = case
+    if name == "small":
+        img = fbm(128, 0.5, 61)
+    elif name == "small16":
+        img = fbm(128, 0.7, 62)
+    else:
+        from synth import workload_images
+        img = workload_images(name)
+    H, W = img.shape
+    x = dev(img)
+    codes, _ = fic.encode(x, b, t, tol=tol)
+    words = fic.fic.pack_codes(codes, H, W, b, t)
+    torch.cuda.synchronize()
+    got = fic.unpack_codes(codes)
+    ref_codes = {"dom": got["domain"], "iso": got["iso"], "k": got["s_idx"], "j": got["o_idx"]}
+    D = orc.num_domains(H, W, b, t)
+    ref_words = orc.pack_codes(ref_codes, D)
+    assert np.array_equal(words.cpu().numpy().view(np.uint32), ref_words)
+    back = fic.unpack_codes(fic.fic.unpack_bitstream(words, H, W, b, t))
+    for f in ("domain", "iso", "s_idx", "o_idx"):
+        assert np.array_equal(back[f], got[f]), f
+    assert np.all(back["flags"] == 0) and np.all(back["err"] == 0)
+
+
+@pytest.mark.parametrize("b,t,n", [(4, 2, 64), (8, 2, 128), (16, 4, 128)])
+def test_decode_twice_size(fic, orc, b, t, n):
+    img = fbm(n, 0.6, 40 + b)
+    codes, _ = fic.encode(dev(img), b, t, tol=0.1)
+    out, iters = fic.decode_pifs(codes, n, n, b, t, max_iters=32, scale=2)
+    torch.cuda.synchronize()
+    got = fic.unpack_codes(codes)
+    ref_codes = {"dom": got["domain"], "iso": got["iso"], "k": got["s_idx"], "j": got["o_idx"]}
+    ref, it = orc.decode_scaled(ref_codes, n, n, b, t, 2, max_iters=32)
+    assert out.shape == (2 * n, 2 * n)
+    assert np.array_equal(out.cpu().numpy(), ref) and int(iters.item()) == it
