@@ -260,6 +260,31 @@ def decode_scaled(codes, h, w, b, t, scale, max_iters=32, init=None, nthreads=0)
     return decode(codes, h * scale, w * scale, b * scale, t * scale, max_iters, init, nthreads)
 
 
+def color_planes(rgb, fd_source):
+    """The three channel planes of an interleaved h x w x 3 uint8 image and
+    the image the fractal dimensions are taken from: fd_source 0 = luma
+    (299 R + 587 G + 114 B + 500) div 1000, 1 = channel mean
+    (R + G + B + 1) div 3 (integers, so every conversion is exact)."""
+    a = np.asarray(rgb, dtype=np.int64)
+    planes = [np.ascontiguousarray(a[:, :, c].astype(np.uint8)) for c in range(3)]
+    if fd_source == 0:
+        fdimg = (299 * a[:, :, 0] + 587 * a[:, :, 1] + 114 * a[:, :, 2] + 500) // 1000
+    elif fd_source == 1:
+        fdimg = (a[:, :, 0] + a[:, :, 1] + a[:, :, 2] + 1) // 3
+    else:
+        raise ValueError("fd_source is 0 (luma) or 1 (mean)")
+    return planes, np.ascontiguousarray(fdimg.astype(np.uint8))
+
+
+def encode_color(rgb, b, t, tol, fd_source=0, nthreads=0):
+    """Per-channel encode (Sec. 3.1 discusses colour images): the pools come
+    from the dimensions of the luma (or mean) image, and each channel is
+    searched over them (tol None = exhaustive). Returns three code dicts."""
+    planes, fdimg = color_planes(rgb, fd_source)
+    fds = classify(fdimg, b, t, nthreads) if tol is not None else None
+    return [encode(p, b, t, tol=tol, fds=fds, nthreads=nthreads) for p in planes]
+
+
 def code_bits(num_domains):
     """Bits of one packed code: the domain index (ceil(log2 D) bits, at least
     1), the isometry (3), the contrast index k + 16 (5) and the brightness

@@ -495,3 +495,38 @@ def test_decode_scaled_attractor_matches(b, t, n):
     o2, _ = oracle.decode_scaled(c, n, n, b, t, 2)
     down = np.round(o2.reshape(n, 2, n, 2).astype(np.float64).mean(axis=(1, 3))).astype(np.uint8)
     assert oracle.psnr(down, o1) > 45.0
+
+
+# ----------------------------------------------------------- colour
+@pytest.mark.parametrize("fd_source", [0, 1])
+def test_color_of_gray_is_the_gray_encode(oracle_lib, fd_source):
+    """A gray image in all three channels: both conversions give the gray
+    value back ((299 + 587 + 114) v + 500) div 1000 = (3v + 1) div 3 = v), so
+    every channel's codes are the gray encode's."""
+    import oracle
+    from synth import fbm
+    g = fbm(64, 64, 0.5, np.random.default_rng(71))
+    rgb = np.stack([g, g, g], axis=2)
+    planes, fdimg = oracle.color_planes(rgb, fd_source)
+    assert np.array_equal(fdimg, g)
+    ref = oracle.encode(g, 8, 2, tol=0.1)
+    for c in oracle.encode_color(rgb, 8, 2, 0.1, fd_source):
+        for k in ("dom", "iso", "k", "j", "flags", "err"):
+            assert np.array_equal(c[k], ref[k]), k
+
+
+def test_color_mean_is_channel_symmetric(oracle_lib):
+    """With the channel mean as the dimension image, permuting the channels
+    permutes the codes."""
+    import oracle
+    from synth import fbm
+    rng = np.random.default_rng(72)
+    rgb = np.stack([fbm(64, 64, h, rng) for h in (0.3, 0.5, 0.8)], axis=2)
+    a = oracle.encode_color(rgb, 8, 2, 0.05, fd_source=1)
+    b = oracle.encode_color(rgb[:, :, [2, 0, 1]], 8, 2, 0.05, fd_source=1)
+    for src, dst in ((2, 0), (0, 1), (1, 2)):
+        for k in ("dom", "iso", "k", "j", "flags", "err"):
+            assert np.array_equal(a[src][k], b[dst][k]), (src, k)
+    # the luma weights are not symmetric: at least one pool differs
+    c = oracle.encode_color(rgb, 8, 2, 0.05, fd_source=0)
+    assert any(not np.array_equal(c[i]["pool"], a[i]["pool"]) for i in range(3))
