@@ -103,6 +103,8 @@ def main():
         out = bench_batch(args, fic, wl)
     elif wl.rms is not None:
         out = bench_quadtree(args, fic, wl, workload_images(args.workload))
+    elif wl.color:
+        out = bench_color(args, fic, wl, workload_images(args.workload))
     else:
         out = bench_image(args, fic, wl, workload_images(args.workload))
     print(json.dumps(out))
@@ -419,6 +421,54 @@ def bench_quadtree(args, fic, wl, img_np):
         out["cpu_baseline"] = oracle_rate(img_np, b1, t1, tol1, sizes[0], None, args.cpu_seconds,
                                           "%s, level 1 (b%dt%d pool %g)" % (wl.name, b1, t1, tol1))
     return out
+
+
+def bench_color(args, fic, wl, rgb_np):
+    """One step = one colour encode (fic_encode_color): channel planes and the
+    luma image, its classification and pool, the three channel searches."""
+    import numpy as np
+    import torch
+
+    dev = torch.device("cuda:0")
+    rgb = torch.from_numpy(rgb_np).to(dev)
+    H, W = rgb_np.shape[:2]
+    (b, t, tol), = wl.jobs
+    ctx = fic.fic.context(0)
+    a = rgb_np.astype(np.int64)
+    luma = ((299 * a[:, :, 0] + 587 * a[:, :, 1] + 114 * a[:, :, 2] + 500) // 1000).astype(np.uint8)
+    lx = torch.from_numpy(luma).to(dev)
+    fr, _ = fic.fd_classify(lx, b, b, want_fp32=False)
+    fd, _ = fic.fd_classify(lx, 2 * b, t, want_fp32=False)
+    _, lo, hi = fic.build_domain_pool(fr, fd, tol)
+    pairs_step = 3 * int((hi.long() - lo.long()).sum().item()) * 8
+    progress("%s: %d pair evaluations per step" % (wl.name, pairs_step))
+    for _ in range(args.warmup):
+        fic.encode_color(rgb, b, t, tol=tol)
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        fic.encode_color(rgb, b, t, tol=tol)
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t_start) * 1e3 / args.steps
+    recs = ctx.timing_read()
+    ctx.timing(False)
+    progress("timed %d steps: %.3f ms per step" % (args.steps, ms_step))
+    searches = [ms for (name, ms) in recs if name == "search"]
+    t_s = float(np.mean(searches)) / 1e3
+    roofline = roofline_of("k_search_mfma<%d> (one channel)" % b, pairs_step / 3 * 2 * b * b, t_s)
+    return {
+        "metric": METRIC, "value": round(pairs_step / (ms_step / 1e3), 1), "unit": "pair evals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f16",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "description": wl.description, "image": "%dx%dx3" % (H, W),
+                   "pairs_per_step": pairs_step},
+        "encode_s_per_image": round(ms_step / 1e3, 6),
+        "stage_ms_per_step": {k: round(v, 4) for k, v in stage_sums(recs, args.steps).items()},
+        "roofline": roofline,
+    }
 
 
 def bench_adaptive(args, fic):

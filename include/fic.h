@@ -227,6 +227,23 @@ fic_status fic_encode_pifs_batch(fic_ctx *ctx, int32_t n_images,
 fic_status fic_set_batch_graph(fic_ctx *ctx, int32_t enable);
 
 /* ------------------------------------------------------------------------
+ * fic_encode_color -- per-channel encode of a colour image (Sec. 3.1
+ * discusses colour): the fractal dimensions, and so the pools, come from one
+ * gray image -- fd_source 0: luma (299 R + 587 G + 114 B + 500) div 1000,
+ * 1: channel mean (R + G + B + 1) div 3 -- and each channel is searched over
+ * them (tol as in fic_image_desc; +INF = exhaustive).
+ *   rgb   (dev) interleaved uint8 R, G, B; g->pitch = bytes per row >= 3*width;
+ *         height, width, range_size, domain_step as for fic_encode_pifs.
+ *   codes_r, codes_g, codes_b (dev) fic_code[fic_num_ranges] each; decode
+ *         each with fic_decode_pifs (pitch = width).
+ *   ws    (dev) >= fic_color_workspace_bytes(g, tol).
+ * ---------------------------------------------------------------------- */
+size_t fic_color_workspace_bytes(const fic_geom *g, double tol);
+fic_status fic_encode_color(fic_ctx *ctx, const uint8_t *rgb, const fic_geom *g, double tol,
+                            int32_t fd_source, fic_code *codes_r, fic_code *codes_g,
+                            fic_code *codes_b, void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
  * fic_pack_codes / fic_unpack_codes -- the stored code as a bit string
  * (Sec. 1: per range the domain, the isometry, the contrast and the
  * brightness). Range r's fields start at bit r*W of a little-endian string

@@ -8,8 +8,9 @@ is missing: there is no CPU fallback.
 from . import fic  # noqa: F401
 from .fic import (CODE_DTYPE, Context, FicError, batch_workspace_bytes,  # noqa: F401
                   build_domain_pool, decode_pifs, decode_quadtree, encode, encode_batch,
-                  encode_pifs, encode_quadtree, fd_classify, unpack_codes)
+                  encode_color, encode_pifs, encode_quadtree, fd_classify, unpack_codes)
 
 __all__ = ["fic", "CODE_DTYPE", "Context", "FicError", "batch_workspace_bytes",
-           "build_domain_pool", "decode_pifs", "decode_quadtree", "encode_quadtree",
+           "build_domain_pool", "decode_pifs", "decode_quadtree", "encode_color",
+           "encode_quadtree",
            "encode", "encode_batch", "encode_pifs", "fd_classify", "unpack_codes"]

@@ -543,6 +543,45 @@ fic_status fic_decode_quadtree(fic_ctx *ctx, const fic_code *codes1, const fic_g
                                                tracer_of(ctx)));
 }
 
+// ---------------------------------------------------------------- colour
+namespace {
+// An RGB geometry: pitch in bytes >= 3 * width; the rest as for gray.
+bool color_geom_ok(const fic_geom *g)
+{
+    if (!g || g->pitch < 3 * (int64_t)g->width) return false;
+    fic_geom p = *g;
+    p.pitch = g->width;
+    return geom_ok(&p);
+}
+}  // namespace
+
+size_t fic_color_workspace_bytes(const fic_geom *g, double tol)
+{
+    if (!color_geom_ok(g) || isnan(tol)) return 0;
+    fic::ColorPlan cp;
+    fic::plan_color(to_geom(g), tol, cp);
+    return cp.total;
+}
+
+fic_status fic_encode_color(fic_ctx *ctx, const uint8_t *rgb, const fic_geom *g, double tol,
+                            int32_t fd_source, fic_code *codes_r, fic_code *codes_g,
+                            fic_code *codes_b, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!ctx || !rgb || !codes_r || !codes_g || !codes_b || !ws) return FIC_ERR_INVALID_ARG;
+    if (!color_geom_ok(g) || isnan(tol) || (fd_source != 0 && fd_source != 1))
+        return FIC_ERR_INVALID_ARG;
+    const Geom gg = to_geom(g);
+    if (!key_fits(gg)) return FIC_ERR_CAPACITY;
+    fic::ColorPlan cp;
+    fic::plan_color(gg, tol, cp);
+    if (ws_bytes < cp.total) return FIC_ERR_WORKSPACE;
+    fic_status st = enter(ctx);
+    if (st != FIC_OK) return st;
+    fic_code *const codes[3] = {codes_r, codes_g, codes_b};
+    return dev_status(fic::run_color(cp, rgb, g->pitch, fd_source, codes, ws, ctx->num_cu,
+                                     ctx->counters, (hipStream_t)stream, tracer_of(ctx)));
+}
+
 int64_t fic_packed_words(const fic_geom *g)
 {
     return geom_ok(g) ? fic::packed_words(to_geom(g)) : 0;

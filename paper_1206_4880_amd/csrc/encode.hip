@@ -1702,4 +1702,79 @@ hipError_t run_quadtree(const QuadPlan &qp, const uint8_t *img, int64_t emax, fi
     }
 }
 
+// ------------------------------------------------------------ colour
+namespace {
+// One thread per pixel: the three planes of an interleaved RGB image and the
+// image the dimensions come from (0: luma (299 R + 587 G + 114 B + 500) div
+// 1000, 1: mean (R + G + B + 1) div 3).
+__global__ void k_color_planes(const uint8_t *__restrict__ rgb, int32_t h, int32_t w,
+                               int32_t pitch, int32_t mode, uint8_t *__restrict__ planes)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t np = (int64_t)h * w;
+    if (i >= np) return;
+    const int64_t y = i / w, x = i - y * w;
+    const uint8_t *p = rgb + y * pitch + 3 * x;
+    const int r = p[0], g = p[1], b = p[2];
+    planes[i] = (uint8_t)r;
+    planes[np + i] = (uint8_t)g;
+    planes[2 * np + i] = (uint8_t)b;
+    planes[3 * np + i] = (uint8_t)(mode == 0 ? (299 * r + 587 * g + 114 * b + 500) / 1000
+                                             : (r + g + b + 1) / 3);
+}
+}  // namespace
+
+// Workspace: four planes (R, G, B, dimension image), the FD/pool/encode parts
+// of one image on the plane geometry.
+void plan_color(const Geom &g, double tol, ColorPlan &cp)
+{
+    cp.gp = g;
+    cp.gp.pitch = g.w;
+    BatchJob j;
+    j.img = nullptr; j.g = cp.gp; j.tol = tol; j.codes = nullptr;
+    j.pooled = std::isfinite(tol) || tol < 0;
+    BatchPlan bp;
+    plan_batch(&j, 1, bp);
+    cp.job = j;
+    cp.part = bp.part[0];
+    size_t o = bp.total;
+    cp.off_planes = o;
+    o += align256((size_t)4 * g.h * g.w);
+    cp.total = o;
+}
+
+hipError_t run_color(const ColorPlan &cp, const uint8_t *rgb, int32_t rgb_pitch, int32_t fd_source,
+                     fic_code *const codes[3], void *ws, int num_cu, u64 *counters, hipStream_t s,
+                     const Tracer *tr)
+{
+    char *w = (char *)ws;
+    const Geom &g = cp.gp;
+    const int64_t np = (int64_t)g.h * g.w;
+    uint8_t *planes = (uint8_t *)(w + cp.off_planes);
+    hipLaunchKernelGGL(k_color_planes, dim3(blocks_for(np, 256)), dim3(256), 0, s, rgb, g.h, g.w,
+                       rgb_pitch, fd_source, planes);
+    hipError_t e = hipGetLastError();
+    const BatchPart &pt = cp.part;
+    double *fdr = (double *)(w + pt.off_fdr);
+    double *fdd = (double *)(w + pt.off_fdd);
+    uint32_t *perm = (uint32_t *)(w + pt.off_perm);
+    uint32_t *lo = (uint32_t *)(w + pt.off_lo);
+    uint32_t *hi = (uint32_t *)(w + pt.off_hi);
+    const bool pooled = cp.job.pooled;
+    if (pooled && e == hipSuccess) {
+        const uint8_t *fdimg = planes + 3 * np;
+        e = launch_fd_classify(fdimg, g.h, g.w, g.pitch, g.b, g.b, fdr, nullptr, s, tr);
+        if (e == hipSuccess)
+            e = launch_fd_classify(fdimg, g.h, g.w, g.pitch, 2 * g.b, g.t, fdd, nullptr, s, tr);
+        if (e == hipSuccess)
+            e = launch_pool(fdr, (int32_t)g.R, fdd, (int32_t)g.D, cp.job.tol, perm, lo, hi,
+                            w + pt.off_pool, s, tr);
+    }
+    for (int c = 0; c < 3 && e == hipSuccess; ++c)
+        e = run_encode(pt.plan, planes + c * np, pooled ? perm : nullptr, pooled ? lo : nullptr,
+                       pooled ? hi : nullptr, FIC_KERNEL_MFMA, codes[c], w + pt.off_enc, num_cu,
+                       counters, s, tr);
+    return e;
+}
+
 }  // namespace fic

@@ -261,6 +261,19 @@ struct QuadPlan {
     size_t off_sel, total;
 };
 void plan_quadtree(const Geom &g1, double tol1, const Geom &g2, double tol2, QuadPlan &qp);
+
+// Colour: the channels of an interleaved RGB image, each searched over the
+// pool of the luma (fd_source 0) or mean (1) image.
+struct ColorPlan {
+    Geom gp;                         // plane geometry (pitch = width)
+    BatchJob job;
+    BatchPart part;
+    size_t off_planes, total;
+};
+void plan_color(const Geom &g, double tol, ColorPlan &cp);
+hipError_t run_color(const ColorPlan &cp, const uint8_t *rgb, int32_t rgb_pitch, int32_t fd_source,
+                     fic_code *const codes[3], void *ws, int num_cu, u64 *counters, hipStream_t s,
+                     const Tracer *tr = nullptr);
 hipError_t run_quadtree(const QuadPlan &qp, const uint8_t *img, int64_t emax, fic_code *codes1,
                         fic_code *codes2, void *ws, int num_cu, u64 *counters, hipStream_t s,
                         const Tracer *tr = nullptr);

@@ -81,6 +81,9 @@ def lib():
                                       _vp, _vp, _vp, ctypes.c_size_t, _vp]),
         "fic_decode_quadtree": (_st, [_vp, _vp, ctypes.POINTER(Geom), _vp, ctypes.POINTER(Geom),
                                       _i32, _vp, _vp, _vp, ctypes.c_size_t, _vp, _vp]),
+        "fic_color_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Geom), ctypes.c_double]),
+        "fic_encode_color": (_st, [_vp, _vp, ctypes.POINTER(Geom), ctypes.c_double, _i32, _vp, _vp,
+                                   _vp, _vp, ctypes.c_size_t, _vp]),
         "fic_packed_words": (ctypes.c_int64, [ctypes.POINTER(Geom)]),
         "fic_pack_codes": (_st, [_vp, _vp, ctypes.POINTER(Geom), _vp, ctypes.c_int64, _vp]),
         "fic_unpack_codes": (_st, [_vp, _vp, ctypes.c_int64, ctypes.POINTER(Geom), _vp, _vp]),
@@ -103,7 +106,7 @@ EXPORTED = ("fic_create", "fic_destroy", "fic_status_string", "fic_set_counters"
             "fic_batch_workspace_bytes", "fic_encode_pifs_batch", "fic_set_batch_graph",
             "fic_decode_workspace_bytes", "fic_decode_pifs", "fic_quadtree_workspace_bytes",
             "fic_encode_quadtree", "fic_decode_quadtree", "fic_packed_words", "fic_pack_codes",
-            "fic_unpack_codes")
+            "fic_unpack_codes", "fic_color_workspace_bytes", "fic_encode_color")
 
 
 def status_string(status):
@@ -396,6 +399,30 @@ def decode_quadtree(codes1, codes2, height, width, b1, t1, b2, t2, max_iters=32,
                                      out.data_ptr(), scratch.data_ptr(), wsb, iters.data_ptr(),
                                      _stream()), "fic_decode_quadtree")
     return out, iters
+
+
+def encode_color(rgb, range_size, domain_step, tol=None, fd_source="luma"):
+    """Per-channel encode of an (H, W, 3) uint8 CUDA tensor with pools from
+    the luma or mean image; returns three codes tensors (R, G, B)."""
+    import torch
+    if rgb.dtype != torch.uint8 or rgb.device.type != "cuda" or rgb.dim() != 3 or rgb.shape[2] != 3:
+        raise ValueError("rgb must be an (H, W, 3) uint8 CUDA tensor")
+    rgb = rgb.contiguous()
+    H, W = int(rgb.shape[0]), int(rgb.shape[1])
+    g = make_geom(H, W, range_size, domain_step, pitch=3 * W)
+    src = {"luma": 0, "mean": 1}[fd_source]
+    tl = float("inf") if tol is None else float(tol)
+    nr = int(lib().fic_num_ranges(ctypes.byref(make_geom(H, W, range_size, domain_step))))
+    codes = [torch.empty((nr, 16), dtype=torch.uint8, device=rgb.device) for _ in range(3)]
+    wsb = lib().fic_color_workspace_bytes(ctypes.byref(g), tl)
+    if wsb == 0:
+        raise ValueError("invalid colour geometry")
+    buf = _ws.get(wsb, rgb.device)
+    _check(lib().fic_encode_color(context(rgb.device.index).handle, rgb.data_ptr(), ctypes.byref(g),
+                                  tl, src, codes[0].data_ptr(), codes[1].data_ptr(),
+                                  codes[2].data_ptr(), buf.data_ptr(), wsb, _stream()),
+           "fic_encode_color")
+    return codes
 
 
 def pack_codes(codes, height, width, range_size, domain_step):

@@ -19,6 +19,7 @@ class Workload:
     seed: int
     jobs: tuple = field(default_factory=tuple)   # ((B, t, tol), ...)
     rms: float = None    # two-level workloads: split above this RMS error (gray levels)
+    color: bool = False  # interleaved RGB image (channels from color_image)
 
 
 def _fbm_img(size, hurst, seed):
@@ -57,7 +58,19 @@ WORKLOADS = {
         "ranges above 1.9 gray levels RMS split into 8x8 ranges / 16x16 domains step 2; "
         "FD pool tol 0.05 at both levels",
         5, ((16, 4, 0.05), (8, 2, 0.05)), 1.9),
+    "color1024_b8t1": Workload(
+        "color1024_b8t1",
+        "1024x1024 RGB, channels fBm H = 0.3 / 0.5 / 0.7; 8x8 ranges, 16x16 domains step 1; "
+        "FD pool tol 0.05 from the luma image",
+        6, ((8, 1, 0.05),), None, True),
 }
+
+
+def color_image(size, seed):
+    """An interleaved size x size x 3 uint8 image: three fBm channels with
+    H = 0.3, 0.5, 0.7 from one generator."""
+    rng = np.random.default_rng(seed)
+    return np.ascontiguousarray(np.stack([fbm(size, size, h, rng) for h in (0.3, 0.5, 0.7)], axis=2))
 
 
 def workload_images(name):
@@ -72,6 +85,8 @@ def workload_images(name):
         return _fbm_img(1024, 0.3, 3)
     if name in ("fbm2048_twolevel", "fbm2048_quadtree"):
         return _fbm_img(2048, 0.6, 5)
+    if name == "color1024_b8t1":
+        return color_image(1024, 6)
     raise KeyError(name)
 
 

@@ -248,3 +248,19 @@ def test_decode_accepts_twice_size_geometry(L, hctx):
                              None) == fic.ERR_DEVICE
     assert L.fic_encode_workspace_bytes(ctypes.byref(g32), 0) == 0
     assert L.fic_decode_workspace_bytes(ctypes.byref(fic.make_geom(32, 32, 32, 8))) == 0
+
+
+def test_color_validation(L, hctx):
+    g = fic.make_geom(128, 96, 8, 2, pitch=3 * 96)
+    ws = L.fic_color_workspace_bytes(ctypes.byref(g), 0.05)
+    assert ws > 0
+
+    def C(gg=g, src=0, wsb=ws, tol=0.05):
+        return L.fic_encode_color(hctx.handle, 1, ctypes.byref(gg), tol, src, 1, 1, 1, 1, wsb, None)
+    assert C() == fic.ERR_DEVICE
+    assert C(src=1) == fic.ERR_DEVICE
+    assert C(src=2) == fic.ERR_INVALID_ARG
+    assert C(wsb=ws - 1) == fic.ERR_WORKSPACE
+    assert C(tol=float("nan")) == fic.ERR_INVALID_ARG
+    assert C(gg=fic.make_geom(128, 96, 8, 2, pitch=96)) == fic.ERR_INVALID_ARG   # not 3 bytes a pixel
+    assert L.fic_color_workspace_bytes(ctypes.byref(fic.make_geom(128, 96, 8, 2, pitch=200)), 0.05) == 0

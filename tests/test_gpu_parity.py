@@ -484,3 +484,29 @@ def test_decode_twice_size(fic, orc, b, t, n):
     ref, it = orc.decode_scaled(ref_codes, n, n, b, t, 2, max_iters=32)
     assert out.shape == (2 * n, 2 * n)
     assert np.array_equal(out.cpu().numpy(), ref) and int(iters.item()) == it
+
+
+# ----------------------------------------------------------- colour
+@pytest.mark.parametrize("case", [(0, 0.05, 8, 2, 128, 96), (1, 0.1, 4, 2, 64, 64),
+                                  (0, None, 8, 1, 64, 64), (1, -1.0, 16, 4, 128, 128)])
+def test_color_codes(fic, orc, case):
+    src, tol, b, t, h, w = case
+    rng = np.random.default_rng(80 + b)
+    from synth import fbm as _f
+    rgb = np.stack([_f(h, w, hh, rng) for hh in (0.3, 0.55, 0.8)], axis=2)
+    codes = fic.encode_color(torch.from_numpy(rgb).cuda(), b, t, tol=tol,
+                             fd_source=("luma", "mean")[src])
+    torch.cuda.synchronize()
+    ref = orc.encode_color(rgb, b, t, tol, fd_source=src)
+    for c in range(3):
+        assert_codes(fic.unpack_codes(codes[c]), ref[c], what="colour %s channel %d" % (case, c))
+
+
+def test_color_of_gray_equals_gray(fic):
+    img = fbm(128, 0.5, 90)
+    rgb = np.ascontiguousarray(np.stack([img, img, img], axis=2))
+    codes = fic.encode_color(torch.from_numpy(rgb).cuda(), 8, 2, tol=0.05)
+    gray, _ = fic.encode(dev(img), 8, 2, tol=0.05)
+    torch.cuda.synchronize()
+    for c in range(3):
+        assert np.array_equal(codes[c].cpu().numpy(), gray.cpu().numpy())
