@@ -12,16 +12,22 @@
 //                centred by an integer level dhat (|.| <= 1020), FP16 (exact);
 //                per column Sdd', eps = sum D - n*dhat and u = sqrt(Sdd')/n.
 //   search       a persistent work queue of (range group, column chunk)
-//                items. The group's A rows stay in VGPRs; each MR-column
-//                block costs MB*KS MFMAs, giving C''' = sum (r-rhat)(D-dhat)
-//                exactly in FP32, and Srd' = n*C''' - delta*eps exactly.
-//                A few FP32 instructions per output tile screen out pairs
-//                whose continuous optimum cannot reach the range's best F;
-//                survivors get the exact int64 fit and a packed
-//                (F, domain, isometry) key; keys meet in a global atomicMin.
+//                items, of one image or of all images of a batch. The
+//                group's A rows stay in VGPRs; each MR-column block costs
+//                MB*KS MFMAs, giving C''' = sum (r-rhat)(D-dhat) exactly in
+//                FP32, and Srd' = n*C''' - delta*eps exactly. A few FP32
+//                instructions per output tile screen out pairs whose
+//                continuous optimum cannot reach the range's best F; passing
+//                cells queue in LDS and get the exact int64 fit a wave's worth
+//                at a time; packed (F, domain, isometry) keys meet in LDS and
+//                then in a global atomicMin.
 //   finalize     recompute the winner exactly from the image, write fic_code.
 // Plain path (FIC_KERNEL_PLAIN): one thread per (range, domain, isometry),
 // integer cross term from the 2x2-sum image, exact fit, the same keys.
+// On top of these: batches (one persistent search per range size over many
+// images, recorded as a HIP graph), the two-level partition (level-2 search
+// of the quadrants of split ranges) and colour (three channel searches over
+// the pools of one gray image).
 #include "fic_internal.h"
 
 #include <algorithm>
@@ -50,7 +56,6 @@ template <int B> constexpr float screen_slack()
 }
 
 template <int EPL> struct Frag;
-template <> struct Frag<4> { typedef half4_t type; };
 template <> struct Frag<8> { typedef half8_t type; };
 
 __device__ __forceinline__ float4_t mma(half8_t a, half8_t b, float4_t c)
@@ -799,7 +804,7 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma(const SearchArgs *__rest
     }
 }
 
-// ---------------- 32 x 32 tiles (4x4 and 8x8 ranges, K = 16 per MFMA)
+// ---------------- 32 x 32 tiles (4x4 ranges; K = 16 per MFMA)
 // A wave owns GR = 4*MB ranges: row block blk holds the range quad 4*blk ..
 // 4*blk+3 under the 8 isometries. Lane l's 16 outputs of a tile are column
 // l%32 against range 4*blk + 2*(l/32) (v < 8) and that + 1 (v >= 8), under
