@@ -804,6 +804,155 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma(const SearchArgs *__rest
     }
 }
 
+// ---------------- 16 x 16 tiles with B shared through LDS (16x16 ranges)
+// A 16x16 range has 256 pixels: every 16-column block brings 8 KB of B
+// fragments per wave for only 16 MFMAs, more than the L1/L2 path feeds four
+// SIMDs. So a workgroup takes (4 consecutive groups, column chunk) items: its
+// 4 waves load each stage of kStage16 column blocks into LDS once (direct
+// global->LDS loads, double-buffered, one barrier per stage) and each wave
+// screens its own group's ranges against them; blocks outside a wave's own
+// pools are skipped, blocks inside all of them skip the per-range mask.
+constexpr int kStage16 = 2;          // 16-column blocks per LDS stage
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+template <int B>
+__global__ __launch_bounds__(256, 2) void k_search_lds16(const SearchArgs *__restrict__ tab,
+                                                         const uint32_t *__restrict__ base,
+                                                         int32_t n_img, uint32_t *item_ctr,
+                                                         u64 *counters)
+{
+    using C = Cfg<B>;
+    constexpr int MW = C::MB, KS = C::KS, GR = C::GR, SB = kStage16, FR = SB * KS;
+    typedef typename WaveState<B>::frag_t frag_t;
+    __shared__ frag_t sB0[FR * 64], sB1[FR * 64];   // two separate buffers: the DMA into one
+    __shared__ float sU0[SB * 16], sU1[SB * 16];    // never aliases the one being read
+    __shared__ Queue16<B> queues[4];
+    __shared__ uint32_t sItem;
+    const int lane = threadIdx.x & 63, hl = lane >> 5, col = lane & 15;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    Queue16<B> *qu = &queues[w];
+    const uint32_t nitems = base[n_img];
+    WaveState<B> st;
+    st.survivors = 0;
+    st.screened = 0;
+    st.qn = 0;
+    u64 items_done = 0;
+    for (;;) {
+        if (threadIdx.x == 0) sItem = atomicAdd(item_ctr, 1u);
+        __syncthreads();
+        const uint32_t item = sItem;
+        __syncthreads();
+        if (item >= nitems) break;
+        int ia = 0, ib = n_img;              // last image whose base <= item
+        while (ib - ia > 1) {
+            const int m = (ia + ib) >> 1;
+            if (base[m] <= item) ia = m; else ib = m;
+        }
+        ia = __builtin_amdgcn_readfirstlane(ia);
+        const SearchArgs *ta = tab + ia;
+        const SearchArgs a = *ta;
+        const WorkItem wi = a.items[item - base[ia]];
+        st.grp = wi.grp * 4 + (uint32_t)w;
+        const frag_t *ap = (const frag_t *)a.A + (int64_t)st.grp * MW * KS * 64 + lane;
+#pragma unroll
+        for (int b = 0; b < MW; ++b)
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) st.af[b][ks] = ap[(b * KS + ks) * 64];
+        if (lane < GR) {
+            const int64_t slot = (int64_t)st.grp * GR + lane;
+            qu->best[lane] = a.keys[slot];
+            qu->srr[lane] = a.rs[slot].srr;
+            qu->delta[lane] = a.rs[slot].delta;
+        }
+        // the wave's own pools: union [wlo, whi) and intersection [ilo, ihi)
+        uint32_t wlo = 0xffffffffu, whi = 0u, ilo = 0u, ihi = 0xffffffffu;
+#pragma unroll
+        for (int b = 0; b < MW; ++b) {
+            const int64_t slot = (int64_t)st.grp * GR + 2 * b + hl;
+            const RangeStat rsx = a.rs[slot];
+            const u64 bk = a.keys[slot];
+            st.lo[b] = rsx.lo;
+            st.hi[b] = rsx.hi;
+            const bool act = !(rsx.flags & kIdle);
+            st.T[b] = !act ? __builtin_inff()
+                           : (bk == kNoKey ? 0.0f : screen_t(rsx.srr, (int64_t)(bk >> a.shift)));
+            if (act) {
+                wlo = min(wlo, rsx.lo); whi = max(whi, rsx.hi);
+                ilo = max(ilo, rsx.lo); ihi = min(ihi, rsx.hi);
+            }
+        }
+        wlo = min(wlo, (uint32_t)__shfl_xor((int)wlo, 32));
+        whi = max(whi, (uint32_t)__shfl_xor((int)whi, 32));
+        ilo = max(ilo, (uint32_t)__shfl_xor((int)ilo, 32));
+        ihi = min(ihi, (uint32_t)__shfl_xor((int)ihi, 32));
+        wlo = __builtin_amdgcn_readfirstlane(wlo);
+        whi = __builtin_amdgcn_readfirstlane(whi);
+        ilo = __builtin_amdgcn_readfirstlane(ilo);
+        ihi = __builtin_amdgcn_readfirstlane(ihi);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        const int cb0 = (int)(wi.c0 >> 4), cb1 = (int)(wi.c1 >> 4);
+        const int nst = (cb1 - cb0 + SB - 1) / SB;
+        const auto *gB = as_global((const frag_t *)a.Bm);
+        const auto *gU = as_global(a.u);
+        auto stage_load = [&](int sidx, frag_t *dB, float *dU) {
+            const int sb0 = cb0 + sidx * SB;
+#pragma unroll
+            for (int f = w; f < FR; f += 4)
+                if (sb0 + f / KS < cb1)
+                    __builtin_amdgcn_global_load_lds(
+                        (const __attribute__((address_space(1))) void *)(gB + ((int64_t)sb0 * KS + f) * 64 + lane),
+                        (lds_void *)(dB + f * 64), 16, 0, 0);
+            if (w == 0 && lane < SB * 16 && sb0 + lane / 16 < cb1)
+                __builtin_amdgcn_global_load_lds(
+                    (const __attribute__((address_space(1))) void *)(gU + (int64_t)sb0 * 16 + lane),
+                    (lds_void *)dU, 4, 0, 0);
+        };
+        if (nst > 0) stage_load(0, sB0, sU0);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        for (int sidx = 0; sidx < nst; ++sidx) {
+            const frag_t *cB = (sidx & 1) ? sB1 : sB0;
+            const float *cU = (sidx & 1) ? sU1 : sU0;
+            if (sidx + 1 < nst) stage_load(sidx + 1, (sidx & 1) ? sB0 : sB1, (sidx & 1) ? sU0 : sU1);
+#pragma unroll
+            for (int j = 0; j < SB; ++j) {
+                const int cb = cb0 + sidx * SB + j;
+                const uint32_t c0 = (uint32_t)cb * 16;
+                if (cb >= cb1 || c0 >= whi || c0 + 16 <= wlo) continue;
+                frag_t bf[KS];
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks) bf[ks] = cB[(j * KS + ks) * 64 + lane];
+                const float u = cU[j * 16 + col];
+                st.screened += 16 * GR * 8;
+                if (c0 >= ilo && c0 + 16 <= ihi)
+                    screen_block<B, false>(ta, st, qu, bf, u, cb);
+                else
+                    screen_block<B, true>(ta, st, qu, bf, u, cb);
+            }
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+        }
+        if (st.qn) flush_and_refresh16<B>(ta, st, qu);
+        if (lane < GR) {
+            const u64 bk = qu->best[lane];
+            if (bk != kNoKey) atomicMin(&a.keys[(int64_t)st.grp * GR + lane], bk);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        items_done += 1;
+    }
+    if (counters) {
+        u64 sv = st.survivors;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) sv += __shfl_xor(sv, off);
+        if (lane == 0) {
+            atomicAdd(&counters[0], st.screened);
+            atomicAdd(&counters[1], sv);
+            if (w == 0) atomicAdd(&counters[2], items_done);
+        }
+    }
+}
+
 // ---------------- 32 x 32 tiles (4x4 ranges; K = 16 per MFMA)
 // A wave owns GR = 4*MB ranges: row block blk holds the range quad 4*blk ..
 // 4*blk+3 under the 8 isometries. Lane l's 16 outputs of a tile are column
@@ -1116,6 +1265,8 @@ template <int B> const void *search_kernel()
 {
     if constexpr (Cfg<B>::MR == 32)
         return reinterpret_cast<const void *>(&k_search_mfma32<B>);
+    else if constexpr (B == 16)
+        return reinterpret_cast<const void *>(&k_search_lds16<B>);
     else
         return reinterpret_cast<const void *>(&k_search_mfma<B>);
 }
@@ -1352,9 +1503,9 @@ hipError_t prep_b(const EncodePlan &p, const uint8_t *img, const uint32_t *perm,
     trace(tr, FIC_STAGE_WORKLIST, 1, s);
     hipLaunchKernelGGL(k_seed<B>, dim3(blocks_for(p.Rp * 64, th)), dim3(th), 0, s, A, Bm, rs, eps,
                        sdd, dom, p.Rp, perm, bmin, p.shift, keys, counters);
-    hipLaunchKernelGGL(k_group_bounds, dim3(blocks_for(p.G, th)), dim3(th), 0, s, rs, p.G,
-                       (int)p.GR, (uint32_t)p.Dp, (uint32_t)Cfg<B>::MR, grp);
-    hipLaunchKernelGGL(k_chunk_span, dim3(blocks_for(p.NC, th)), dim3(th), 0, s, grp, p.G, p.NC,
+    hipLaunchKernelGGL(k_group_bounds, dim3(blocks_for(p.IG, th)), dim3(th), 0, s, rs, p.IG,
+                       (int)(p.GR * p.IGW), (uint32_t)p.Dp, (uint32_t)Cfg<B>::MR, grp);
+    hipLaunchKernelGGL(k_chunk_span, dim3(blocks_for(p.NC, th)), dim3(th), 0, s, grp, p.IG, p.NC,
                        (uint32_t)p.chunk, chunkcnt, chunkfill);
     // exclusive scan of the per-chunk counts; the total is the item count
     scan_u32(chunkcnt, p.NC, ctr + 1, w + p.off_scan, s);
@@ -1393,6 +1544,9 @@ hipError_t search_b(const SearchArgs *tab, int32_t n, uint32_t *base, uint32_t *
     trace(tr, FIC_STAGE_SEARCH, 1, s);
     if constexpr (Cfg<B>::MR == 32)
         hipLaunchKernelGGL(k_search_mfma32<B>, dim3(per_cu * num_cu), dim3(256), 0, s, tab,
+                           (const uint32_t *)base, n, item_ctr, counters);
+    else if constexpr (B == 16)
+        hipLaunchKernelGGL(k_search_lds16<B>, dim3(per_cu * num_cu), dim3(256), 0, s, tab,
                            (const uint32_t *)base, n, item_ctr, counters);
     else
         hipLaunchKernelGGL(k_search_mfma<B>, dim3(per_cu * num_cu), dim3(256), 0, s, tab,
@@ -1454,12 +1608,16 @@ void plan_encode(const Geom &g, int pooled, EncodePlan &p)
     p.pooled = pooled;
     p.GR = g.b == 16 ? Cfg<16>::GR : g.b == 8 ? Cfg<8>::GR : Cfg<4>::GR;
     const int mr = g.b == 16 ? Cfg<16>::MR : g.b == 8 ? Cfg<8>::MR : Cfg<4>::MR;
-    p.Rp = (g.R + p.GR - 1) / p.GR * p.GR;
+    // 16x16 ranges: a workgroup's 4 waves search 4 consecutive groups over
+    // the same columns, sharing the B fragments through LDS
+    p.IGW = g.b == 16 ? 4 : 1;
+    p.Rp = (g.R + p.GR * p.IGW - 1) / (p.GR * p.IGW) * (p.GR * p.IGW);
     p.G = p.Rp / p.GR;
+    p.IG = p.G / p.IGW;
     p.Dp = (g.D + mr - 1) / mr * mr;
     p.chunk = pooled ? kChunkPooled : kChunkExhaustive;
     p.NC = (p.Dp + p.chunk - 1) / p.chunk;
-    p.max_items = p.G * p.NC;
+    p.max_items = p.IG * p.NC;
     int dbits = 1;
     while (((int64_t)1 << dbits) < g.D) ++dbits;
     p.shift = dbits + 3;
@@ -1479,7 +1637,7 @@ void plan_encode(const Geom &g, int pooled, EncodePlan &p)
     p.off_args = take(sizeof(SearchArgs));
     p.off_chunkcnt = take((size_t)p.NC * 4);
     p.off_chunkfill = take((size_t)p.NC * 4);
-    p.off_grp = take((size_t)p.G * 16);
+    p.off_grp = take((size_t)p.IG * 16);
     p.off_bmin = take((size_t)((g.D + kBminBlock - 1) / kBminBlock) * 4);
     p.off_S = take((size_t)(g.h - 1) * (g.w - 1) * 2);
     p.off_sortkeys = take((size_t)p.Rp * 8);

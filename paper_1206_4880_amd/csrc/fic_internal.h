@@ -49,7 +49,7 @@ template <> struct Cfg<8> {
     static constexpr int n = 64, MR = 16, KPI = 32, EPL = 8, KS = 2, MB = 8, NCH = 1, GR = 16;
 };
 template <> struct Cfg<16> {
-    static constexpr int n = 256, MR = 16, KPI = 32, EPL = 8, KS = 8, MB = 2, NCH = 4, GR = 4;
+    static constexpr int n = 256, MR = 16, KPI = 32, EPL = 8, KS = 8, MB = 3, NCH = 4, GR = 6;
 };
 
 // Row of range ls (0..GR-1 of its wave group) under isometry q: row block
@@ -203,6 +203,7 @@ struct EncodePlan {
     Geom g;
     int pooled;
     int64_t Rp, Dp, G, GR, NC;   // padded ranges/columns, groups, ranges per group, chunks
+    int64_t IGW, IG;              // groups per work item (one per wave of a workgroup), item groups
     int32_t chunk, shift;
     int64_t max_items;
     size_t off_A, off_rs, off_order, off_B, off_u, off_eps, off_sdd, off_dom, off_keys,
