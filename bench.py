@@ -154,6 +154,11 @@ def oracle_rate(img_np, b, t, tol, pool_sizes, D, seconds, what):
                       % (what, count, R, cpu_pairs, cpu_s)}
 
 
+def search_kernel_name(b):
+    """Name of the matrix-core search kernel the library runs for B x B ranges."""
+    return {4: "k_search_mfma32<4>", 16: "k_search_lds16<16>"}.get(b, "k_search_mfma<%d>" % b)
+
+
 def roofline_of(kernel, flops, t_s):
     achieved = flops / t_s / 1e12
     return {"kernel": kernel, "bound": "mfma", "achieved": round(achieved, 2),
@@ -266,7 +271,7 @@ def bench_image(args, fic, wl, img_np):
     dom = max(range(len(jobs)), key=lambda i: np.mean(search_ms[i]))
     bd, td, told = jobs[dom]
     t_search = float(np.mean(search_ms[dom])) / 1e3
-    roofline = roofline_of("k_search_mfma<%d> (%s)" % (bd, job_label(bd, td, told, multi)),
+    roofline = roofline_of("%s (%s)" % (search_kernel_name(bd), job_label(bd, td, told, multi)),
                            pairs[dom] * 2 * bd * bd, t_search)
     if wl.name == "fbm1024_b8t1" and dom == 0:
         roofline["traffic"] = measured_traffic()
@@ -397,7 +402,7 @@ def bench_quadtree(args, fic, wl, img_np):
     lv_ms = [float(np.mean(searches[0::2])), float(np.mean(searches[1::2]))]
     dom = 0 if lv_ms[0] >= lv_ms[1] else 1
     bd = wl.jobs[dom][0]
-    roofline = roofline_of("k_search_mfma<%d> (level %d)" % (bd, dom + 1),
+    roofline = roofline_of("%s (level %d)" % (search_kernel_name(bd), dom + 1),
                            pairs[dom] * 2 * bd * bd, lv_ms[dom] / 1e3)
     out = {
         "metric": METRIC,
@@ -457,7 +462,7 @@ def bench_color(args, fic, wl, rgb_np):
     progress("timed %d steps: %.3f ms per step" % (args.steps, ms_step))
     searches = [ms for (name, ms) in recs if name == "search"]
     t_s = float(np.mean(searches)) / 1e3
-    roofline = roofline_of("k_search_mfma<%d> (one channel)" % b, pairs_step / 3 * 2 * b * b, t_s)
+    roofline = roofline_of("%s (one channel)" % search_kernel_name(b), pairs_step / 3 * 2 * b * b, t_s)
     return {
         "metric": METRIC, "value": round(pairs_step / (ms_step / 1e3), 1), "unit": "pair evals/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
@@ -594,7 +599,7 @@ def bench_batch(args, fic, wl):
     order = sorted(pairs_b)                 # one search launch per range size, ascending B
     launches = {b: ms for b, ms in zip(order, searches)}
     bd = max(launches, key=lambda b: launches[b])
-    roofline = roofline_of("k_search_mfma<%d> (batch, all B=%d images)" % (bd, bd),
+    roofline = roofline_of("%s (batch, all B=%d images)" % (search_kernel_name(bd), bd),
                            pairs_b[bd] * 2 * bd * bd, launches[bd] / 1e3)
     out = {
         "metric": METRIC,

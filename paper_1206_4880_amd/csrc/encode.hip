@@ -55,6 +55,25 @@ template <int B> constexpr float screen_slack()
     return Cfg<B>::n / 4.0f + (Cfg<B>::NCH > 1 ? 64.0f : 0.0f);
 }
 
+// Threshold of the 16x16 search, whose hot screen sums all n products in one
+// FP32 accumulator. The products are exact; every partial sum is at most
+// ||A|| ||B|| (Cauchy-Schwarz), so each of the at most n + KS roundings is off
+// by at most ||A|| ||B|| 2^-23. With ||B|| <= sqrt(n) (u + 1/2) and
+// ||A||^2 <= Srr'/n + n/4 (centring by an integer level), lowering T by
+// e = (n + KS) 2^-23 sqrt(n) ||A|| covers the u-proportional part of the
+// error; the rest, e/2 <= 1.1, is inside screen_slack. Other range sizes
+// accumulate exactly and keep T.
+template <int B> __device__ inline float screen_t_b(int64_t srr, int64_t f)
+{
+    using C = Cfg<B>;
+    const float t = screen_t(srr, f);
+    if (C::NCH == 1 || t == 0.0f) return t;
+    const double na = sqrt((double)srr / C::n + C::n / 4.0);
+    const double e = (double)(C::n + C::KS) * 0x1p-23 * sqrt((double)C::n) * na;
+    const double tf = ((double)t - e) * (1.0 - 0x1p-20);
+    return tf > 0.0 ? (float)tf : 0.0f;
+}
+
 template <int EPL> struct Frag;
 template <> struct Frag<8> { typedef half8_t type; };
 
@@ -495,6 +514,22 @@ as_global(const T *p)
     return (const __attribute__((address_space(1))) T *)p;
 }
 
+// A pointer every lane holds the same value of, moved to scalar registers, so
+// that block offsets are scalar arithmetic and loads use the scalar base.
+template <class T> __device__ __forceinline__ const T *uniform_ptr(const T *p)
+{
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (const T *)(((uint64_t)hi << 32) | lo);
+}
+
+// True when any lane's flag is set; a scalar test of the lane mask.
+__device__ __forceinline__ bool wave_any(bool x)
+{
+    return __builtin_amdgcn_ballot_w64(x) != 0;
+}
+
 // ---------------- 16 x 16 tiles (8x8 and 16x16 ranges)
 // A wave owns GR = 2*MB ranges: row block b holds ranges 2b and 2b+1 under
 // the 8 isometries. Lane l of a tile sees column l%16 against range
@@ -575,7 +610,7 @@ __device__ __noinline__ void flush16(const SearchArgs *ta, uint32_t nq, Queue16<
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     if (lane < GR) {
         const u64 bk = qu->best[lane];
-        qu->T[lane] = bk == kNoKey ? 0.0f : screen_t(qu->srr[lane], (int64_t)(bk >> a.shift));
+        qu->T[lane] = bk == kNoKey ? 0.0f : screen_t_b<B>(qu->srr[lane], (int64_t)(bk >> a.shift));
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
@@ -595,17 +630,14 @@ __device__ __forceinline__ void flush_and_refresh16(const SearchArgs *ta, WaveSt
             st.T[b] = qu->T[2 * b + hl];
 }
 
-template <int B, bool MASK>
-__device__ __forceinline__ void screen_block(const SearchArgs *ta, WaveState<B> &st,
-                                             Queue16<B> *qu,
-                                             const typename WaveState<B>::frag_t (&bf)[Cfg<B>::KS],
-                                             float u, int cb)
+// The cross terms of one 16-column block against the wave's row blocks.
+template <int B>
+__device__ __forceinline__ void mma_block(const WaveState<B> &st,
+                                          const typename WaveState<B>::frag_t (&bf)[Cfg<B>::KS],
+                                          float4_t (&acc)[Cfg<B>::MB][Cfg<B>::NCH])
 {
     using C = Cfg<B>;
     constexpr int MW = C::MB, NCH = C::NCH, KPC = C::KS / NCH;
-    const float slack = screen_slack<B>();
-    const int lane = threadIdx.x & 63, hl = lane >> 5, col = lane & 15;
-    float4_t acc[MW][NCH];
 #pragma unroll
     for (int c = 0; c < NCH; ++c)
 #pragma unroll
@@ -615,21 +647,39 @@ __device__ __forceinline__ void screen_block(const SearchArgs *ta, WaveState<B> 
                 const float4_t z = {0.f, 0.f, 0.f, 0.f};
                 acc[b][c] = mma(st.af[b][c * KPC + kk], bf[c * KPC + kk], kk ? acc[b][c] : z);
             }
+}
+
+// Screen the cross terms of column block cb; queue the passing half cells.
+template <int B, bool MASK>
+__device__ __forceinline__ void screen_acc(const SearchArgs *ta, WaveState<B> &st,
+                                           Queue16<B> *qu,
+                                           const float4_t (&acc)[Cfg<B>::MB][Cfg<B>::NCH],
+                                           float u, int cb)
+{
+    using C = Cfg<B>;
+    constexpr int MW = C::MB, NCH = C::NCH;
+    const float slack = screen_slack<B>();
+    const int lane = threadIdx.x & 63, hl = lane >> 5, col = lane & 15;
     const uint32_t p = (uint32_t)cb * 16 + col;
     bool pass[MW];
     bool hit = false;
+    float dmax = -__builtin_inff();
 #pragma unroll
     for (int b = 0; b < MW; ++b) {
         float4_t sv = acc[b][0];
 #pragma unroll
         for (int c = 1; c < NCH; ++c) sv += acc[b][c];
         const float m = fmaxf(fmaxf(fabsf(sv[0]), fabsf(sv[1])), fmaxf(fabsf(sv[2]), fabsf(sv[3])));
-        bool h = m >= fmaf(st.T[b], u, -slack);
+        // m - T u in one rounding: >= -slack whenever m >= T u - slack
+        const float d = fmaf(-st.T[b], u, m);
+        bool h = d >= -slack;
         if (MASK) h = h && p >= st.lo[b] && p < st.hi[b];
         pass[b] = h;
-        hit = hit || h;
+        if (MASK) hit = hit || h;
+        else dmax = fmaxf(dmax, d);  // unmasked: one compare for all row blocks
     }
-    if (!__any(hit)) return;
+    if (!MASK) hit = dmax >= -slack;
+    if (!wave_any(hit)) return;
     // append the passing half cells (at most 64 per row block)
     const uint32_t isob = ((lane >> 4) & 1) * 4;
 #pragma unroll
@@ -656,6 +706,66 @@ __device__ __forceinline__ void screen_block(const SearchArgs *ta, WaveState<B> 
     }
 }
 
+template <int B, bool MASK>
+__device__ __forceinline__ void screen_block(const SearchArgs *ta, WaveState<B> &st,
+                                             Queue16<B> *qu,
+                                             const typename WaveState<B>::frag_t (&bf)[Cfg<B>::KS],
+                                             float u, int cb)
+{
+    float4_t acc[Cfg<B>::MB][Cfg<B>::NCH];
+    mma_block<B>(st, bf, acc);
+    screen_acc<B, MASK>(ta, st, qu, acc, u, cb);
+}
+
+// 16x16 ranges, B fragments of the block in LDS (lane order). The hot test
+// chains all KS MFMAs into one accumulator per row block; only a block where
+// some lane passes recomputes the exact 64-term chunk sums (re-reading its
+// fragments) and goes through the exact screen and queue.
+template <int B, bool MASK>
+__device__ __forceinline__ void screen_block_lds(const SearchArgs *ta, WaveState<B> &st,
+                                                 Queue16<B> *qu,
+                                                 const typename WaveState<B>::frag_t *lb,
+                                                 float u, int cb)
+{
+    using C = Cfg<B>;
+    constexpr int MW = C::MB, KS = C::KS;
+    typedef typename WaveState<B>::frag_t frag_t;
+    const int lane = threadIdx.x & 63, col = lane & 15;
+    const float slack = screen_slack<B>();
+    float4_t acc[MW];
+    {
+        frag_t bf[KS];
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) bf[ks] = lb[ks * 64 + lane];
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+            for (int b = 0; b < MW; ++b) {
+                const float4_t z = {0.f, 0.f, 0.f, 0.f};
+                acc[b] = mma(st.af[b][ks], bf[ks], ks ? acc[b] : z);
+            }
+    }
+    const uint32_t p = (uint32_t)cb * 16 + col;
+    bool hit = false;
+    float dmax = -__builtin_inff();
+#pragma unroll
+    for (int b = 0; b < MW; ++b) {
+        const float4_t sv = acc[b];
+        const float m = fmaxf(fmaxf(fabsf(sv[0]), fabsf(sv[1])), fmaxf(fabsf(sv[2]), fabsf(sv[3])));
+        const float d = fmaf(-st.T[b], u, m);
+        if (MASK) hit = hit || (d >= -slack && p >= st.lo[b] && p < st.hi[b]);
+        else dmax = fmaxf(dmax, d);
+    }
+    if (!MASK) hit = dmax >= -slack;
+    if (!wave_any(hit)) return;
+    frag_t bx[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) bx[ks] = lb[ks * 64 + lane];
+    float4_t accx[MW][C::NCH];
+    mma_block<B>(st, bx, accx);
+    screen_acc<B, MASK>(ta, st, qu, accx, u, cb);
+}
+
 // Column blocks [cb_begin, cb_end) against the wave's A rows. The B
 // fragments and u of the block two ahead are loaded while a block computes.
 template <int B, bool MASK>
@@ -666,10 +776,14 @@ __device__ __forceinline__ void scan_blocks(const SearchArgs &a, const SearchArg
     using C = Cfg<B>;
     constexpr int KS = C::KS;
     typedef typename WaveState<B>::frag_t frag_t;
+    cb_begin = __builtin_amdgcn_readfirstlane(cb_begin);
+    cb_end = __builtin_amdgcn_readfirstlane(cb_end);
     if (cb_begin >= cb_end) return;
     const int lane = threadIdx.x & 63, col = lane & 15;
-    const auto *bbase = as_global((const frag_t *)a.Bm) + lane;
-    const auto *ubase = as_global(a.u) + col;
+    // scalar base + block offset, 32-bit lane offset
+    const auto *bbase = as_global(uniform_ptr((const frag_t *)a.Bm));
+    const auto *ubase = as_global(uniform_ptr(a.u));
+    const uint32_t lb = (uint32_t)lane, lu = (uint32_t)col;
     const int last = cb_end - 1;
     frag_t b0[KS], b1[KS];
     float u0, u1;
@@ -677,37 +791,37 @@ __device__ __forceinline__ void scan_blocks(const SearchArgs &a, const SearchArg
         const int c1 = min(cb_begin + 1, last);
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
-            b0[ks] = bbase[((int64_t)cb_begin * KS + ks) * 64];
-            b1[ks] = bbase[((int64_t)c1 * KS + ks) * 64];
+            b0[ks] = (bbase + (int64_t)cb_begin * KS * 64)[lb + ks * 64];
+            b1[ks] = (bbase + (int64_t)c1 * KS * 64)[lb + ks * 64];
         }
-        u0 = ubase[(int64_t)cb_begin * 16];
-        u1 = ubase[(int64_t)c1 * 16];
+        u0 = (ubase + (int64_t)cb_begin * 16)[lu];
+        u1 = (ubase + (int64_t)c1 * 16)[lu];
     }
     // whole pairs of blocks without a branch between them (a conditional
     // second step would make the compiler wait for the loads just issued)
+    // the MFMAs of a block are issued before its fragments are reloaded
+    // (no register copies), and the screen follows the reload
     int cb = cb_begin;
     for (; cb + 2 <= cb_end; cb += 2) {
         {
-            frag_t bc[KS];
-#pragma unroll
-            for (int ks = 0; ks < KS; ++ks) bc[ks] = b0[ks];
+            float4_t acc[C::MB][C::NCH];
+            mma_block<B>(st, b0, acc);
             const float uc = u0;
             const int nx = min(cb + 2, last);
 #pragma unroll
-            for (int ks = 0; ks < KS; ++ks) b0[ks] = bbase[((int64_t)nx * KS + ks) * 64];
-            u0 = ubase[(int64_t)nx * 16];
-            screen_block<B, MASK>(ta, st, qu, bc, uc, cb);
+            for (int ks = 0; ks < KS; ++ks) b0[ks] = (bbase + (int64_t)nx * KS * 64)[lb + ks * 64];
+            u0 = (ubase + (int64_t)nx * 16)[lu];
+            screen_acc<B, MASK>(ta, st, qu, acc, uc, cb);
         }
         {
-            frag_t bc[KS];
-#pragma unroll
-            for (int ks = 0; ks < KS; ++ks) bc[ks] = b1[ks];
+            float4_t acc[C::MB][C::NCH];
+            mma_block<B>(st, b1, acc);
             const float uc = u1;
             const int nx = min(cb + 3, last);
 #pragma unroll
-            for (int ks = 0; ks < KS; ++ks) b1[ks] = bbase[((int64_t)nx * KS + ks) * 64];
-            u1 = ubase[(int64_t)nx * 16];
-            screen_block<B, MASK>(ta, st, qu, bc, uc, cb + 1);
+            for (int ks = 0; ks < KS; ++ks) b1[ks] = (bbase + (int64_t)nx * KS * 64)[lb + ks * 64];
+            u1 = (ubase + (int64_t)nx * 16)[lu];
+            screen_acc<B, MASK>(ta, st, qu, acc, uc, cb + 1);
         }
     }
     if (cb < cb_end) screen_block<B, MASK>(ta, st, qu, b0, u0, cb);
@@ -771,7 +885,7 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma(const SearchArgs *__rest
             st.hi[b] = rsx.hi;
             const bool act = !(rsx.flags & kIdle);
             st.T[b] = !act ? __builtin_inff()
-                           : (bk == kNoKey ? 0.0f : screen_t(rsx.srr, (int64_t)(bk >> a.shift)));
+                           : (bk == kNoKey ? 0.0f : screen_t_b<B>(rsx.srr, (int64_t)(bk >> a.shift)));
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         const uint4 gb = a.grp[st.grp];
@@ -876,7 +990,7 @@ __global__ __launch_bounds__(256, 2) void k_search_lds16(const SearchArgs *__res
             st.hi[b] = rsx.hi;
             const bool act = !(rsx.flags & kIdle);
             st.T[b] = !act ? __builtin_inff()
-                           : (bk == kNoKey ? 0.0f : screen_t(rsx.srr, (int64_t)(bk >> a.shift)));
+                           : (bk == kNoKey ? 0.0f : screen_t_b<B>(rsx.srr, (int64_t)(bk >> a.shift)));
             if (act) {
                 wlo = min(wlo, rsx.lo); whi = max(whi, rsx.hi);
                 ilo = max(ilo, rsx.lo); ihi = min(ihi, rsx.hi);
@@ -920,15 +1034,12 @@ __global__ __launch_bounds__(256, 2) void k_search_lds16(const SearchArgs *__res
                 const int cb = cb0 + sidx * SB + j;
                 const uint32_t c0 = (uint32_t)cb * 16;
                 if (cb >= cb1 || c0 >= whi || c0 + 16 <= wlo) continue;
-                frag_t bf[KS];
-#pragma unroll
-                for (int ks = 0; ks < KS; ++ks) bf[ks] = cB[(j * KS + ks) * 64 + lane];
                 const float u = cU[j * 16 + col];
                 st.screened += 16 * GR * 8;
                 if (c0 >= ilo && c0 + 16 <= ihi)
-                    screen_block<B, false>(ta, st, qu, bf, u, cb);
+                    screen_block_lds<B, false>(ta, st, qu, cB + j * KS * 64, u, cb);
                 else
-                    screen_block<B, true>(ta, st, qu, bf, u, cb);
+                    screen_block_lds<B, true>(ta, st, qu, cB + j * KS * 64, u, cb);
             }
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
@@ -1066,38 +1177,29 @@ __device__ __forceinline__ void flush_and_refresh(const SearchArgs *ta, Wave32<B
 template <int B, bool MASK>
 __device__ __forceinline__ void screen32(const SearchArgs &a, const SearchArgs *ta,
                                          Wave32<B> &st, Queue32<B> *qu,
-                                         const half8_t (&bf)[Cfg<B>::KS], float u, int cb)
+                                         const float16_t (&acc)[Cfg<B>::MB], float u, int cb)
 {
-    constexpr int MB = Cfg<B>::MB, KS = Cfg<B>::KS;
+    constexpr int MB = Cfg<B>::MB;
     const float slack = screen_slack<B>();
     const int lane = threadIdx.x & 63, h = lane >> 5;
-    float16_t acc[MB];
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-        for (int blk = 0; blk < MB; ++blk) {
-            float16_t z;
-            if (ks == 0) {
-#pragma unroll
-                for (int e = 0; e < 16; ++e) z[e] = 0.0f;
-            } else {
-                z = acc[blk];
-            }
-            acc[blk] = mma32(st.af[blk][ks], bf[ks], z);
-        }
     const uint32_t p = (uint32_t)cb * 32 + (lane & 31);
     bool pass[MB][2];
     bool hit = false;
+    float dmax = -__builtin_inff();
 #pragma unroll
     for (int blk = 0; blk < MB; ++blk)
 #pragma unroll
         for (int hl = 0; hl < 2; ++hl) {
-            bool ok = max8(acc[blk], 8 * hl) >= fmaf(st.T[blk][hl], u, -slack);
+            // max |C'''| - T u in one rounding (see the 16x16 screen)
+            const float d = fmaf(-st.T[blk][hl], u, max8(acc[blk], 8 * hl));
+            bool ok = d >= -slack;
             if (MASK) ok = ok && p >= st.lo[blk][hl] && p < st.hi[blk][hl];
             pass[blk][hl] = ok;
-            hit = hit || ok;
+            if (MASK) hit = hit || ok;
+            else dmax = fmaxf(dmax, d);
         }
-    if (!__any(hit)) return;
+    if (!MASK) hit = dmax >= -slack;
+    if (!wave_any(hit)) return;
     // append the passing cells (at most 64 per row block half)
 #pragma unroll
     for (int blk = 0; blk < MB; ++blk)
@@ -1129,18 +1231,38 @@ template <int B, bool MASK>
 __device__ __forceinline__ void scan32(const SearchArgs &a, const SearchArgs *ta, Wave32<B> &st,
                                        Queue32<B> *qu, int cb_begin, int cb_end)
 {
-    constexpr int KS = Cfg<B>::KS, PD = KS == 1 ? 4 : 2;
+    constexpr int MB = Cfg<B>::MB, KS = Cfg<B>::KS, PD = KS == 1 ? 4 : 2;
+    cb_begin = __builtin_amdgcn_readfirstlane(cb_begin);
+    cb_end = __builtin_amdgcn_readfirstlane(cb_end);
     if (cb_begin >= cb_end) return;
     const int lane = threadIdx.x & 63, col = lane & 31;
-    const auto *bbase = as_global((const half8_t *)a.Bm) + lane;
-    const auto *ubase = as_global(a.u) + col;
+    // scalar base + block offset, 32-bit lane offset
+    const auto *bbase = as_global(uniform_ptr((const half8_t *)a.Bm));
+    const auto *ubase = as_global(uniform_ptr(a.u));
+    const uint32_t lb = (uint32_t)lane, lu = (uint32_t)col;
     const int last = cb_end - 1;
     half8_t b0[KS], b1[KS], b2[KS], b3[KS];
     float u0, u1, u2 = 0.0f, u3 = 0.0f;
     auto load = [&](half8_t (&bq)[KS], float &uq, int c) {
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) bq[ks] = bbase[((int64_t)c * KS + ks) * 64];
-        uq = ubase[(int64_t)c * 32];
+        for (int ks = 0; ks < KS; ++ks) bq[ks] = (bbase + (int64_t)c * KS * 64)[lb + ks * 64];
+        uq = (ubase + (int64_t)c * 32)[lu];
+    };
+    // the cross terms of one column block (MB row blocks of 32 x 32)
+    auto mmab = [&](const half8_t (&bq)[KS], float16_t (&acc)[MB]) {
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+            for (int blk = 0; blk < MB; ++blk) {
+                float16_t z;
+                if (ks == 0) {
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) z[e] = 0.0f;
+                } else {
+                    z = acc[blk];
+                }
+                acc[blk] = mma32(st.af[blk][ks], bq[ks], z);
+            }
     };
     load(b0, u0, min(cb_begin + 0, last));
     load(b1, u1, min(cb_begin + 1, last));
@@ -1149,13 +1271,18 @@ __device__ __forceinline__ void scan32(const SearchArgs &a, const SearchArgs *ta
         load(b3, u3, min(cb_begin + 3, last));
     }
     int cb = cb_begin;
+    // the MFMAs of a block are issued before its fragments are reloaded
     auto step = [&](half8_t (&bq)[KS], float &uq, int i) {
-        half8_t bc[KS];
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) bc[ks] = bq[ks];
+        float16_t acc[MB];
+        mmab(bq, acc);
         const float uc = uq;
         load(bq, uq, min(cb + i + PD, last));
-        screen32<B, MASK>(a, ta, st, qu, bc, uc, cb + i);
+        screen32<B, MASK>(a, ta, st, qu, acc, uc, cb + i);
+    };
+    auto tail = [&](const half8_t (&bq)[KS], float uq, int i) {
+        float16_t acc[MB];
+        mmab(bq, acc);
+        screen32<B, MASK>(a, ta, st, qu, acc, uq, cb + i);
     };
     for (; cb + PD <= cb_end; cb += PD) {
         step(b0, u0, 0);
@@ -1165,10 +1292,10 @@ __device__ __forceinline__ void scan32(const SearchArgs &a, const SearchArgs *ta
             step(b3, u3, 3);
         }
     }
-    if (cb + 0 < cb_end) screen32<B, MASK>(a, ta, st, qu, b0, u0, cb + 0);
+    if (cb + 0 < cb_end) tail(b0, u0, 0);
     if constexpr (PD == 4) {
-        if (cb + 1 < cb_end) screen32<B, MASK>(a, ta, st, qu, b1, u1, cb + 1);
-        if (cb + 2 < cb_end) screen32<B, MASK>(a, ta, st, qu, b2, u2, cb + 2);
+        if (cb + 1 < cb_end) tail(b1, u1, 1);
+        if (cb + 2 < cb_end) tail(b2, u2, 2);
     }
 }
 
