@@ -649,6 +649,37 @@ __device__ __forceinline__ void mma_block(const WaveState<B> &st,
             }
 }
 
+// Append row block b's passing half cells (at most 64) to the wave's queue,
+// with their exact cross terms (each 64-term chunk is exact in FP32).
+template <int B>
+__device__ __forceinline__ void queue_rowblock(const SearchArgs *ta, WaveState<B> &st,
+                                               Queue16<B> *qu, int b, bool pass,
+                                               const float4_t (&accb)[Cfg<B>::NCH], uint32_t p)
+{
+    constexpr int NCH = Cfg<B>::NCH;
+    const int lane = threadIdx.x & 63, hl = lane >> 5;
+    const u64 ball = __ballot(pass);
+    if (ball == 0) return;
+    const uint32_t cnt = (uint32_t)__popcll(ball);
+    if (st.qn + cnt > (uint32_t)kQueue) flush_and_refresh16<B>(ta, st, qu);
+    if (pass) {
+        const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+            (uint32_t)(ball >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ball, 0u));
+        const uint32_t pos = st.qn + below;
+        const uint32_t isob = ((lane >> 4) & 1) * 4;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            int32_t cx = 0;
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) cx += (int32_t)accb[c][v];
+            qu->c[v][pos] = cx;
+        }
+        qu->p[pos] = p;
+        qu->lq[pos] = (uint32_t)(2 * b + hl) | (isob << 8);
+    }
+    st.qn += cnt;
+}
+
 // Screen the cross terms of column block cb; queue the passing half cells.
 template <int B, bool MASK>
 __device__ __forceinline__ void screen_acc(const SearchArgs *ta, WaveState<B> &st,
@@ -680,30 +711,8 @@ __device__ __forceinline__ void screen_acc(const SearchArgs *ta, WaveState<B> &s
     }
     if (!MASK) hit = dmax >= -slack;
     if (!wave_any(hit)) return;
-    // append the passing half cells (at most 64 per row block)
-    const uint32_t isob = ((lane >> 4) & 1) * 4;
 #pragma unroll
-    for (int b = 0; b < MW; ++b) {
-        const u64 ball = __ballot(pass[b]);
-        if (ball == 0) continue;
-        const uint32_t cnt = (uint32_t)__popcll(ball);
-        if (st.qn + cnt > (uint32_t)kQueue) flush_and_refresh16<B>(ta, st, qu);
-        if (pass[b]) {
-            const uint32_t below = __builtin_amdgcn_mbcnt_hi(
-                (uint32_t)(ball >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ball, 0u));
-            const uint32_t pos = st.qn + below;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                int32_t cx = 0;      // each 64-term chunk is exact in FP32
-#pragma unroll
-                for (int c = 0; c < NCH; ++c) cx += (int32_t)acc[b][c][v];
-                qu->c[v][pos] = cx;
-            }
-            qu->p[pos] = p;
-            qu->lq[pos] = (uint32_t)(2 * b + hl) | (isob << 8);
-        }
-        st.qn += cnt;
-    }
+    for (int b = 0; b < MW; ++b) queue_rowblock<B>(ta, st, qu, b, pass[b], acc[b], p);
 }
 
 template <int B, bool MASK>
@@ -758,12 +767,27 @@ __device__ __forceinline__ void screen_block_lds(const SearchArgs *ta, WaveState
     }
     if (!MASK) hit = dmax >= -slack;
     if (!wave_any(hit)) return;
-    frag_t bx[KS];
+    // exact chunk sums, exact screen and queue, one row block at a time
+    constexpr int NCH = C::NCH, KPC = KS / NCH;
+    const float slx = screen_slack<B>();
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) bx[ks] = lb[ks * 64 + lane];
-    float4_t accx[MW][C::NCH];
-    mma_block<B>(st, bx, accx);
-    screen_acc<B, MASK>(ta, st, qu, accx, u, cb);
+    for (int b = 0; b < MW; ++b) {
+        float4_t ax[NCH];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c)
+#pragma unroll
+            for (int kk = 0; kk < KPC; ++kk) {
+                const float4_t z = {0.f, 0.f, 0.f, 0.f};
+                ax[c] = mma(st.af[b][c * KPC + kk], lb[(c * KPC + kk) * 64 + lane], kk ? ax[c] : z);
+            }
+        float4_t sv = ax[0];
+#pragma unroll
+        for (int c = 1; c < NCH; ++c) sv += ax[c];
+        const float m = fmaxf(fmaxf(fabsf(sv[0]), fabsf(sv[1])), fmaxf(fabsf(sv[2]), fabsf(sv[3])));
+        bool h = fmaf(-st.T[b], u, m) >= -slx;
+        if (MASK) h = h && p >= st.lo[b] && p < st.hi[b];
+        queue_rowblock<B>(ta, st, qu, b, h, ax, p);
+    }
 }
 
 // Column blocks [cb_begin, cb_end) against the wave's A rows. The B
@@ -926,7 +950,7 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma(const SearchArgs *__rest
 // global->LDS loads, double-buffered, one barrier per stage) and each wave
 // screens its own group's ranges against them; blocks outside a wave's own
 // pools are skipped, blocks inside all of them skip the per-range mask.
-constexpr int kStage16 = 2;          // 16-column blocks per LDS stage
+constexpr int kStage16 = 3;          // 16-column blocks per LDS stage
 
 typedef __attribute__((address_space(3))) void lds_void;
 
@@ -967,7 +991,7 @@ __global__ __launch_bounds__(256, 2) void k_search_lds16(const SearchArgs *__res
         const SearchArgs *ta = tab + ia;
         const SearchArgs a = *ta;
         const WorkItem wi = a.items[item - base[ia]];
-        st.grp = wi.grp * 4 + (uint32_t)w;
+        st.grp = __builtin_amdgcn_readfirstlane(wi.grp) * 4 + (uint32_t)w;
         const frag_t *ap = (const frag_t *)a.A + (int64_t)st.grp * MW * KS * 64 + lane;
 #pragma unroll
         for (int b = 0; b < MW; ++b)
@@ -1005,10 +1029,11 @@ __global__ __launch_bounds__(256, 2) void k_search_lds16(const SearchArgs *__res
         ilo = __builtin_amdgcn_readfirstlane(ilo);
         ihi = __builtin_amdgcn_readfirstlane(ihi);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        const int cb0 = (int)(wi.c0 >> 4), cb1 = (int)(wi.c1 >> 4);
+        const int cb0 = __builtin_amdgcn_readfirstlane((int)(wi.c0 >> 4));
+        const int cb1 = __builtin_amdgcn_readfirstlane((int)(wi.c1 >> 4));
         const int nst = (cb1 - cb0 + SB - 1) / SB;
-        const auto *gB = as_global((const frag_t *)a.Bm);
-        const auto *gU = as_global(a.u);
+        const auto *gB = as_global(uniform_ptr((const frag_t *)a.Bm));
+        const auto *gU = as_global(uniform_ptr(a.u));
         auto stage_load = [&](int sidx, frag_t *dB, float *dU) {
             const int sb0 = cb0 + sidx * SB;
 #pragma unroll
