@@ -56,7 +56,7 @@ void mark_stage(void *self, int stage, int begin, hipStream_t s)
     fic_ctx *c = (fic_ctx *)self;
     hipEvent_t e = take_event(c);
     if (!e) return;
-    hipEventRecord(e, s);
+    (void)hipEventRecord(e, s);
     if (begin) {
         if (c->open_ev) c->spare.push_back(c->open_ev);
         c->open_ev = e;
@@ -178,14 +178,14 @@ const fic::BatchStreams *side_streams(fic_ctx *c)
     for (int q = 0; q < kSideStreams; ++q) {
         if (hipStreamCreateWithFlags(&b.side[q], hipStreamNonBlocking) != hipSuccess) break;
         if (hipEventCreateWithFlags(&b.join[q], hipEventDisableTiming) != hipSuccess) {
-            hipStreamDestroy(b.side[q]);
+            (void)hipStreamDestroy(b.side[q]);
             break;
         }
         b.ns = q + 1;
     }
     if (b.ns < kSideStreams) {
-        for (int q = 0; q < b.ns; ++q) { hipEventDestroy(b.join[q]); hipStreamDestroy(b.side[q]); }
-        hipEventDestroy(b.fork);
+        for (int q = 0; q < b.ns; ++q) { (void)hipEventDestroy(b.join[q]); (void)hipStreamDestroy(b.side[q]); }
+        (void)hipEventDestroy(b.fork);
         return nullptr;
     }
     c->side = b;
@@ -196,16 +196,16 @@ void drop_side_streams(fic_ctx *c)
 {
     if (c->side.ns == 0) return;
     for (int q = 0; q < c->side.ns; ++q) {
-        hipEventDestroy(c->side.join[q]);
-        hipStreamDestroy(c->side.side[q]);
+        (void)hipEventDestroy(c->side.join[q]);
+        (void)hipStreamDestroy(c->side.side[q]);
     }
-    hipEventDestroy(c->side.fork);
+    (void)hipEventDestroy(c->side.fork);
     c->side.ns = 0;
 }
 
 void drop_graphs(fic_ctx *c)
 {
-    for (auto &g : c->graphs) hipGraphExecDestroy(g.exec);
+    for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.exec);
     c->graphs.clear();
 }
 
@@ -287,12 +287,12 @@ fic_status fic_destroy(fic_ctx *ctx)
 {
     if (!ctx) return FIC_ERR_INVALID_ARG;
     if (ctx->device >= 0) {
-        for (auto &r : ctx->recs) { hipEventDestroy(r.a); hipEventDestroy(r.b); }
-        for (auto e : ctx->spare) hipEventDestroy(e);
-        if (ctx->open_ev) hipEventDestroy(ctx->open_ev);
+        for (auto &r : ctx->recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+        for (auto e : ctx->spare) (void)hipEventDestroy(e);
+        if (ctx->open_ev) (void)hipEventDestroy(ctx->open_ev);
         drop_graphs(ctx);
         drop_side_streams(ctx);
-        if (ctx->cap) hipStreamDestroy(ctx->cap);
+        if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
     }
     delete ctx;
     return FIC_OK;
@@ -463,10 +463,10 @@ fic_status fic_encode_pifs_batch(fic_ctx *ctx, int32_t n_images, const fic_image
         hipError_t e3 = hipErrorUnknown;
         if (e == hipSuccess && e2 == hipSuccess && graph)
             e3 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        if (graph) hipGraphDestroy(graph);
+        if (graph) (void)hipGraphDestroy(graph);
         if (e3 != hipSuccess) return FIC_ERR_DEVICE;
         if (ctx->graphs.size() >= kMaxGraphs) {
-            hipGraphExecDestroy(ctx->graphs.front().exec);
+            (void)hipGraphExecDestroy(ctx->graphs.front().exec);
             ctx->graphs.erase(ctx->graphs.begin());
         }
         ctx->graphs.push_back({std::move(key), exec});

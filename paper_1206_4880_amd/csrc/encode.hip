@@ -690,7 +690,7 @@ __device__ __forceinline__ void screen_acc(const SearchArgs *ta, WaveState<B> &s
     using C = Cfg<B>;
     constexpr int MW = C::MB, NCH = C::NCH;
     const float slack = screen_slack<B>();
-    const int lane = threadIdx.x & 63, hl = lane >> 5, col = lane & 15;
+    const int lane = threadIdx.x & 63, col = lane & 15;
     const uint32_t p = (uint32_t)cb * 16 + col;
     bool pass[MW];
     bool hit = false;
@@ -1660,7 +1660,8 @@ hipError_t prep_b(const EncodePlan &p, const uint8_t *img, const uint32_t *perm,
     hipLaunchKernelGGL(k_chunk_span, dim3(blocks_for(p.NC, th)), dim3(th), 0, s, grp, p.IG, p.NC,
                        (uint32_t)p.chunk, chunkcnt, chunkfill);
     // exclusive scan of the per-chunk counts; the total is the item count
-    scan_u32(chunkcnt, p.NC, ctr + 1, w + p.off_scan, s);
+    const hipError_t se = scan_u32(chunkcnt, p.NC, ctr + 1, w + p.off_scan, s);
+    if (se != hipSuccess) return se;
     SearchArgs a;
     a.A = A; a.Bm = Bm; a.u = u; a.eps = eps; a.sdd = sdd; a.dom = dom; a.rs = rs; a.grp = grp;
     a.items = items; a.n_items = ctr + 1; a.keys = keys; a.shift = p.shift;

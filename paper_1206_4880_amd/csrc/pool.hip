@@ -159,12 +159,6 @@ __global__ __launch_bounds__(kSortThreads) void k_digit_scatter(
     }
 }
 
-__global__ void k_iota(uint32_t *v, int64_t n)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) v[i] = (uint32_t)i;
-}
-
 // Order-preserving integer image of an fp64 value.
 __device__ inline u64 fd_bits(double x)
 {
@@ -289,7 +283,8 @@ hipError_t radix_sort_pairs(u64 *keys, uint32_t *vals, int64_t n, int key_bits, 
     for (int pass = 0; pass < passes; ++pass) {
         const int shift = pass * 8;
         hipLaunchKernelGGL(k_digit_hist, dim3(nb), dim3(kSortThreads), 0, s, ka, n, shift, hist, nb);
-        scan_u32(hist, (int64_t)nb * 256, nullptr, scanws, s);
+        const hipError_t se = scan_u32(hist, (int64_t)nb * 256, nullptr, scanws, s);
+        if (se != hipSuccess) return se;
         hipLaunchKernelGGL(k_digit_scatter, dim3(nb), dim3(kSortThreads), 0, s, ka, va, kb, vb, n,
                            shift, hist, nb);
         u64 *tk = ka; ka = kb; kb = tk;
