@@ -64,7 +64,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-kernel comparison")
     ap.add_argument("--counters", action="store_true",
-                    help="one extra untimed step with survivor counters")
+                    help="one extra untimed step with survivor counters (the default for "
+                         "single-image workloads)")
+    ap.add_argument("--no-counters", action="store_true",
+                    help="skip the untimed survivor-counter step")
     ap.add_argument("--only", default=None,
                     help="run only this job per step (e.g. 'exhaustive'), for profiling")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -152,6 +155,25 @@ def oracle_rate(img_np, b, t, tol, pool_sizes, D, seconds, what):
             "kind": "oracle",
             "sample": "%s: %d of %d ranges (%d pair evaluations, %.1f s)"
                       % (what, count, R, cpu_pairs, cpu_s)}
+
+
+def oracle_single_thread():
+    """The oracle on one host thread: the whole 64x64 exhaustive encode
+    (8x8 ranges, step 1: 64 ranges x 2401 domains x 8), pairs/s per core."""
+    import oracle
+    from synth import workload_images
+    oracle.build(force=False)
+    img = workload_images("fbm64_b8t1")
+    pairs = 64 * 2401 * 8
+    best = None
+    for _ in range(3):
+        t0 = time.perf_counter()
+        oracle.encode(img, 8, 1, tol=None, nthreads=1)
+        dt = time.perf_counter() - t0
+        best = dt if best is None else min(best, dt)
+    return {"value": round(pairs / best, 1), "unit": "pair evals/s per core", "cores": 1,
+            "sample": "fbm64_b8t1 exhaustive, all 64 ranges (%d pair evaluations, best of 3: "
+                      "%.3f s)" % (pairs, best)}
 
 
 def search_kernel_name(b):
@@ -315,7 +337,7 @@ def bench_image(args, fic, wl, img_np):
                 fic.fic.make_geom(H, W, b, t)))), 3)} for (b, t) in sorted(set((b, t) for (b, t, _) in jobs))},
     }
 
-    if args.counters:
+    if args.counters or not args.no_counters:
         cnt = torch.zeros(4, dtype=torch.int64, device=dev)
         ctx.set_counters(cnt)
         step()
@@ -350,6 +372,7 @@ def bench_image(args, fic, wl, img_np):
         out["cpu_baseline"] = oracle_rate(
             img_np, bd, td, told, sizes[dom], D[(bd, td)], args.cpu_seconds,
             "%s, %s" % (wl.name, job_label(bd, td, told, multi)))
+        out["cpu_baseline"]["single_thread"] = oracle_single_thread()
     return out
 
 
