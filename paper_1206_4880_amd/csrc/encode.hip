@@ -506,7 +506,12 @@ __global__ __launch_bounds__(256) void k_item_bases(const SearchArgs *__restrict
 // wave's best keys (in LDS) take an LDS atomic minimum, and the refreshed
 // thresholds come back through LDS. Fitting a passing cell in place would run
 // the exact int64 fit on the whole wave for the few lanes that passed.
-constexpr int kQueue = 256;          // queued cells per wave (flushed with > 3 waves' worth)
+constexpr int kQueue = 256;          // queued cells per wave (capacity)
+// At 8x8, a block that leaves a wave's worth of cells queued flushes them at
+// once: every flush publishes the wave's best keys, takes the other waves',
+// and tightens the thresholds (narrow pools pass many cells early). At 4x4
+// and 16x16 the extra flushes cost more than they save.
+constexpr int kFlushAt = 64;
 
 template <class T> __device__ __forceinline__ const __attribute__((address_space(1))) T *
 as_global(const T *p)
@@ -560,7 +565,8 @@ template <int B> struct WaveState {
 // all rounds are issued before the first fit, so their latency is paid once
 // per flush; the range constants come from LDS.
 template <int B>
-__device__ __noinline__ void flush16(const SearchArgs *ta, uint32_t nq, Queue16<B> *qu)
+__device__ __noinline__ void flush16(const SearchArgs *ta, uint32_t nq, Queue16<B> *qu,
+                                     uint32_t grp)
 {
     constexpr int n = Cfg<B>::n, GR = Cfg<B>::GR, RQ = kQueue / 64;
     const int lane = threadIdx.x & 63;
@@ -609,7 +615,12 @@ __device__ __noinline__ void flush16(const SearchArgs *ta, uint32_t nq, Queue16<
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     if (lane < GR) {
-        const u64 bk = qu->best[lane];
+        // publish the wave's best keys and take what other waves on the same
+        // ranges (other column chunks) have found
+        u64 bk = qu->best[lane];
+        const u64 g = atomicMin(&a.keys[(int64_t)grp * GR + lane], bk);
+        bk = g < bk ? g : bk;
+        qu->best[lane] = bk;
         qu->T[lane] = bk == kNoKey ? 0.0f : screen_t_b<B>(qu->srr[lane], (int64_t)(bk >> a.shift));
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -621,7 +632,7 @@ __device__ __forceinline__ void flush_and_refresh16(const SearchArgs *ta, WaveSt
 {
     constexpr int MW = Cfg<B>::MB;
     const int hl = (threadIdx.x >> 5) & 1;
-    flush16<B>(ta, st.qn, qu);
+    flush16<B>(ta, st.qn, qu, st.grp);
     st.survivors += (threadIdx.x & 63) == 0 ? 4ull * st.qn : 0ull;
     st.qn = 0;
 #pragma unroll
@@ -713,6 +724,7 @@ __device__ __forceinline__ void screen_acc(const SearchArgs *ta, WaveState<B> &s
     if (!wave_any(hit)) return;
 #pragma unroll
     for (int b = 0; b < MW; ++b) queue_rowblock<B>(ta, st, qu, b, pass[b], acc[b], p);
+    if (st.qn >= (uint32_t)kFlushAt) flush_and_refresh16<B>(ta, st, qu);
 }
 
 template <int B, bool MASK>
@@ -1127,7 +1139,8 @@ __device__ __forceinline__ float max8(const float16_t &a, int base)
 // Fit the nq queued cells (one per lane and round of 64) as flush16 does,
 // over all 8 isometries of each cell.
 template <int B>
-__device__ __noinline__ void flush32(const SearchArgs *ta, uint32_t nq, Queue32<B> *qu)
+__device__ __noinline__ void flush32(const SearchArgs *ta, uint32_t nq, Queue32<B> *qu,
+                                     uint32_t grp)
 {
     constexpr int n = Cfg<B>::n, GR = Cfg<B>::GR, RQ = kQueue / 64;
     const int lane = threadIdx.x & 63;
@@ -1176,7 +1189,11 @@ __device__ __noinline__ void flush32(const SearchArgs *ta, uint32_t nq, Queue32<
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     if (lane < GR) {
-        const u64 bk = qu->best[lane];
+        // publish the wave's best keys and take what other waves found
+        u64 bk = qu->best[lane];
+        const u64 g = atomicMin(&a.keys[(int64_t)grp * GR + lane], bk);
+        bk = g < bk ? g : bk;
+        qu->best[lane] = bk;
         qu->T[lane] = bk == kNoKey ? 0.0f : screen_t(qu->srr[lane], (int64_t)(bk >> a.shift));
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -1188,7 +1205,7 @@ __device__ __forceinline__ void flush_and_refresh(const SearchArgs *ta, Wave32<B
 {
     constexpr int MB = Cfg<B>::MB;
     const int h = (threadIdx.x >> 5) & 1;
-    flush32<B>(ta, st.qn, qu);
+    flush32<B>(ta, st.qn, qu, st.grp);
     st.survivors += (threadIdx.x & 63) == 0 ? 8ull * st.qn : 0ull;
     st.qn = 0;
 #pragma unroll
