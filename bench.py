@@ -34,10 +34,16 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "search_mfma_fbm1024_traffic.json"
 
 
 def kernel_source_hash():
+    """Hash of the search kernels' code with comments and layout removed, so
+    that the traffic record stays valid across comment-only edits."""
+    import re
     h = hashlib.sha256()
     for f in ("encode.hip", "fic_internal.h"):
-        with open(os.path.join(ROOT, "paper_1206_4880_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1206_4880_amd", "csrc", f)) as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 

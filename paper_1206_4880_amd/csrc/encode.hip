@@ -15,12 +15,20 @@
 //                items, of one image or of all images of a batch. The
 //                group's A rows stay in VGPRs; each MR-column block costs
 //                MB*KS MFMAs, giving C''' = sum (r-rhat)(D-dhat) exactly in
-//                FP32, and Srd' = n*C''' - delta*eps exactly. A few FP32
-//                instructions per output tile screen out pairs whose
-//                continuous optimum cannot reach the range's best F; passing
-//                cells queue in LDS and get the exact int64 fit a wave's worth
-//                at a time; packed (F, domain, isometry) keys meet in LDS and
-//                then in a global atomicMin.
+//                FP32 (64-term chunks), and Srd' = n*C''' - delta*eps
+//                exactly. A few FP32 instructions per output tile screen out
+//                pairs whose continuous optimum cannot reach the range's best
+//                F (16x16 ranges screen one FP32 sum against a threshold
+//                lowered by its rounding bound and recompute the exact chunks
+//                only for blocks that pass); passing cells queue in LDS and
+//                get the exact int64 fit a wave's worth at a time; packed
+//                (F, domain, isometry) keys meet in LDS, and each flush
+//                exchanges them with the global keys, so waves on other
+//                column chunks of the same ranges tighten each other's
+//                thresholds.
+// VALU and MFMA instruction time add up on a SIMD, so the hot loops are
+// written for few VALU instructions per MFMA (scalar addressing, one compare
+// per block), not to hide them.
 //   finalize     recompute the winner exactly from the image, write fic_code.
 // Plain path (FIC_KERNEL_PLAIN): one thread per (range, domain, isometry),
 // integer cross term from the 2x2-sum image, exact fit, the same keys.
@@ -529,7 +537,7 @@ template <class T> __device__ __forceinline__ const T *uniform_ptr(const T *p)
     return (const T *)(((uint64_t)hi << 32) | lo);
 }
 
-// True when any lane's flag is set; a scalar test of the lane mask.
+// True when any lane's flag is set (the wave's ballot is not zero).
 __device__ __forceinline__ bool wave_any(bool x)
 {
     return __builtin_amdgcn_ballot_w64(x) != 0;
