@@ -138,6 +138,14 @@ SMALL = [
     ("flat 64 8/1 pool", lambda: np.full((64, 64), 200, np.uint8), 8, 1, 0.05),
     ("minimal 16x16 8/1", lambda: fbm(16, 0.5, 3), 8, 1, None),
     ("tol 0: empty pools", lambda: fbm(64, 0.3, 12), 8, 2, 0.0),
+    # 0/255 pixels: the largest centred operands, partial sums near 2^26 at
+    # 16x16 (the one-accumulator screen rounds there), many near-ties
+    ("binary 128 16/1", lambda: (np.random.default_rng(31).integers(0, 2, (128, 128)) * 255).astype(np.uint8),
+     16, 1, None),
+    ("binary 128 16/2 pool", lambda: (np.random.default_rng(32).integers(0, 2, (128, 128)) * 255).astype(np.uint8),
+     16, 2, 0.05),
+    ("binary 64 8/1", lambda: (np.random.default_rng(33).integers(0, 2, (64, 64)) * 255).astype(np.uint8),
+     8, 1, None),
 ]
 
 
