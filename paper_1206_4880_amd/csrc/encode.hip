@@ -607,18 +607,23 @@ __device__ __noinline__ void flush16(const SearchArgs *ta, uint32_t nq, Queue16<
         const uint32_t e = (uint32_t)(r * 64 + lane);
         if (e < nq) {
             const uint32_t ls = lqe[r] & 255u, isob = lqe[r] >> 8;
-            const int64_t srr = qu->srr[ls];
-            const int32_t delta = qu->delta[ls];
-            u64 cand = kNoKey;
+            const double base = 4096.0 * (double)qu->srr[ls];
+            const double ne = (double)qu->delta[ls] * (double)ep[r];
+            const double dd = (double)sd[r];
+            const float inv = __builtin_amdgcn_rcpf((float)dd);
+            // the half cell's 4 isometries: lowest F, then lowest isometry
+            double fb = 0.0;
+            int vb = 0;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int64_t srd = (int64_t)n * qu->c[v][e] - (int64_t)delta * ep[r];
-                int k;
-                const int64_t f = fit_f(srr, srd, sd[r], k);
-                const u64 key = pack_key(f, dm[r], (int)isob + v, a.shift);
-                cand = key < cand ? key : cand;
+                const double rd = (double)n * (double)qu->c[v][e] - ne;   // exact integers
+                const double f = fit_f_d(base, rd, dd, inv);
+                if (v == 0 || f < fb) {
+                    fb = f;
+                    vb = v;
+                }
             }
-            atomicMin(&qu->best[ls], cand);
+            atomicMin(&qu->best[ls], pack_key((int64_t)fb, dm[r], (int)isob + vb, a.shift));
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -1181,18 +1186,23 @@ __device__ __noinline__ void flush32(const SearchArgs *ta, uint32_t nq, Queue32<
         const uint32_t e = (uint32_t)(r * 64 + lane);
         if (e < nq) {
             const uint32_t ls = le[r];
-            const int64_t srr = qu->srr[ls];
-            const int32_t delta = qu->delta[ls];
-            u64 cand = kNoKey;
+            const double base = 4096.0 * (double)qu->srr[ls];
+            const double ne = (double)qu->delta[ls] * (double)ep[r];
+            const double dd = (double)sd[r];
+            const float inv = __builtin_amdgcn_rcpf((float)dd);
+            // the cell's 8 isometries: lowest F, then lowest isometry
+            double fb = 0.0;
+            int qb = 0;
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
-                const int64_t srd = (int64_t)n * (int64_t)qu->c[q][e] - (int64_t)delta * ep[r];
-                int k;
-                const int64_t f = fit_f(srr, srd, sd[r], k);
-                const u64 key = pack_key(f, dm[r], q, a.shift);
-                cand = key < cand ? key : cand;
+                const double rd = (double)n * (double)qu->c[q][e] - ne;   // exact integers
+                const double f = fit_f_d(base, rd, dd, inv);
+                if (q == 0 || f < fb) {
+                    fb = f;
+                    qb = q;
+                }
             }
-            atomicMin(&qu->best[ls], cand);
+            atomicMin(&qu->best[ls], pack_key((int64_t)fb, dm[r], qb, a.shift));
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");

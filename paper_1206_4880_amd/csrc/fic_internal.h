@@ -138,6 +138,34 @@ __host__ __device__ inline int64_t fit_f(int64_t srr, int64_t srd, int64_t sdd, 
     return 4096 * srr - 128 * (int64_t)k * srd + (int64_t)k * k * sdd;
 }
 
+// F of the best contrast index, as fit_f, for the queue flushes (many fits
+// per call), in fp64: every term of F is an integer below 2^53 for n <= 256
+// (|Srd'| <= sqrt(Srr' Sdd')), so each fma is exact. base = 4096 Srr', rd =
+// Srd', dd = Sdd', inv = an fp32 reciprocal of Sdd'. The vertex
+// v = 64 Srd'/Sdd' it gives is off by far less than 1/2, so the integer
+// minimiser over [-16, 15] is among round(v) - 1, round(v), round(v) + 1;
+// those three are compared exactly, ties to the smaller |k| (fit_f's rule).
+__device__ inline double fit_f_d(double base, double rd, double dd, float inv)
+{
+    if (dd <= 0.0) return base;
+    const float v = 64.0f * (float)rd * inv;
+    int kr = (int)rintf(fminf(fmaxf(v, -17.0f), 16.0f));
+    kr = kr < -15 ? -15 : (kr > 14 ? 14 : kr);     // candidates kr - 1 .. kr + 1 in [-16, 15]
+    double best = 0.0;
+    int babs = 0;
+#pragma unroll
+    for (int j = -1; j <= 1; ++j) {
+        const int k = kr + j;
+        const double f = fma((double)(k * k), dd, fma(-128.0 * (double)k, rd, base));
+        const int a = k < 0 ? -k : k;
+        if (j == -1 || f < best || (f == best && a < babs)) {
+            best = f;
+            babs = a;
+        }
+    }
+    return best;
+}
+
 // Packed search key: (F << shift) | (domain << 3) | isometry. Its unsigned
 // minimum is the lexicographic minimum of (F, domain, isometry).
 __host__ __device__ inline u64 pack_key(int64_t f, uint32_t dom, int q, int shift)
