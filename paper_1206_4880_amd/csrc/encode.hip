@@ -1057,20 +1057,33 @@ __global__ __launch_bounds__(256, 2) void k_search_lds16(const SearchArgs *__res
         const int cb0 = __builtin_amdgcn_readfirstlane((int)(wi.c0 >> 4));
         const int cb1 = __builtin_amdgcn_readfirstlane((int)(wi.c1 >> 4));
         const int nst = (cb1 - cb0 + SB - 1) / SB;
+        // the wave's blocks: [lb0, lb1) meet its pools, [ib0, ib1) lie inside
+        // all of them (no per-range mask)
+        const int lb0 = max(cb0, (int)(wlo >> 4)), lb1 = min(cb1, (int)((whi + 15u) >> 4));
+        const int ib0 = (int)((ilo + 15u) >> 4), ib1 = (int)(ihi >> 4);
+        st.screened += (u64)(lb1 > lb0 ? lb1 - lb0 : 0) * 16 * GR * 8;
         const auto *gB = as_global(uniform_ptr((const frag_t *)a.Bm));
         const auto *gU = as_global(uniform_ptr(a.u));
+        // each wave loads fragments w, w + 4, ... of the stage; blocks past
+        // the item reload its last block (in bounds, never read), so the
+        // loads need no branches
+        static_assert(FR % 4 == 0, "stage fragments split over 4 waves");
         auto stage_load = [&](int sidx, frag_t *dB, float *dU) {
             const int sb0 = cb0 + sidx * SB;
 #pragma unroll
-            for (int f = w; f < FR; f += 4)
-                if (sb0 + f / KS < cb1)
-                    __builtin_amdgcn_global_load_lds(
-                        (const __attribute__((address_space(1))) void *)(gB + ((int64_t)sb0 * KS + f) * 64 + lane),
-                        (lds_void *)(dB + f * 64), 16, 0, 0);
-            if (w == 0 && lane < SB * 16 && sb0 + lane / 16 < cb1)
+            for (int f = 0; f < FR / 4; ++f) {
+                const int fr = w + 4 * f;
+                const int blk = min(sb0 + fr / KS, cb1 - 1);
                 __builtin_amdgcn_global_load_lds(
-                    (const __attribute__((address_space(1))) void *)(gU + (int64_t)sb0 * 16 + lane),
+                    (const __attribute__((address_space(1))) void *)(gB + ((int64_t)blk * KS + fr % KS) * 64 + lane),
+                    (lds_void *)(dB + fr * 64), 16, 0, 0);
+            }
+            if (w == 0 && lane < SB * 16) {
+                const int blk = min(sb0 + lane / 16, cb1 - 1);
+                __builtin_amdgcn_global_load_lds(
+                    (const __attribute__((address_space(1))) void *)(gU + (int64_t)blk * 16 + (lane & 15)),
                     (lds_void *)dU, 4, 0, 0);
+            }
         };
         if (nst > 0) stage_load(0, sB0, sU0);
         __builtin_amdgcn_s_waitcnt(0);
@@ -1082,11 +1095,9 @@ __global__ __launch_bounds__(256, 2) void k_search_lds16(const SearchArgs *__res
 #pragma unroll
             for (int j = 0; j < SB; ++j) {
                 const int cb = cb0 + sidx * SB + j;
-                const uint32_t c0 = (uint32_t)cb * 16;
-                if (cb >= cb1 || c0 >= whi || c0 + 16 <= wlo) continue;
+                if (cb < lb0 || cb >= lb1) continue;
                 const float u = cU[j * 16 + col];
-                st.screened += 16 * GR * 8;
-                if (c0 >= ilo && c0 + 16 <= ihi)
+                if (cb >= ib0 && cb < ib1)
                     screen_block_lds<B, false>(ta, st, qu, cB + j * KS * 64, u, cb);
                 else
                     screen_block_lds<B, true>(ta, st, qu, cB + j * KS * 64, u, cb);
