@@ -110,7 +110,7 @@ const char *fic_status_string(fic_status s);
 
 /* Optional instrumentation: when `counters` (dev, 4 x uint64, zeroed by the
    caller) is set, the search kernels add
-     [0] pair evaluations screened, [1] pairs passed to the exact int64 path,
+     [0] pair evaluations screened, [1] pairs passed to the exact fit,
      [2] work items processed,      [3] exact seeds evaluated.
    NULL (the default) disables the adds. */
 fic_status fic_set_counters(fic_ctx *ctx, uint64_t *counters /* dev */);

@@ -21,7 +21,7 @@
 //                F (16x16 ranges screen one FP32 sum against a threshold
 //                lowered by its rounding bound and recompute the exact chunks
 //                only for blocks that pass); passing cells queue in LDS and
-//                get the exact int64 fit a wave's worth at a time; packed
+//                get the exact fit a wave's worth at a time; packed
 //                (F, domain, isometry) keys meet in LDS, and each flush
 //                exchanges them with the global keys, so waves on other
 //                column chunks of the same ranges tighten each other's
@@ -513,7 +513,7 @@ __global__ __launch_bounds__(256) void k_item_bases(const SearchArgs *__restrict
 // them exactly (out of line, so the hot loop stays small and unrolled), the
 // wave's best keys (in LDS) take an LDS atomic minimum, and the refreshed
 // thresholds come back through LDS. Fitting a passing cell in place would run
-// the exact int64 fit on the whole wave for the few lanes that passed.
+// the exact fit on the whole wave for the few lanes that passed.
 constexpr int kQueue = 256;          // queued cells per wave (capacity)
 // At 8x8, a block that leaves a wave's worth of cells queued flushes them at
 // once: every flush publishes the wave's best keys, takes the other waves',
