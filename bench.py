@@ -270,30 +270,38 @@ def bench_image(args, fic, wl, img_np):
     pool_ms = {}
     job_ms = [dict() for _ in jobs]
     search_ms = [[] for _ in jobs]
+    enc_steps = [[] for _ in jobs]        # per step: the job's whole encode, ms
     pooled_jobs = [j for j in jobs if j[2] is not None]
     for s in range(args.steps):
         chunk = recs[s * per_step:(s + 1) * per_step]
+        cls_s, pool_s = {}, {}
         for k in range(n_cls):
             cls_ms[geos[k // 2]] += chunk[k][1] / args.steps
+            cls_s[geos[k // 2]] = cls_s.get(geos[k // 2], 0.0) + chunk[k][1]
         for k in range(n_pool):
             pool_ms[pooled_jobs[k]] = pool_ms.get(pooled_jobs[k], 0.0) + \
                 chunk[n_cls + k][1] / args.steps
+            pool_s[pooled_jobs[k]] = chunk[n_cls + k][1]
         ji = -1
+        job_s = [0.0 for _ in jobs]
         for (name, ms) in chunk[n_cls + n_pool:]:
             if name == "range_prep":
                 ji += 1
             job_ms[ji][name] = job_ms[ji].get(name, 0.0) + ms / args.steps
+            job_s[ji] += ms
             if name == "search":
                 search_ms[ji].append(ms)
+        for i, (b, t, tol) in enumerate(jobs):
+            # a pooled job also needs its classification and its pool
+            extra = cls_s[(b, t)] + pool_s[(b, t, tol)] if tol is not None else 0.0
+            enc_steps[i].append(job_s[i] + extra)
 
+    # encode s/image and search rate: medians over the timed steps
     encode_s, job_rate = {}, {}
     for i, (b, t, tol) in enumerate(jobs):
-        enc_ms = sum(job_ms[i].values())
-        if tol is not None:   # a pooled job also needs its classification and its pool
-            enc_ms += cls_ms[(b, t)] + pool_ms[(b, t, tol)]
         lab = job_label(b, t, tol, multi)
-        encode_s[lab] = round(enc_ms / 1e3, 6)
-        job_rate[lab] = pairs[i] / (float(np.mean(search_ms[i])) / 1e3)
+        encode_s[lab] = round(float(np.median(enc_steps[i])) / 1e3, 6)
+        job_rate[lab] = pairs[i] / (float(np.median(search_ms[i])) / 1e3)
 
     # roofline of the dominant kernel: the search launch that takes longest
     dom = max(range(len(jobs)), key=lambda i: np.mean(search_ms[i]))
