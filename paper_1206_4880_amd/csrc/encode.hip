@@ -515,6 +515,8 @@ __global__ __launch_bounds__(256) void k_item_bases(const SearchArgs *__restrict
 // thresholds come back through LDS. Fitting a passing cell in place would run
 // the exact fit on the whole wave for the few lanes that passed.
 constexpr int kQueue = 256;          // queued cells per wave (capacity)
+// 16x16 ranges pass few cells: half the capacity leaves LDS for wider stages
+template <int B> constexpr int queue16_cap() { return B == 16 ? 128 : kQueue; }
 // At 8x8, a block that leaves a wave's worth of cells queued flushes them at
 // once: every flush publishes the wave's best keys, takes the other waves',
 // and tightens the thresholds (narrow pools pass many cells early). At 4x4
@@ -548,9 +550,9 @@ __device__ __forceinline__ bool wave_any(bool x)
 // the 8 isometries. Lane l of a tile sees column l%16 against range
 // 2b + l/32 under isometries 4*((l/16)%2) .. +3, i.e. half of a cell.
 template <int B> struct Queue16 {
-    int32_t c[4][kQueue];            // exact cross terms of the half cell
-    uint32_t p[kQueue];              // column
-    uint32_t lq[kQueue];             // range within the group | isometry base << 8
+    int32_t c[4][queue16_cap<B>()];  // exact cross terms of the half cell
+    uint32_t p[queue16_cap<B>()];    // column
+    uint32_t lq[queue16_cap<B>()];   // range within the group | isometry base << 8
     u64 best[Cfg<B>::GR];            // best keys of the wave's ranges
     float T[Cfg<B>::GR];             // their thresholds
     int64_t srr[Cfg<B>::GR];         // their Srr'
@@ -576,7 +578,7 @@ template <int B>
 __device__ __noinline__ void flush16(const SearchArgs *ta, uint32_t nq, Queue16<B> *qu,
                                      uint32_t grp)
 {
-    constexpr int n = Cfg<B>::n, GR = Cfg<B>::GR, RQ = kQueue / 64;
+    constexpr int n = Cfg<B>::n, GR = Cfg<B>::GR, RQ = queue16_cap<B>() / 64;
     const int lane = threadIdx.x & 63;
     const SearchArgs a = *ta;
     const auto *gsdd = as_global(a.sdd);
@@ -685,7 +687,7 @@ __device__ __forceinline__ void queue_rowblock(const SearchArgs *ta, WaveState<B
     const u64 ball = __ballot(pass);
     if (ball == 0) return;
     const uint32_t cnt = (uint32_t)__popcll(ball);
-    if (st.qn + cnt > (uint32_t)kQueue) flush_and_refresh16<B>(ta, st, qu);
+    if (st.qn + cnt > (uint32_t)queue16_cap<B>()) flush_and_refresh16<B>(ta, st, qu);
     if (pass) {
         const uint32_t below = __builtin_amdgcn_mbcnt_hi(
             (uint32_t)(ball >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ball, 0u));
@@ -975,7 +977,7 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma(const SearchArgs *__rest
 // global->LDS loads, double-buffered, one barrier per stage) and each wave
 // screens its own group's ranges against them; blocks outside a wave's own
 // pools are skipped, blocks inside all of them skip the per-range mask.
-constexpr int kStage16 = 3;          // 16-column blocks per LDS stage
+constexpr int kStage16 = 4;          // 16-column blocks per LDS stage
 
 typedef __attribute__((address_space(3))) void lds_void;
 
