@@ -220,7 +220,7 @@ def test_workload_1024(fic, orc, tol):
     assert_codes(mf, ref, sel=sel, what="1024 tol=%s" % tol)
 
 
-@pytest.mark.parametrize("job", [(16, 4, 0.05), (8, 2, 0.05)])
+@pytest.mark.parametrize("job", [(16, 4, 0.05), (8, 2, 0.05), (16, 4, None)])
 def test_workload_2048(fic, orc, job):
     from synth import workload_images
     img = workload_images("fbm2048_twolevel")
