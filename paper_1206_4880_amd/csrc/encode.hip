@@ -201,9 +201,39 @@ __global__ __launch_bounds__(256) void k_range_prep(
     }
 }
 
+// Pair sums of the 2B bytes at p: pk[j] holds p[4j] + p[4j+1] in its low
+// and p[4j+2] + p[4j+3] in its high 16 bits. Aligned dword loads (one more
+// than the span) and byte funnel shifts replace 2B byte loads; where those
+// words would reach outside the image [begin, end) the bytes are read one by
+// one.
+template <int B>
+__device__ __forceinline__ void pair_sums(const uint8_t *p, const uint8_t *begin,
+                                          const uint8_t *end, uint32_t (&pk)[B / 2])
+{
+    constexpr int NW = B / 2;                        // 4-byte words in 2B bytes
+    const uintptr_t a = (uintptr_t)p & ~(uintptr_t)3;
+    const int sh = (int)((uintptr_t)p & 3);
+    if (a >= (uintptr_t)begin && a + 4 * (NW + 1) <= (uintptr_t)end) {
+        const uint32_t *w = (const uint32_t *)a;
+        uint32_t r[NW + 1];
+#pragma unroll
+        for (int j = 0; j <= NW; ++j) r[j] = w[j];
+#pragma unroll
+        for (int j = 0; j < NW; ++j) {
+            const uint32_t x = __builtin_amdgcn_alignbyte(r[j + 1], r[j], (uint32_t)sh);
+            pk[j] = (x & 0x00ff00ffu) + ((x >> 8) & 0x00ff00ffu);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < NW; ++j)
+            pk[j] = (uint32_t)(p[4 * j] + p[4 * j + 1]) |
+                    ((uint32_t)(p[4 * j + 2] + p[4 * j + 3]) << 16);
+    }
+}
+
 template <int B>
 __global__ __launch_bounds__(256) void k_domain_prep(
-    const uint8_t *__restrict__ img, int32_t pitch, int32_t dcols, int32_t t,
+    const uint8_t *__restrict__ img, int64_t img_bytes, int32_t pitch, int32_t dcols, int32_t t,
     const uint32_t *__restrict__ perm, int64_t D, int64_t Dp, _Float16 *__restrict__ Bm,
     float *__restrict__ u, int32_t *__restrict__ eps, int64_t *__restrict__ sdd,
     uint32_t *__restrict__ dom)
@@ -221,9 +251,17 @@ __global__ __launch_bounds__(256) void k_domain_prep(
     int v[B];
     int64_t rs1 = 0, rs2 = 0;
     const uint8_t *q = img + (int64_t)(y + 2 * i) * pitch + x;
+    uint32_t p0[B / 2], p1[B / 2];
+    pair_sums<B>(q, img, img + img_bytes, p0);
+    pair_sums<B>(q + pitch, img, img + img_bytes, p1);
+#pragma unroll
+    for (int j = 0; j < B / 2; ++j) {
+        const uint32_t s2 = p0[j] + p1[j];           // two 2x2 sums, <= 1020 each
+        v[2 * j] = valid ? (int)(s2 & 0xffffu) : 0;
+        v[2 * j + 1] = valid ? (int)(s2 >> 16) : 0;
+    }
 #pragma unroll
     for (int e = 0; e < B; ++e) {
-        v[e] = valid ? (q[2 * e] + q[2 * e + 1] + q[pitch + 2 * e] + q[pitch + 2 * e + 1]) : 0;
         rs1 += v[e];
         rs2 += v[e] * v[e];
     }
@@ -1697,8 +1735,9 @@ hipError_t prep_b(const EncodePlan &p, const uint8_t *img, const uint32_t *perm,
                        rs);
     trace(tr, FIC_STAGE_RANGE_PREP, 0, s);
     trace(tr, FIC_STAGE_DOMAIN_PREP, 1, s);
+    const int64_t img_bytes = (int64_t)(g.h - 1) * g.pitch + g.w;
     hipLaunchKernelGGL(k_domain_prep<B>, dim3(blocks_for(p.Dp * B, th)), dim3(th), 0, s, img,
-                       g.pitch, g.dcols, g.t, perm, g.D, p.Dp, Bm, u, eps, sdd, dom);
+                       img_bytes, g.pitch, g.dcols, g.t, perm, g.D, p.Dp, Bm, u, eps, sdd, dom);
     trace(tr, FIC_STAGE_DOMAIN_PREP, 0, s);
     trace(tr, FIC_STAGE_WORKLIST, 1, s);
     hipLaunchKernelGGL(k_seed<B>, dim3(blocks_for(p.Rp * 64, th)), dim3(th), 0, s, A, Bm, rs, eps,

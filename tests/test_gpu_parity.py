@@ -169,6 +169,23 @@ def test_encode_small_exact(fic, orc, case, kernel):
     assert_codes(got, ref, what=name)
 
 
+@pytest.mark.parametrize("b,h,w", [(4, 40, 44), (8, 64, 72), (16, 96, 80)])
+def test_encode_odd_pitch_and_offset(fic, orc, b, h, w):
+    """An image view whose rows start at odd addresses (odd pitch, odd start
+    offset): the domain operands read the same pixels as from a packed copy,
+    up to the first and last byte of the view."""
+    img = fbm(h, 0.5, 40 + b, w=w)
+    big = torch.zeros((h + 1, w + 5), dtype=torch.uint8, device="cuda")
+    view = big[:h, 3:3 + w]                       # pitch w + 5 (odd), offset 3
+    view.copy_(dev(img))
+    assert view.stride(0) == w + 5 and view.data_ptr() % 4 == 3
+    for tol in (None, 0.05):
+        codes, _ = fic.encode(view, b, 1, tol=tol)
+        torch.cuda.synchronize()
+        ref = orc.encode(img, b, 1, tol=tol)
+        assert_codes(fic.unpack_codes(codes), ref, what="odd pitch b=%d tol=%s" % (b, tol))
+
+
 def test_encode_planted_copy(fic, orc):
     """A range planted as s=1/2 times an isometric domain copy: zero error."""
     from oracle import bruteforce as bf
