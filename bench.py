@@ -85,7 +85,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py measures one GPU: the search shards by ranges with no exchange "
-              "beyond gathering codes, and this build runs on a single device only "
+              "beyond gathering codes, and the library drives one device per process "
               "(got --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 

@@ -57,7 +57,7 @@ extern "C" {
 typedef enum {
     FIC_OK = 0,
     FIC_ERR_INVALID_ARG = 1,   /* null pointer, bad geometry, NaN tolerance ... */
-    FIC_ERR_UNSUPPORTED = 2,   /* a valid request this build does not handle    */
+    FIC_ERR_UNSUPPORTED = 2,   /* a valid request the library does not handle   */
     FIC_ERR_WORKSPACE = 3,     /* ws_bytes below fic_*_workspace_bytes()        */
     FIC_ERR_CAPACITY = 4,      /* the packed (F, domain, isometry) key would
                                   not fit 64 bits for this geometry             */
