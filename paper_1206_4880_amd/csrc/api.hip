@@ -116,7 +116,10 @@ Geom to_geom(const fic_geom *g)
 }
 
 // Bits of the largest F = 4096 * Srr' <= 4096 * n^2 * 255^2 / 4, plus the
-// domain index and the isometry, must fit the 64-bit key.
+// domain index and the isometry, must fit the 64-bit key. The 4x4 and 8x8
+// searches address their B operand (2n bytes per domain, padded to whole
+// blocks) with 32-bit buffer offsets, so it must stay below 2^31 bytes
+// (at 8x8 the key already bounds it to 2^30).
 bool key_fits(const Geom &g)
 {
     const double fmax = 1024.0 * (double)g.n * (double)g.n * 65025.0;
@@ -124,6 +127,7 @@ bool key_fits(const Geom &g)
     while (ldexp(1.0, fbits) <= fmax) ++fbits;
     int dbits = 1;
     while (((int64_t)1 << dbits) < g.D) ++dbits;
+    if (g.b != 16 && (double)(g.D + 64) * (double)g.n * 2.0 >= 2147483648.0) return false;
     return fbits + dbits + 3 <= 64;
 }
 

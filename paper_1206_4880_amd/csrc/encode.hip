@@ -560,6 +560,9 @@ template <int B> constexpr int queue16_cap() { return B == 16 ? 128 : kQueue; }
 // and tightens the thresholds (narrow pools pass many cells early). At 4x4
 // and 16x16 the extra flushes cost more than they save.
 constexpr int kFlushAt = 64;
+// Word 3 of a raw buffer descriptor on gfx9-family GPUs (32-bit data format,
+// no swizzle): byte offsets, no stride.
+constexpr int kBufWord3 = 0x00020000;
 
 template <class T> __device__ __forceinline__ const __attribute__((address_space(1))) T *
 as_global(const T *p)
@@ -584,9 +587,19 @@ __device__ __forceinline__ bool wave_any(bool x)
 }
 
 // ---------------- 16 x 16 tiles (8x8 and 16x16 ranges)
-// A wave owns GR = 2*MB ranges: row block b holds ranges 2b and 2b+1 under
-// the 8 isometries. Lane l of a tile sees column l%16 against range
-// 2b + l/32 under isometries 4*((l/16)%2) .. +3, i.e. half of a cell.
+// A wave owns GR = 2*MB ranges. Lane l of a tile sees column l%16 against 4
+// isometries of one range, half of a cell (a_place): at 8x8 the two row
+// blocks 2g, 2g+1 hold range 4*(l/16) + g, at 16x16 row block b holds ranges
+// 2b and 2b+1.
+template <int B> __device__ __forceinline__ int tile_range(int b, int lane)
+{
+    return Cfg<B>::QR ? 4 * (lane >> 4) + (b >> 1) : 2 * b + (lane >> 5);
+}
+template <int B> __device__ __forceinline__ int tile_iso(int b, int lane)
+{
+    return Cfg<B>::QR ? 4 * (b & 1) : 4 * ((lane >> 4) & 1);
+}
+
 template <int B> struct Queue16 {
     int32_t c[4][queue16_cap<B>()];  // exact cross terms of the half cell
     uint32_t p[queue16_cap<B>()];    // column
@@ -684,14 +697,14 @@ __device__ __forceinline__ void flush_and_refresh16(const SearchArgs *ta, WaveSt
                                                     Queue16<B> *qu)
 {
     constexpr int MW = Cfg<B>::MB;
-    const int hl = (threadIdx.x >> 5) & 1;
+    const int lane = threadIdx.x & 63;
     flush16<B>(ta, st.qn, qu, st.grp);
-    st.survivors += (threadIdx.x & 63) == 0 ? 4ull * st.qn : 0ull;
+    st.survivors += lane == 0 ? 4ull * st.qn : 0ull;
     st.qn = 0;
 #pragma unroll
     for (int b = 0; b < MW; ++b)
         if (st.T[b] != __builtin_inff())        // searched ranges only
-            st.T[b] = qu->T[2 * b + hl];
+            st.T[b] = qu->T[tile_range<B>(b, lane)];
 }
 
 // The cross terms of one 16-column block against the wave's row blocks.
@@ -721,7 +734,7 @@ __device__ __forceinline__ void queue_rowblock(const SearchArgs *ta, WaveState<B
                                                const float4_t (&accb)[Cfg<B>::NCH], uint32_t p)
 {
     constexpr int NCH = Cfg<B>::NCH;
-    const int lane = threadIdx.x & 63, hl = lane >> 5;
+    const int lane = threadIdx.x & 63;
     const u64 ball = __ballot(pass);
     if (ball == 0) return;
     const uint32_t cnt = (uint32_t)__popcll(ball);
@@ -730,7 +743,7 @@ __device__ __forceinline__ void queue_rowblock(const SearchArgs *ta, WaveState<B
         const uint32_t below = __builtin_amdgcn_mbcnt_hi(
             (uint32_t)(ball >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ball, 0u));
         const uint32_t pos = st.qn + below;
-        const uint32_t isob = ((lane >> 4) & 1) * 4;
+        const uint32_t isob = (uint32_t)tile_iso<B>(b, lane);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             int32_t cx = 0;
@@ -739,7 +752,7 @@ __device__ __forceinline__ void queue_rowblock(const SearchArgs *ta, WaveState<B
             qu->c[v][pos] = cx;
         }
         qu->p[pos] = p;
-        qu->lq[pos] = (uint32_t)(2 * b + hl) | (isob << 8);
+        qu->lq[pos] = (uint32_t)tile_range<B>(b, lane) | (isob << 8);
     }
     st.qn += cnt;
 }
@@ -756,6 +769,27 @@ __device__ __forceinline__ void screen_acc(const SearchArgs *ta, WaveState<B> &s
     const float slack = screen_slack<B>();
     const int lane = threadIdx.x & 63, col = lane & 15;
     const uint32_t p = (uint32_t)cb * 16 + col;
+    if (C::QR) {
+        // one range per lane in row blocks 2g, 2g+1: one threshold for the
+        // 8 isometries, and only a block where some lane passes takes the
+        // per-row-block tests below
+        bool any = false;
+        float dg = -__builtin_inff();
+#pragma unroll
+        for (int g = 0; g < MW / 2; ++g) {
+            const float4_t x = acc[2 * g][0], y = acc[2 * g + 1][0];
+            // a left-leaning chain: v_max3 takes two new values at a time
+            float m = fmaxf(fabsf(x[0]), fabsf(x[1]));
+            m = fmaxf(fmaxf(m, fabsf(x[2])), fabsf(x[3]));
+            m = fmaxf(fmaxf(m, fabsf(y[0])), fabsf(y[1]));
+            m = fmaxf(fmaxf(m, fabsf(y[2])), fabsf(y[3]));
+            const float d = fmaf(-st.T[2 * g], u, m);
+            if (MASK) any = any || (d >= -slack && p >= st.lo[2 * g] && p < st.hi[2 * g]);
+            else dg = fmaxf(dg, d);
+        }
+        if (!MASK) any = dg >= -slack;
+        if (!wave_any(any)) return;
+    }
     bool pass[MW];
     bool hit = false;
     float dmax = -__builtin_inff();
@@ -869,10 +903,26 @@ __device__ __forceinline__ void scan_blocks(const SearchArgs &a, const SearchArg
     cb_end = __builtin_amdgcn_readfirstlane(cb_end);
     if (cb_begin >= cb_end) return;
     const int lane = threadIdx.x & 63, col = lane & 15;
-    // scalar base + block offset, 32-bit lane offset
-    const auto *bbase = as_global(uniform_ptr((const frag_t *)a.Bm));
-    const auto *ubase = as_global(uniform_ptr(a.u));
-    const uint32_t lb = (uint32_t)lane, lu = (uint32_t)col;
+    // Buffer loads: the block offset goes in the scalar offset, the lane
+    // offset in a 32-bit VGPR, so no 64-bit address arithmetic per block. The
+    // key's domain field holds at most 2^23 domains at 8x8 (F < 2^38), so B
+    // stays below 2^30 bytes and every offset fits 32 bits (the API checks it).
+    static_assert(B == 8, "32-bit buffer offsets are sized for 8x8 ranges");
+    const __amdgpu_buffer_rsrc_t rb =
+        __builtin_amdgcn_make_buffer_rsrc((void *)uniform_ptr(a.Bm), (short)0, -1, kBufWord3);
+    const __amdgpu_buffer_rsrc_t ru =
+        __builtin_amdgcn_make_buffer_rsrc((void *)uniform_ptr(a.u), (short)0, -1, kBufWord3);
+    const uint32_t lb = (uint32_t)lane * (uint32_t)sizeof(frag_t), lu = (uint32_t)col * 4u;
+    constexpr uint32_t kBlkB = KS * 64 * sizeof(frag_t), kBlkU = 16 * 4;
+    auto ldb = [&](int c, int ks) {
+        return __builtin_bit_cast(frag_t, __builtin_amdgcn_raw_buffer_load_b128(
+                                              rb, lb + (uint32_t)(ks * 64 * sizeof(frag_t)),
+                                              (int)((uint32_t)c * kBlkB), 0));
+    };
+    auto ldu = [&](int c) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                             ru, lu, (int)((uint32_t)c * kBlkU), 0));
+    };
     const int last = cb_end - 1;
     frag_t b0[KS], b1[KS];
     float u0, u1;
@@ -880,11 +930,11 @@ __device__ __forceinline__ void scan_blocks(const SearchArgs &a, const SearchArg
         const int c1 = min(cb_begin + 1, last);
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
-            b0[ks] = (bbase + (int64_t)cb_begin * KS * 64)[lb + ks * 64];
-            b1[ks] = (bbase + (int64_t)c1 * KS * 64)[lb + ks * 64];
+            b0[ks] = ldb(cb_begin, ks);
+            b1[ks] = ldb(c1, ks);
         }
-        u0 = (ubase + (int64_t)cb_begin * 16)[lu];
-        u1 = (ubase + (int64_t)c1 * 16)[lu];
+        u0 = ldu(cb_begin);
+        u1 = ldu(c1);
     }
     // whole pairs of blocks without a branch between them (a conditional
     // second step would make the compiler wait for the loads just issued)
@@ -898,8 +948,8 @@ __device__ __forceinline__ void scan_blocks(const SearchArgs &a, const SearchArg
             const float uc = u0;
             const int nx = min(cb + 2, last);
 #pragma unroll
-            for (int ks = 0; ks < KS; ++ks) b0[ks] = (bbase + (int64_t)nx * KS * 64)[lb + ks * 64];
-            u0 = (ubase + (int64_t)nx * 16)[lu];
+            for (int ks = 0; ks < KS; ++ks) b0[ks] = ldb(nx, ks);
+            u0 = ldu(nx);
             screen_acc<B, MASK>(ta, st, qu, acc, uc, cb);
         }
         {
@@ -908,8 +958,8 @@ __device__ __forceinline__ void scan_blocks(const SearchArgs &a, const SearchArg
             const float uc = u1;
             const int nx = min(cb + 3, last);
 #pragma unroll
-            for (int ks = 0; ks < KS; ++ks) b1[ks] = (bbase + (int64_t)nx * KS * 64)[lb + ks * 64];
-            u1 = (ubase + (int64_t)nx * 16)[lu];
+            for (int ks = 0; ks < KS; ++ks) b1[ks] = ldb(nx, ks);
+            u1 = ldu(nx);
             screen_acc<B, MASK>(ta, st, qu, acc, uc, cb + 1);
         }
     }
@@ -931,7 +981,7 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma(const SearchArgs *__rest
     constexpr int MW = C::MB, KS = C::KS, GR = C::GR;
     typedef typename WaveState<B>::frag_t frag_t;
     __shared__ Queue16<B> queues[4];
-    const int lane = threadIdx.x & 63, hl = lane >> 5;
+    const int lane = threadIdx.x & 63;
     Queue16<B> *qu = &queues[threadIdx.x >> 6];
     const uint32_t nitems = base[n_img];
     WaveState<B> st;
@@ -967,7 +1017,7 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma(const SearchArgs *__rest
         }
 #pragma unroll
         for (int b = 0; b < MW; ++b) {
-            const int64_t slot = (int64_t)st.grp * GR + 2 * b + hl;
+            const int64_t slot = (int64_t)st.grp * GR + tile_range<B>(b, lane);
             const RangeStat rsx = a.rs[slot];
             const u64 bk = a.keys[slot];
             st.lo[b] = rsx.lo;
@@ -1032,7 +1082,7 @@ __global__ __launch_bounds__(256, 2) void k_search_lds16(const SearchArgs *__res
     __shared__ float sU0[SB * 16], sU1[SB * 16];    // never aliases the one being read
     __shared__ Queue16<B> queues[4];
     __shared__ uint32_t sItem;
-    const int lane = threadIdx.x & 63, hl = lane >> 5, col = lane & 15;
+    const int lane = threadIdx.x & 63, col = lane & 15;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     Queue16<B> *qu = &queues[w];
     const uint32_t nitems = base[n_img];
@@ -1072,7 +1122,7 @@ __global__ __launch_bounds__(256, 2) void k_search_lds16(const SearchArgs *__res
         uint32_t wlo = 0xffffffffu, whi = 0u, ilo = 0u, ihi = 0xffffffffu;
 #pragma unroll
         for (int b = 0; b < MW; ++b) {
-            const int64_t slot = (int64_t)st.grp * GR + 2 * b + hl;
+            const int64_t slot = (int64_t)st.grp * GR + tile_range<B>(b, lane);
             const RangeStat rsx = a.rs[slot];
             const u64 bk = a.keys[slot];
             st.lo[b] = rsx.lo;
@@ -1347,17 +1397,26 @@ __device__ __forceinline__ void scan32(const SearchArgs &a, const SearchArgs *ta
     cb_end = __builtin_amdgcn_readfirstlane(cb_end);
     if (cb_begin >= cb_end) return;
     const int lane = threadIdx.x & 63, col = lane & 31;
-    // scalar base + block offset, 32-bit lane offset
-    const auto *bbase = as_global(uniform_ptr((const half8_t *)a.Bm));
-    const auto *ubase = as_global(uniform_ptr(a.u));
-    const uint32_t lb = (uint32_t)lane, lu = (uint32_t)col;
+    // buffer loads: block offset in the scalar offset, 32-bit lane offset
+    // (the API rejects a B operand of 2^31 bytes or more)
+    static_assert(B == 4, "32-bit buffer offsets are sized for 4x4 ranges");
+    const __amdgpu_buffer_rsrc_t rb =
+        __builtin_amdgcn_make_buffer_rsrc((void *)uniform_ptr(a.Bm), (short)0, -1, kBufWord3);
+    const __amdgpu_buffer_rsrc_t ru =
+        __builtin_amdgcn_make_buffer_rsrc((void *)uniform_ptr(a.u), (short)0, -1, kBufWord3);
+    const uint32_t lb = (uint32_t)lane * 16u, lu = (uint32_t)col * 4u;
+    constexpr uint32_t kBlkB = KS * 64 * 16, kBlkU = 32 * 4;
     const int last = cb_end - 1;
     half8_t b0[KS], b1[KS], b2[KS], b3[KS];
     float u0, u1, u2 = 0.0f, u3 = 0.0f;
     auto load = [&](half8_t (&bq)[KS], float &uq, int c) {
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) bq[ks] = (bbase + (int64_t)c * KS * 64)[lb + ks * 64];
-        uq = (ubase + (int64_t)c * 32)[lu];
+        for (int ks = 0; ks < KS; ++ks)
+            bq[ks] = __builtin_bit_cast(half8_t, __builtin_amdgcn_raw_buffer_load_b128(
+                                                     rb, lb + (uint32_t)ks * 1024u,
+                                                     (int)((uint32_t)c * kBlkB), 0));
+        uq = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                           ru, lu, (int)((uint32_t)c * kBlkU), 0));
     };
     // the cross terms of one column block (MB row blocks of 32 x 32)
     auto mmab = [&](const half8_t (&bq)[KS], float16_t (&acc)[MB]) {

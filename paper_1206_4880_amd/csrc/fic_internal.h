@@ -42,20 +42,29 @@ constexpr u64 kNoKey = ~0ull;
 // the block in row-major order, for the A (rows) and B (columns) operand
 // alike, so their products pair up pixel by pixel.
 template <int B> struct Cfg;
+// QR: the 16 x 16 tiles hold a range's 8 isometries in one quarter of the
+// lanes over two row blocks (1), or in one row block (0); see a_place.
 template <> struct Cfg<4> {
-    static constexpr int n = 16, MR = 32, KPI = 16, EPL = 8, KS = 1, MB = 4, NCH = 1, GR = 16;
+    static constexpr int n = 16, MR = 32, KPI = 16, EPL = 8, KS = 1, MB = 4, NCH = 1, GR = 16,
+                         QR = 0;
 };
 template <> struct Cfg<8> {
-    static constexpr int n = 64, MR = 16, KPI = 32, EPL = 8, KS = 2, MB = 8, NCH = 1, GR = 16;
+    static constexpr int n = 64, MR = 16, KPI = 32, EPL = 8, KS = 2, MB = 8, NCH = 1, GR = 16,
+                         QR = 1;
 };
 template <> struct Cfg<16> {
-    static constexpr int n = 256, MR = 16, KPI = 32, EPL = 8, KS = 8, MB = 3, NCH = 4, GR = 6;
+    static constexpr int n = 256, MR = 16, KPI = 32, EPL = 8, KS = 8, MB = 3, NCH = 4, GR = 6,
+                         QR = 0;
 };
 
 // Row of range ls (0..GR-1 of its wave group) under isometry q: row block
-// blk and row inside it.
-//   MR = 16: rows 8*(ls%2) + q. Lane l of the 16x16 output (rows 4*(l/16)
-//            .. +3) sees range ls%2 = l/32 under isometries 4*((l/16)%2) + v.
+// blk and row inside it. Lane l of a 16x16 output holds rows 4*(l/16) + v,
+// v = 0..3.
+//   MR = 16, QR = 1: row block 2*(ls%4) + q/4, row 4*(ls/4) + q%4. Lane l
+//            sees range 4*(l/16) + blk/2 under isometries 4*(blk%2) + v, so
+//            a pair of row blocks holds all 8 isometries of one range per lane.
+//   MR = 16, QR = 0: row block ls/2, row 8*(ls%2) + q. Lane l sees range
+//            2*blk + l/32 under isometries 4*((l/16)%2) + v.
 //   MR = 32: the output of lane l holds rows 8*(v/4) + 4*(l/32) + v%4,
 //            v = 0..15; the placement below makes v < 8 range 2*(l/32) and
 //            v >= 8 range 2*(l/32) + 1 of the quad, isometry v % 8.
@@ -66,6 +75,9 @@ __host__ __device__ inline void a_place(int ls, int q, int &blk, int &row)
         const int rl = ls & 3;
         blk = ls >> 2;
         row = 8 * (2 * (rl & 1) + (q >> 2)) + 4 * (rl >> 1) + (q & 3);
+    } else if (Cfg<B>::QR) {
+        blk = 2 * (ls & 3) + (q >> 2);
+        row = 4 * (ls >> 2) + (q & 3);
     } else {
         blk = ls >> 1;
         row = 8 * (ls & 1) + q;

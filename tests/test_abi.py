@@ -95,13 +95,20 @@ def test_encode_validation(L, hctx):
 
 def test_capacity_limit(L, hctx):
     """F needs 42 bits at 16x16 ranges; 2^19 or more domains leave fewer than
-    the 64 - 42 - 3 bits an index needs."""
+    the 64 - 42 - 3 bits an index needs. 4x4 and 8x8 searches also need their
+    B operand below 2^31 bytes."""
     ok = fic.make_geom(2048, 2048, 16, 4)         # 255,025 domains: 18 bits
     assert _encode(L, hctx, ok, wsb=1 << 40) == fic.ERR_DEVICE
     big = fic.make_geom(8192, 8192, 16, 4)        # 4,182,025 domains: 22 bits
     assert _encode(L, hctx, big, wsb=1 << 40) == fic.ERR_CAPACITY
     b8 = fic.make_geom(4096, 4096, 8, 1)          # 38 + 24 + 3 > 64
     assert _encode(L, hctx, b8, wsb=1 << 40) == fic.ERR_CAPACITY
+    # 4x4: the key fits 67M domains, but the B operand (32 bytes a domain) is
+    # addressed with 32-bit offsets and must stay below 2^31 bytes
+    b4ok = fic.make_geom(8192, 8192, 4, 1)        # 66,994,225 domains
+    assert _encode(L, hctx, b4ok, wsb=1 << 40) == fic.ERR_DEVICE
+    b4big = fic.make_geom(8200, 8200, 4, 1)       # 67,125,249 domains: 2^31 bytes
+    assert _encode(L, hctx, b4big, wsb=1 << 40) == fic.ERR_CAPACITY
 
 
 def test_classify_validation(L, hctx):
