@@ -630,19 +630,22 @@ __device__ __noinline__ void flush16(const SearchArgs *ta, uint32_t nq, Queue16<
                                      uint32_t grp)
 {
     constexpr int n = Cfg<B>::n, GR = Cfg<B>::GR, RQ = queue16_cap<B>() / 64;
+    const float slack = screen_slack<B>();
     const int lane = threadIdx.x & 63;
     const SearchArgs a = *ta;
     const auto *gsdd = as_global(a.sdd);
     const auto *geps = as_global(a.eps);
     const auto *gdom = as_global(a.dom);
+    const auto *gu = as_global(a.u);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     uint32_t pe[RQ], lqe[RQ], dm[RQ];
     int64_t sd[RQ];
     int32_t ep[RQ];
+    float uu[RQ];
 #pragma unroll
     for (int r = 0; r < RQ; ++r) {
         const uint32_t e = (uint32_t)(r * 64 + lane);
-        pe[r] = 0; lqe[r] = 0; dm[r] = 0; sd[r] = 0; ep[r] = 0;
+        pe[r] = 0; lqe[r] = 0; dm[r] = 0; sd[r] = 0; ep[r] = 0; uu[r] = 0.0f;
         if (e < nq) {
             pe[r] = qu->p[e];
             lqe[r] = qu->lq[e];
@@ -654,30 +657,45 @@ __device__ __noinline__ void flush16(const SearchArgs *ta, uint32_t nq, Queue16<
             sd[r] = gsdd[pe[r]];
             ep[r] = geps[pe[r]];
             dm[r] = gdom[pe[r]];
+            uu[r] = gu[pe[r]];
         }
 #pragma unroll
     for (int r = 0; r < RQ; ++r) {
         const uint32_t e = (uint32_t)(r * 64 + lane);
+        // the isometries of the half cell that still pass the screen against
+        // the range's current threshold (the queued cross terms are exact);
+        // the wave fits one of them per lane and step, in increasing order
+        uint32_t mask = 0;
+        uint32_t ls = 0, isob = 0;
         if (e < nq) {
-            const uint32_t ls = lqe[r] & 255u, isob = lqe[r] >> 8;
-            const double base = 4096.0 * (double)qu->srr[ls];
-            const double ne = (double)qu->delta[ls] * (double)ep[r];
-            const double dd = (double)sd[r];
-            const float inv = __builtin_amdgcn_rcpf((float)dd);
-            // the half cell's 4 isometries: lowest F, then lowest isometry
-            double fb = 0.0;
-            int vb = 0;
+            ls = lqe[r] & 255u;
+            isob = lqe[r] >> 8;
+            const float t = qu->T[ls];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
+            for (int v = 0; v < 4; ++v)
+                if (fmaf(-t, uu[r], fabsf((float)qu->c[v][e])) >= -slack) mask |= 1u << v;
+        }
+        if (!wave_any(mask != 0)) continue;
+        const double base = 4096.0 * (double)qu->srr[ls];
+        const double ne = (double)qu->delta[ls] * (double)ep[r];
+        const double dd = (double)sd[r];
+        const float inv = __builtin_amdgcn_rcpf((float)dd);
+        const bool any = mask != 0;
+        double fb = 0.0;
+        int vb = -1;
+        while (wave_any(mask != 0)) {
+            if (mask) {
+                const int v = __builtin_ctz(mask);
+                mask &= mask - 1u;
                 const double rd = (double)n * (double)qu->c[v][e] - ne;   // exact integers
                 const double f = fit_f_d(base, rd, dd, inv);
-                if (v == 0 || f < fb) {
+                if (vb < 0 || f < fb) {      // ascending v: ties keep the lower isometry
                     fb = f;
                     vb = v;
                 }
             }
-            atomicMin(&qu->best[ls], pack_key((int64_t)fb, dm[r], (int)isob + vb, a.shift));
         }
+        if (any) atomicMin(&qu->best[ls], pack_key((int64_t)fb, dm[r], (int)isob + vb, a.shift));
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     if (lane < GR) {
@@ -1010,10 +1028,14 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma(const SearchArgs *__rest
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) st.af[b][ks] = ap[(b * KS + ks) * 64];
         if (lane < GR) {
+            // the flush re-screens queued cells against these thresholds
             const int64_t slot = (int64_t)st.grp * GR + lane;
-            qu->best[lane] = a.keys[slot];
-            qu->srr[lane] = a.rs[slot].srr;
+            const u64 bk = a.keys[slot];
+            const int64_t srr = a.rs[slot].srr;
+            qu->best[lane] = bk;
+            qu->srr[lane] = srr;
             qu->delta[lane] = a.rs[slot].delta;
+            qu->T[lane] = bk == kNoKey ? 0.0f : screen_t_b<B>(srr, (int64_t)(bk >> a.shift));
         }
 #pragma unroll
         for (int b = 0; b < MW; ++b) {
@@ -1113,10 +1135,14 @@ __global__ __launch_bounds__(256, 2) void k_search_lds16(const SearchArgs *__res
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) st.af[b][ks] = ap[(b * KS + ks) * 64];
         if (lane < GR) {
+            // the flush re-screens queued cells against these thresholds
             const int64_t slot = (int64_t)st.grp * GR + lane;
-            qu->best[lane] = a.keys[slot];
-            qu->srr[lane] = a.rs[slot].srr;
+            const u64 bk = a.keys[slot];
+            const int64_t srr = a.rs[slot].srr;
+            qu->best[lane] = bk;
+            qu->srr[lane] = srr;
             qu->delta[lane] = a.rs[slot].delta;
+            qu->T[lane] = bk == kNoKey ? 0.0f : screen_t_b<B>(srr, (int64_t)(bk >> a.shift));
         }
         // the wave's own pools: union [wlo, whi) and intersection [ilo, ihi)
         uint32_t wlo = 0xffffffffu, whi = 0u, ilo = 0u, ihi = 0xffffffffu;
@@ -1257,19 +1283,22 @@ __device__ __noinline__ void flush32(const SearchArgs *ta, uint32_t nq, Queue32<
                                      uint32_t grp)
 {
     constexpr int n = Cfg<B>::n, GR = Cfg<B>::GR, RQ = kQueue / 64;
+    const float slack = screen_slack<B>();
     const int lane = threadIdx.x & 63;
     const SearchArgs a = *ta;
     const auto *gsdd = as_global(a.sdd);
     const auto *geps = as_global(a.eps);
     const auto *gdom = as_global(a.dom);
+    const auto *gu = as_global(a.u);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     uint32_t pe[RQ], le[RQ], dm[RQ];
     int64_t sd[RQ];
     int32_t ep[RQ];
+    float uu[RQ];
 #pragma unroll
     for (int r = 0; r < RQ; ++r) {
         const uint32_t e = (uint32_t)(r * 64 + lane);
-        pe[r] = 0; le[r] = 0; dm[r] = 0; sd[r] = 0; ep[r] = 0;
+        pe[r] = 0; le[r] = 0; dm[r] = 0; sd[r] = 0; ep[r] = 0; uu[r] = 0.0f;
         if (e < nq) {
             pe[r] = qu->p[e];
             le[r] = qu->ls[e];
@@ -1281,30 +1310,46 @@ __device__ __noinline__ void flush32(const SearchArgs *ta, uint32_t nq, Queue32<
             sd[r] = gsdd[pe[r]];
             ep[r] = geps[pe[r]];
             dm[r] = gdom[pe[r]];
+            uu[r] = gu[pe[r]];
         }
 #pragma unroll
     for (int r = 0; r < RQ; ++r) {
         const uint32_t e = (uint32_t)(r * 64 + lane);
+        // The isometries of the cell that still pass the screen against the
+        // range's current threshold (never looser than when it was queued);
+        // the others cannot reach the range's best key. Usually one or two
+        // of the 8 pass, so the wave fits one passing isometry per lane and
+        // step, in increasing order, until no lane has one left.
+        uint32_t mask = 0;
+        uint32_t ls = 0;
         if (e < nq) {
-            const uint32_t ls = le[r];
-            const double base = 4096.0 * (double)qu->srr[ls];
-            const double ne = (double)qu->delta[ls] * (double)ep[r];
-            const double dd = (double)sd[r];
-            const float inv = __builtin_amdgcn_rcpf((float)dd);
-            // the cell's 8 isometries: lowest F, then lowest isometry
-            double fb = 0.0;
-            int qb = 0;
+            ls = le[r];
+            const float t = qu->T[ls];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
+            for (int q = 0; q < 8; ++q)
+                if (fmaf(-t, uu[r], fabsf(qu->c[q][e])) >= -slack) mask |= 1u << q;
+        }
+        if (!wave_any(mask != 0)) continue;
+        const double base = 4096.0 * (double)qu->srr[ls];
+        const double ne = (double)qu->delta[ls] * (double)ep[r];
+        const double dd = (double)sd[r];
+        const float inv = __builtin_amdgcn_rcpf((float)dd);
+        const bool any = mask != 0;
+        double fb = 0.0;
+        int qb = -1;
+        while (wave_any(mask != 0)) {
+            if (mask) {
+                const int q = __builtin_ctz(mask);
+                mask &= mask - 1u;
                 const double rd = (double)n * (double)qu->c[q][e] - ne;   // exact integers
                 const double f = fit_f_d(base, rd, dd, inv);
-                if (q == 0 || f < fb) {
+                if (qb < 0 || f < fb) {      // ascending q: ties keep the lower isometry
                     fb = f;
                     qb = q;
                 }
             }
-            atomicMin(&qu->best[ls], pack_key((int64_t)fb, dm[r], qb, a.shift));
         }
+        if (any) atomicMin(&qu->best[ls], pack_key((int64_t)fb, dm[r], qb, a.shift));
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     if (lane < GR) {
@@ -1506,10 +1551,14 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma32(const SearchArgs *__re
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) st.af[blk][ks] = ap[(blk * KS + ks) * 64];
         if (lane < GR) {
+            // the flush re-screens queued cells against these thresholds
             const int64_t slot = (int64_t)st.grp * GR + lane;
-            qu->best[lane] = a.keys[slot];
-            qu->srr[lane] = a.rs[slot].srr;
+            const u64 bk = a.keys[slot];
+            const int64_t srr = a.rs[slot].srr;
+            qu->best[lane] = bk;
+            qu->srr[lane] = srr;
             qu->delta[lane] = a.rs[slot].delta;
+            qu->T[lane] = bk == kNoKey ? 0.0f : screen_t(srr, (int64_t)(bk >> a.shift));
         }
 #pragma unroll
         for (int blk = 0; blk < MB; ++blk)
