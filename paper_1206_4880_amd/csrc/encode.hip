@@ -843,34 +843,48 @@ __device__ __forceinline__ void screen_block(const SearchArgs *ta, WaveState<B> 
     screen_acc<B, MASK>(ta, st, qu, acc, u, cb);
 }
 
-// 16x16 ranges, B fragments of the block in LDS (lane order). The hot test
-// chains all KS MFMAs into one accumulator per row block; only a block where
-// some lane passes recomputes the exact 64-term chunk sums (re-reading its
-// fragments) and goes through the exact screen and queue.
-template <int B, bool MASK>
-__device__ __forceinline__ void screen_block_lds(const SearchArgs *ta, WaveState<B> &st,
-                                                 Queue16<B> *qu,
-                                                 const typename WaveState<B>::frag_t *lb,
-                                                 float u, int cb)
+// The hot cross terms of one 16-column block whose B fragments are in LDS:
+// all KS MFMAs of a row block chained into one accumulator.
+template <int B>
+__device__ __forceinline__ void mma_block_lds(const WaveState<B> &st,
+                                              const typename WaveState<B>::frag_t *lb,
+                                              float4_t (&acc)[Cfg<B>::MB])
 {
     using C = Cfg<B>;
     constexpr int MW = C::MB, KS = C::KS;
     typedef typename WaveState<B>::frag_t frag_t;
+    const int lane = threadIdx.x & 63;
+    frag_t bf[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) bf[ks] = lb[ks * 64 + lane];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int b = 0; b < MW; ++b) {
+            const float4_t z = {0.f, 0.f, 0.f, 0.f};
+            acc[b] = mma(st.af[b][ks], bf[ks], ks ? acc[b] : z);
+        }
+    // all reads first, then the MFMAs K step by K step (without this the
+    // scheduler interleaves them less well and the block needs more VGPRs)
+    __builtin_amdgcn_sched_group_barrier(0x100, KS, 0);   // LDS reads
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) __builtin_amdgcn_sched_group_barrier(0x008, MW, 0);   // MFMAs
+}
+
+// 16x16 ranges, B fragments of the block in LDS (lane order). The hot test
+// screens the one-accumulator sums; only a block where some lane passes
+// recomputes the exact 64-term chunk sums (re-reading its fragments) and
+// goes through the exact screen and queue.
+template <int B, bool MASK>
+__device__ __forceinline__ void screen_block_lds(const SearchArgs *ta, WaveState<B> &st,
+                                                 Queue16<B> *qu,
+                                                 const typename WaveState<B>::frag_t *lb,
+                                                 const float4_t (&acc)[Cfg<B>::MB], float u, int cb)
+{
+    using C = Cfg<B>;
+    constexpr int MW = C::MB, KS = C::KS;
     const int lane = threadIdx.x & 63, col = lane & 15;
     const float slack = screen_slack<B>();
-    float4_t acc[MW];
-    {
-        frag_t bf[KS];
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) bf[ks] = lb[ks * 64 + lane];
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-            for (int b = 0; b < MW; ++b) {
-                const float4_t z = {0.f, 0.f, 0.f, 0.f};
-                acc[b] = mma(st.af[b][ks], bf[ks], ks ? acc[b] : z);
-            }
-    }
     const uint32_t p = (uint32_t)cb * 16 + col;
     bool hit = false;
     float dmax = -__builtin_inff();
@@ -1213,10 +1227,12 @@ __global__ __launch_bounds__(256, 2) void k_search_lds16(const SearchArgs *__res
                 const int cb = cb0 + sidx * SB + j;
                 if (cb < lb0 || cb >= lb1) continue;
                 const float u = cU[j * 16 + col];
+                float4_t acc[MW];
+                mma_block_lds<B>(st, cB + j * KS * 64, acc);
                 if (cb >= ib0 && cb < ib1)
-                    screen_block_lds<B, false>(ta, st, qu, cB + j * KS * 64, u, cb);
+                    screen_block_lds<B, false>(ta, st, qu, cB + j * KS * 64, acc, u, cb);
                 else
-                    screen_block_lds<B, true>(ta, st, qu, cB + j * KS * 64, u, cb);
+                    screen_block_lds<B, true>(ta, st, qu, cB + j * KS * 64, acc, u, cb);
             }
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
