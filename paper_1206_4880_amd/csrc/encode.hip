@@ -806,6 +806,18 @@ __device__ __forceinline__ void screen_acc(const SearchArgs *ta, WaveState<B> &s
             else dg = fmaxf(dg, d);
         }
         if (!MASK) any = dg >= -slack;
+        if (!MASK && MW == 8 && C::KS == 2) {
+            // the last MFMAs of the block interleaved with the screens of the
+            // ranges whose row blocks are done (12 MFMAs, then a range's 5
+            // VALU instructions per 2 MFMAs, the last two ranges, the fold and
+            // the compare): the screen no longer waits on fresh MFMA results
+            __builtin_amdgcn_sched_group_barrier(0x008, 12, 0);   // MFMA
+            __builtin_amdgcn_sched_group_barrier(0x002, 5, 0);    // VALU
+            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+            __builtin_amdgcn_sched_group_barrier(0x002, 5, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+            __builtin_amdgcn_sched_group_barrier(0x002, 13, 0);
+        }
         if (!wave_any(any)) return;
     }
     bool pass[MW];
@@ -1421,6 +1433,14 @@ __device__ __forceinline__ void screen32(const SearchArgs &a, const SearchArgs *
             else dmax = fmaxf(dmax, d);
         }
     if (!MASK) hit = dmax >= -slack;
+    if (!MASK && MB == 4) {
+        // three MFMAs, the first row block's screen, the last MFMA, the rest:
+        // the screen starts on results that are done
+        __builtin_amdgcn_sched_group_barrier(0x008, 3, 0);    // MFMA
+        __builtin_amdgcn_sched_group_barrier(0x002, 10, 0);   // VALU
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x002, 40, 0);
+    }
     if (!wave_any(hit)) return;
     // append the passing cells (at most 64 per row block half)
 #pragma unroll
