@@ -81,7 +81,13 @@ typedef struct {
     uint8_t  o_idx;    /* j, o = 2j                                           */
     uint8_t  flags;    /* bit 0: empty pool, DC-only code (domain 0, iso 0,
                           k = 0); bit 1: split (two-level encode); bit 2:
-                          not coded (two-level encode, parent not split)     */
+                          not coded (two-level encode, parent not split);
+                          bit 7: internal check failed -- the search's
+                          packed key disagreed with the exact recomputation
+                          of its winner from the pixels. It never occurs
+                          in a correct build; a code carrying it must not
+                          be trusted (the call itself still returned
+                          FIC_OK, since codes are written asynchronously). */
     int64_t  err;      /* E = 4096 * n * SSE                                  */
 } fic_code;
 
@@ -108,12 +114,29 @@ fic_status fic_destroy(fic_ctx *ctx);
 /* Static text of a status (host). */
 const char *fic_status_string(fic_status s);
 
-/* Optional instrumentation: when `counters` (dev, 4 x uint64, zeroed by the
+/* Optional instrumentation: when `counters` (dev, 8 x uint64, zeroed by the
    caller) is set, the search kernels add
      [0] pair evaluations screened, [1] pairs passed to the exact fit,
-     [2] work items processed,      [3] exact seeds evaluated.
+     [2] work items processed,      [3] exact seeds evaluated,
+   and with FIC_DEBUG_VERIFY16 (fic_set_debug) the 16x16 search adds
+     [4] FP32 sums whose rounding error exceeded the bound its screen
+         threshold is lowered by (must stay 0),
+     [5] sums checked, [6] the largest error / bound seen, in units of
+         2^-20 (an atomic maximum).
    NULL (the default) disables the adds. */
 fic_status fic_set_counters(fic_ctx *ctx, uint64_t *counters /* dev */);
+
+/* Debug switches (host state of the context, for tests; 0 = off, the
+   default). FIC_DEBUG_REVERSE_ITEMS: the persistent searches take their
+   work items in reverse order (codes must not change: the packed-key minimum
+   is order independent). FIC_DEBUG_VERIFY16: the 16x16 search recomputes the
+   exact 64-term chunk sums of every block it screens and checks the rounding
+   error of its one-accumulator FP32 sums against the bound its screen relies
+   on, counting into counters [4]..[6] (much slower; codes unchanged).
+   FIC_ERR_INVALID_ARG for unknown bits. Batch graphs are recorded per
+   switch setting. */
+enum { FIC_DEBUG_REVERSE_ITEMS = 1, FIC_DEBUG_VERIFY16 = 2 };
+fic_status fic_set_debug(fic_ctx *ctx, uint32_t flags);
 
 /* Stage tracing. With timing enabled, each later call records a pair of HIP
    events around each of its stages, on the call's own stream:
@@ -320,6 +343,62 @@ fic_status fic_decode_quadtree(fic_ctx *ctx, const fic_code *codes1, const fic_g
                                const fic_code *codes2, const fic_geom *g2, int32_t max_iters,
                                const uint8_t *init, uint8_t *out, void *scratch,
                                size_t scratch_bytes, int32_t *iters_done, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Autotuning of the persistent search (the uneven per-range pools of Sec.
+ * 3.1 make the work per range vary widely).
+ * Each encode picks, ON THE DEVICE, two parameters of its work list from a
+ * table row of the context, indexed by the image's pool-fraction bucket
+ * (0: exhaustive; pooled images 1 + floor(-log2 f) clamped to 1..5, f = the
+ * sum of the searched ranges' pool sizes / (R * D)):
+ *   chunk_log2  columns per work item = 2^chunk_log2, 11..16;
+ *   flush_at    early flush of a wave's queue of passing cells once it holds
+ *               at least this many (0 = only when full), 0..256.
+ * A row serves one (range size B, floor(log2 D)) class; classes without a
+ * row use the built-in defaults (exhaustive 2^14, pooled 2^12; flush 64 at
+ * B = 8, else 0). Every choice gives the same codes.
+ *
+ * fic_autotune: for the images described by descs (each with its geometry
+ * and tolerance, codes written to descs[i].codes), group them by (B,
+ * floor(log2 D), bucket) and, per group, time whole encodes (classify, pool,
+ * search, finalize of each image alone, best of `reps`) of candidate rows by
+ * coordinate descent (chunk_log2 over 11..16, then flush_at over 0, 32, 64,
+ * 128), keep the winner only if a final interleaved re-measurement still has
+ * it faster than the starting row, and store it in the context. BLOCKS THE
+ * HOST (event synchronisation); not for stream capture. Recorded batch graphs
+ * are dropped. report (host, nullable) receives up to report_cap entries, one
+ * per group; *report_count (nullable) the number of groups.
+ *   ws  (dev) >= fic_autotune_workspace_bytes(n_images, descs) (the largest
+ *       single-image batch workspace).
+ * fic_tune_save / fic_tune_load: the context's rows as a JSON file (host
+ * path) tagged with the device's gcnArchName and fic_kernel_hash(); load
+ * replaces the rows, answers FIC_ERR_UNSUPPORTED (rows unchanged) for a file
+ * written for another architecture or other kernels, FIC_ERR_INVALID_ARG for
+ * an unreadable or malformed one. fic_create loads the file named by the
+ * environment variable FIC_TUNE_CACHE when it matches.
+ * fic_tune_reset: back to the defaults.
+ * fic_tune_query: the (chunk_log2, flush_at) an encode of geometry g would
+ * use (pool_fraction as above, ignored when pooled = 0).
+ * fic_kernel_hash: static string identifying the kernel sources of this
+ * build.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    int32_t range_size, dlog2, bucket, images;   /* the tuning class         */
+    int32_t chunk_log2, flush_at;                /* chosen                   */
+    int32_t base_chunk_log2, base_flush_at;      /* the row it started from  */
+    float base_ms, tuned_ms;   /* summed encode times of the class's images */
+} fic_tune_entry;
+size_t fic_autotune_workspace_bytes(int32_t n_images, const fic_image_desc *descs);
+fic_status fic_autotune(fic_ctx *ctx, int32_t n_images, const fic_image_desc *descs,
+                        void *ws, size_t ws_bytes, int32_t reps,
+                        fic_tune_entry *report /* host */, int32_t report_cap,
+                        int32_t *report_count /* host */, void *stream);
+fic_status fic_tune_save(fic_ctx *ctx, const char *path);
+fic_status fic_tune_load(fic_ctx *ctx, const char *path);
+fic_status fic_tune_reset(fic_ctx *ctx);
+fic_status fic_tune_query(fic_ctx *ctx, const fic_geom *g, int32_t pooled, double pool_fraction,
+                          int32_t *chunk_log2 /* host */, int32_t *flush_at /* host */);
+const char *fic_kernel_hash(void);
 
 #ifdef __cplusplus
 }

@@ -39,15 +39,29 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
+def kernel_hash():
+    """First 16 hex digits of SHA-256 over the library's sources (every
+    csrc/*.hip and *.h, then include/fic.h): the tag of autotuning caches."""
+    import hashlib
+    h = hashlib.sha256()
+    files = sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".h")))
+    for f in files + ["../../include/fic.h"]:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(os.path.basename(f).encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
 def build(verbose=False, jobs=8):
     os.makedirs(BUILD, exist_ok=True)
     hipcc = _hipcc()
     srcs = sources()
+    per_file = dict(PER_FILE)
+    per_file["api.hip"] = per_file.get("api.hip", []) + ['-DFIC_KERNEL_HASH="%s"' % kernel_hash()]
     objs = [os.path.join(BUILD, os.path.basename(s)[:-4] + ".o") for s in srcs]
 
     def one(pair):
         s, o = pair
-        cmd = [hipcc] + FLAGS + PER_FILE.get(os.path.basename(s), []) + ["-c", s, "-o", o]
+        cmd = [hipcc] + FLAGS + per_file.get(os.path.basename(s), []) + ["-c", s, "-o", o]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError("hipcc failed on %s:\n%s" % (s, r.stderr))

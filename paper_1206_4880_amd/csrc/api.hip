@@ -6,9 +6,12 @@
 // then does a context without a device (device = -1, used to test the
 // validation on machines without a GPU) answer FIC_ERR_DEVICE.
 #include <new>
+#include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 #include <math.h>
 #include <stdint.h>
+#include <string>
 #include <vector>
 
 #include "fic_internal.h"
@@ -35,6 +38,12 @@ struct fic_ctx {
     std::vector<Graph> graphs;
     hipStream_t cap;     // capture stream, created with the first graph
     fic::BatchStreams side;   // batch preparation streams (side.ns == 0 until created)
+    uint32_t dbg;        // fic_set_debug switches
+    char arch[64];       // gcnArchName of the device (tuning cache key)
+    // tuned search parameters per (range size, floor(log2 D)); classes
+    // without a row use fic::default_tune_row
+    struct TuneEntry { int32_t b, dlog; fic::TuneRow row; };
+    std::vector<TuneEntry> tune;
 };
 
 namespace {
@@ -70,6 +79,35 @@ void mark_stage(void *self, int stage, int begin, hipStream_t s)
 }
 
 const fic::Tracer *tracer_of(fic_ctx *c) { return c->timing ? &c->tracer : nullptr; }
+
+int dlog2_of(int64_t D)
+{
+    int l = 0;
+    while (((int64_t)2 << l) <= D) ++l;
+    return l;                        // floor(log2 D), D >= 1
+}
+
+fic::TuneRow tune_row(const fic_ctx *c, int b, int64_t D)
+{
+    const int dl = dlog2_of(D);
+    for (const auto &t : c->tune)
+        if (t.b == b && t.dlog == dl) return t.row;
+    return fic::default_tune_row(b);
+}
+
+void set_tune_row(fic_ctx *c, int b, int dlog, const fic::TuneRow &row)
+{
+    for (auto &t : c->tune)
+        if (t.b == b && t.dlog == dlog) { t.row = row; return; }
+    c->tune.push_back({b, dlog, row});
+}
+
+// The context's parameters and switches on a plan (before it runs).
+void apply_ctx(const fic_ctx *c, fic::EncodePlan &p)
+{
+    p.tune = tune_row(c, p.g.b, p.g.D);
+    p.dbg = c->dbg;
+}
 
 }  // namespace
 
@@ -152,10 +190,11 @@ template <class T> void put(std::vector<unsigned char> &k, const T &v)
 // descriptor field, the workspace and the counters (field by field, so no
 // padding bytes enter the key).
 std::vector<unsigned char> batch_key(int32_t n, const fic_image_desc *d, const void *ws,
-                                     size_t ws_bytes, const u64 *counters)
+                                     size_t ws_bytes, const u64 *counters, uint32_t dbg)
 {
     std::vector<unsigned char> k;
     put(k, n);
+    put(k, dbg);
     for (int32_t i = 0; i < n; ++i) {
         put(k, d[i].img);
         put(k, d[i].geom.height); put(k, d[i].geom.width); put(k, d[i].geom.pitch);
@@ -262,6 +301,8 @@ fic_status fic_create(int32_t device, fic_ctx **out)
     c->use_graph = true;
     c->cap = nullptr;
     c->side.ns = 0;
+    c->dbg = 0;
+    snprintf(c->arch, sizeof c->arch, "%s", "none");
     if (device >= 0) {
         int n = 0;
         if (hipGetDeviceCount(&n) != hipSuccess || device >= n) {
@@ -277,11 +318,16 @@ fic_status fic_create(int32_t device, fic_ctx **out)
             delete c;
             return FIC_ERR_UNSUPPORTED;
         }
+        snprintf(c->arch, sizeof c->arch, "%s", prop.gcnArchName);
         c->num_cu = prop.multiProcessorCount;
         if (hipSetDevice(device) != hipSuccess || fic::init_search_occupancy() != hipSuccess) {
             delete c;
             return FIC_ERR_DEVICE;
         }
+        // tuned parameters from the cache file named by FIC_TUNE_CACHE, when
+        // it was written for this architecture and these kernels
+        const char *cache = getenv("FIC_TUNE_CACHE");
+        if (cache && *cache) (void)fic_tune_load(c, cache);
     }
     *out = c;
     return FIC_OK;
@@ -398,6 +444,7 @@ fic_status fic_encode_pifs(fic_ctx *ctx, const uint8_t *img, const fic_geom *g,
     fic::EncodePlan p;
     fic::plan_encode(gg, nset == 3, p);
     if (ws_bytes < p.total) return FIC_ERR_WORKSPACE;
+    apply_ctx(ctx, p);
     fic_status st = enter(ctx);
     if (st != FIC_OK) return st;
     return dev_status(fic::run_encode(p, img, perm, lo, hi, kernel, codes, ws, ctx->num_cu,
@@ -439,6 +486,8 @@ fic_status fic_encode_pifs_batch(fic_ctx *ctx, int32_t n_images, const fic_image
     fic::plan_batch(jobs.data(), n_images, bp);
     if (bp.items > (int64_t)0xffffffffll) return FIC_ERR_CAPACITY;   // one 32-bit item queue
     if (ws_bytes < bp.total) return FIC_ERR_WORKSPACE;
+    for (auto &pt : bp.part) apply_ctx(ctx, pt.plan);
+    bp.dbg = ctx->dbg;
     fic_status st = enter(ctx);
     if (st != FIC_OK) return st;
     hipStream_t s = (hipStream_t)stream;
@@ -447,7 +496,7 @@ fic_status fic_encode_pifs_batch(fic_ctx *ctx, int32_t n_images, const fic_image
     if (!ctx->use_graph)
         return dev_status(fic::run_encode_batch(jobs.data(), bp, ws, ctx->num_cu, ctx->counters, s,
                                                 tracer_of(ctx), side));
-    std::vector<unsigned char> key = batch_key(n_images, descs, ws, ws_bytes, ctx->counters);
+    std::vector<unsigned char> key = batch_key(n_images, descs, ws, ws_bytes, ctx->counters, ctx->dbg);
     size_t hit = ctx->graphs.size();
     for (size_t i = 0; i < ctx->graphs.size(); ++i)
         if (ctx->graphs[i].key == key) { hit = i; break; }
@@ -519,6 +568,8 @@ fic_status fic_encode_quadtree(fic_ctx *ctx, const uint8_t *img, const fic_geom 
     fic::QuadPlan qp;
     fic::plan_quadtree(gg1, tol1, gg2, tol2, qp);
     if (ws_bytes < qp.total) return FIC_ERR_WORKSPACE;
+    apply_ctx(ctx, qp.part[0].plan);
+    apply_ctx(ctx, qp.part[1].plan);
     // E is split when E > 4096 * n^2 * rms^2 (fp64, in this operation order),
     // i.e. when it exceeds that bound floored to an integer.
     const double n1 = (double)gg1.n;
@@ -579,6 +630,7 @@ fic_status fic_encode_color(fic_ctx *ctx, const uint8_t *rgb, const fic_geom *g,
     fic::ColorPlan cp;
     fic::plan_color(gg, tol, cp);
     if (ws_bytes < cp.total) return FIC_ERR_WORKSPACE;
+    apply_ctx(ctx, cp.part.plan);
     fic_status st = enter(ctx);
     if (st != FIC_OK) return st;
     fic_code *const codes[3] = {codes_r, codes_g, codes_b};
@@ -633,6 +685,336 @@ fic_status fic_decode_pifs(fic_ctx *ctx, const fic_code *codes, const fic_geom *
     return dev_status(
         fic::run_decode(gg, codes, max_iters, init, out, scratch, iters_done, (hipStream_t)stream,
                         tracer_of(ctx)));
+}
+
+// ---------------------------------------------------------------- debug switches
+fic_status fic_set_debug(fic_ctx *ctx, uint32_t flags)
+{
+    if (!ctx || (flags & ~(uint32_t)(FIC_DEBUG_REVERSE_ITEMS | FIC_DEBUG_VERIFY16)))
+        return FIC_ERR_INVALID_ARG;
+    ctx->dbg = flags;
+    return FIC_OK;
+}
+
+// ---------------------------------------------------------------- autotuner
+#ifndef FIC_KERNEL_HASH
+#define FIC_KERNEL_HASH "unknown"
+#endif
+
+const char *fic_kernel_hash(void) { return FIC_KERNEL_HASH; }
+
+fic_status fic_tune_reset(fic_ctx *ctx)
+{
+    if (!ctx) return FIC_ERR_INVALID_ARG;
+    ctx->tune.clear();
+    if (ctx->device >= 0 && enter(ctx) == FIC_OK) drop_graphs(ctx);
+    return FIC_OK;
+}
+
+fic_status fic_tune_query(fic_ctx *ctx, const fic_geom *g, int32_t pooled, double pool_fraction,
+                          int32_t *chunk_log2, int32_t *flush_at)
+{
+    if (!ctx || !g || !chunk_log2 || !flush_at || !geom_ok(g)) return FIC_ERR_INVALID_ARG;
+    if (pooled && !(pool_fraction >= 0.0 && pool_fraction <= 1.0)) return FIC_ERR_INVALID_ARG;
+    const Geom gg = to_geom(g);
+    const fic::TuneRow row = tune_row(ctx, gg.b, gg.D);
+    const int k = pooled ? fic::tune_bucket_of_fraction(pool_fraction) : 0;
+    *chunk_log2 = row.chunk_log2[k];
+    *flush_at = row.flush_at[k];
+    return FIC_OK;
+}
+
+size_t fic_autotune_workspace_bytes(int32_t n_images, const fic_image_desc *descs)
+{
+    if (n_images < 1 || !descs) return 0;
+    size_t m = 0;
+    for (int32_t i = 0; i < n_images; ++i) {
+        const size_t b = fic_batch_workspace_bytes(1, descs + i);
+        if (b == 0) return 0;
+        m = b > m ? b : m;
+    }
+    return m;
+}
+
+namespace {
+struct TuneImage {
+    fic::BatchJob job;
+    fic::BatchPlan bp;
+    int b, dlog, bucket;
+};
+
+// One whole encode of image `im` (classify, pool, prep, search, finalize)
+// with row `row`, timed by events on s. Blocks the host.
+hipError_t timed_encode(fic_ctx *c, TuneImage &im, const fic::TuneRow &row, void *ws, hipStream_t s,
+                        hipEvent_t e0, hipEvent_t e1, float &ms)
+{
+    im.bp.part[0].plan.tune = row;
+    im.bp.part[0].plan.dbg = 0;
+    im.bp.dbg = 0;
+    hipError_t e = hipEventRecord(e0, s);
+    if (e == hipSuccess) e = fic::run_encode_batch(&im.job, im.bp, ws, c->num_cu, nullptr, s, nullptr, nullptr);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    return e;
+}
+}  // namespace
+
+fic_status fic_autotune(fic_ctx *ctx, int32_t n_images, const fic_image_desc *descs, void *ws,
+                        size_t ws_bytes, int32_t reps, fic_tune_entry *report, int32_t report_cap,
+                        int32_t *report_count, void *stream)
+{
+    if (!ctx || n_images < 1 || !descs || !ws || reps < 1 || reps > 16 || report_cap < 0 ||
+        (report_cap > 0 && !report))
+        return FIC_ERR_INVALID_ARG;
+    for (int32_t i = 0; i < n_images; ++i) {
+        const fic_image_desc &d = descs[i];
+        if (!d.img || !d.codes || !geom_ok(&d.geom) || isnan(d.tol)) return FIC_ERR_INVALID_ARG;
+        if (!key_fits(to_geom(&d.geom))) return FIC_ERR_CAPACITY;
+    }
+    if (ws_bytes < fic_autotune_workspace_bytes(n_images, descs)) return FIC_ERR_WORKSPACE;
+    if (report_count) *report_count = 0;
+    fic_status st = enter(ctx);
+    if (st != FIC_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<TuneImage> ims(n_images);
+    for (int32_t i = 0; i < n_images; ++i) {
+        std::vector<fic::BatchJob> one;
+        batch_jobs(1, descs + i, one);
+        ims[i].job = one[0];
+        fic::plan_batch(&ims[i].job, 1, ims[i].bp);
+        ims[i].b = ims[i].job.g.b;
+        ims[i].dlog = dlog2_of(ims[i].job.g.D);
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return FIC_ERR_DEVICE;
+    }
+    hipError_t e = hipSuccess;
+    // the bucket of every image: one (warm-up) encode, then its pool sum
+    for (auto &im : ims) {
+        float ms = 0.0f;
+        e = timed_encode(ctx, im, tune_row(ctx, im.b, im.job.g.D), ws, s, e0, e1, ms);
+        if (e != hipSuccess) break;
+        const fic::EncodePlan &pl = im.bp.part[0].plan;
+        uint64_t psum = 0;
+        e = hipMemcpy(&psum, (const char *)ws + im.bp.part[0].off_enc + pl.off_ctr + 32, 8,
+                      hipMemcpyDeviceToHost);
+        if (e != hipSuccess) break;
+        im.bucket = fic::tune_bucket(im.job.pooled, psum, im.job.g.R, im.job.g.D);
+    }
+    // one tuning class at a time: (range size, log2 D, bucket); a candidate's
+    // cost is the sum over the class's images of the best of `reps` encodes
+    std::vector<char> done(n_images, 0);
+    int32_t nrep = 0;
+    for (int32_t i = 0; i < n_images && e == hipSuccess; ++i) {
+        if (done[i]) continue;
+        std::vector<int32_t> cls;
+        for (int32_t j = i; j < n_images; ++j)
+            if (!done[j] && ims[j].b == ims[i].b && ims[j].dlog == ims[i].dlog &&
+                ims[j].bucket == ims[i].bucket) {
+                cls.push_back(j);
+                done[j] = 1;
+            }
+        const int k = ims[i].bucket;
+        const fic::TuneRow base = tune_row(ctx, ims[i].b, ims[i].job.g.D);
+        auto cost = [&](const fic::TuneRow &row, float &total) {
+            total = 0.0f;
+            for (int32_t j : cls) {
+                float best = 1e30f;
+                for (int r = 0; r < reps && e == hipSuccess; ++r) {
+                    float ms = 0.0f;
+                    e = timed_encode(ctx, ims[j], row, ws, s, e0, e1, ms);
+                    best = ms < best ? ms : best;
+                }
+                total += best;
+            }
+        };
+        float t_base = 0.0f;
+        cost(base, t_base);
+        fic::TuneRow best = base;
+        float t_best = t_base;
+        // coordinate descent: the item width, then the flush trigger
+        for (int cl = fic::kChunkLog2Min; cl <= fic::kChunkLog2Max && e == hipSuccess; ++cl) {
+            if (cl == best.chunk_log2[k]) continue;
+            fic::TuneRow cand = best;
+            cand.chunk_log2[k] = (int8_t)cl;
+            float t = 0.0f;
+            cost(cand, t);
+            if (t < t_best) { t_best = t; best = cand; }
+        }
+        static const int kFlush[] = {0, 32, 64, 128};
+        for (int fi = 0; fi < 4 && e == hipSuccess; ++fi) {
+            if (kFlush[fi] == best.flush_at[k]) continue;
+            fic::TuneRow cand = best;
+            cand.flush_at[k] = (int16_t)kFlush[fi];
+            float t = 0.0f;
+            cost(cand, t);
+            if (t < t_best) { t_best = t; best = cand; }
+        }
+        if (e != hipSuccess) break;
+        // measure the starting row and the winner again, interleaved, and keep
+        // the winner only if it is still faster
+        float tb = 0.0f, tw = 0.0f, sb = 1e30f, sw = 1e30f;
+        for (int r = 0; r < 2 && e == hipSuccess; ++r) {
+            cost(base, tb);
+            cost(best, tw);
+            sb = tb < sb ? tb : sb;
+            sw = tw < sw ? tw : sw;
+        }
+        if (e != hipSuccess) break;
+        if (!(sw < sb)) { best = base; sw = sb; }
+        set_tune_row(ctx, ims[i].b, ims[i].dlog, best);
+        if (nrep < report_cap) {
+            fic_tune_entry &r = report[nrep];
+            r.range_size = ims[i].b;
+            r.dlog2 = ims[i].dlog;
+            r.bucket = k;
+            r.images = (int32_t)cls.size();
+            r.chunk_log2 = best.chunk_log2[k];
+            r.flush_at = best.flush_at[k];
+            r.base_chunk_log2 = base.chunk_log2[k];
+            r.base_flush_at = base.flush_at[k];
+            r.base_ms = sb;
+            r.tuned_ms = sw;
+        }
+        ++nrep;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    drop_graphs(ctx);                // recorded batches carry the old parameters
+    if (report_count) *report_count = nrep;
+    return dev_status(e);
+}
+
+fic_status fic_tune_save(fic_ctx *ctx, const char *path)
+{
+    if (!ctx || !path) return FIC_ERR_INVALID_ARG;
+    std::string out = "{\n \"format\": \"fic-tune-1\",\n";
+    char line[512];
+    snprintf(line, sizeof line, " \"arch\": \"%s\",\n \"kernel_hash\": \"%s\",\n \"rows\": [",
+             ctx->arch, FIC_KERNEL_HASH);
+    out += line;
+    for (size_t i = 0; i < ctx->tune.size(); ++i) {
+        const auto &t = ctx->tune[i];
+        snprintf(line, sizeof line, "%s\n  {\"range_size\": %d, \"dlog2\": %d, \"chunk_log2\": [",
+                 i ? "," : "", t.b, t.dlog);
+        out += line;
+        for (int k = 0; k < fic::kTuneBuckets; ++k) {
+            snprintf(line, sizeof line, "%s%d", k ? ", " : "", (int)t.row.chunk_log2[k]);
+            out += line;
+        }
+        out += "], \"flush_at\": [";
+        for (int k = 0; k < fic::kTuneBuckets; ++k) {
+            snprintf(line, sizeof line, "%s%d", k ? ", " : "", (int)t.row.flush_at[k]);
+            out += line;
+        }
+        out += "]}";
+    }
+    out += "\n ]\n}\n";
+    FILE *f = fopen(path, "wb");
+    if (!f) return FIC_ERR_INVALID_ARG;
+    const bool ok = fwrite(out.data(), 1, out.size(), f) == out.size();
+    return (fclose(f) == 0 && ok) ? FIC_OK : FIC_ERR_INVALID_ARG;
+}
+
+namespace {
+// The string value of "key" in text (after the key's colon), or "".
+std::string json_str(const char *text, const char *key)
+{
+    std::string k = std::string("\"") + key + "\"";
+    const char *p = strstr(text, k.c_str());
+    if (!p) return "";
+    p = strchr(p + k.size(), ':');
+    if (!p) return "";
+    p = strchr(p, '"');
+    if (!p) return "";
+    const char *q = strchr(p + 1, '"');
+    if (!q) return "";
+    return std::string(p + 1, q);
+}
+// Integer after "key": in [p, end); advances p past it. False if missing.
+bool json_int(const char *&p, const char *end, const char *key, long &v)
+{
+    std::string k = std::string("\"") + key + "\"";
+    const char *q = strstr(p, k.c_str());
+    if (!q || q >= end) return false;
+    q = strchr(q + k.size(), ':');
+    if (!q || q >= end) return false;
+    char *e = nullptr;
+    v = strtol(q + 1, &e, 10);
+    if (e == q + 1) return false;
+    p = e;
+    return true;
+}
+// kTuneBuckets integers of the array after "key".
+bool json_ints(const char *&p, const char *end, const char *key, long *v)
+{
+    std::string k = std::string("\"") + key + "\"";
+    const char *q = strstr(p, k.c_str());
+    if (!q || q >= end) return false;
+    q = strchr(q + k.size(), '[');
+    if (!q || q >= end) return false;
+    ++q;
+    for (int i = 0; i < fic::kTuneBuckets; ++i) {
+        char *e = nullptr;
+        v[i] = strtol(q, &e, 10);
+        if (e == q) return false;
+        q = e;
+        while (*q == ' ' || *q == ',' || *q == '\n') ++q;
+    }
+    if (*q != ']') return false;
+    p = q + 1;
+    return true;
+}
+}  // namespace
+
+fic_status fic_tune_load(fic_ctx *ctx, const char *path)
+{
+    if (!ctx || !path) return FIC_ERR_INVALID_ARG;
+    FILE *f = fopen(path, "rb");
+    if (!f) return FIC_ERR_INVALID_ARG;
+    std::string text;
+    char buf[4096];
+    size_t nr;
+    while ((nr = fread(buf, 1, sizeof buf, f)) > 0) {
+        text.append(buf, nr);
+        if (text.size() > (1u << 20)) break;
+    }
+    fclose(f);
+    if (json_str(text.c_str(), "format") != "fic-tune-1") return FIC_ERR_INVALID_ARG;
+    if (json_str(text.c_str(), "arch") != ctx->arch ||
+        json_str(text.c_str(), "kernel_hash") != FIC_KERNEL_HASH)
+        return FIC_ERR_UNSUPPORTED;   // written for another device or other kernels
+    std::vector<fic_ctx::TuneEntry> rows;
+    const char *p = strstr(text.c_str(), "\"rows\"");
+    const char *end = text.c_str() + text.size();
+    if (!p) return FIC_ERR_INVALID_ARG;
+    for (;;) {
+        const char *q = strstr(p, "\"range_size\"");
+        if (!q) break;
+        long b = 0, dl = 0, cl[fic::kTuneBuckets], fl[fic::kTuneBuckets];
+        if (!json_int(q, end, "range_size", b) || !json_int(q, end, "dlog2", dl) ||
+            !json_ints(q, end, "chunk_log2", cl) || !json_ints(q, end, "flush_at", fl))
+            return FIC_ERR_INVALID_ARG;
+        if ((b != 4 && b != 8 && b != 16) || dl < 0 || dl > 40) return FIC_ERR_INVALID_ARG;
+        fic_ctx::TuneEntry t;
+        t.b = (int32_t)b;
+        t.dlog = (int32_t)dl;
+        for (int k = 0; k < fic::kTuneBuckets; ++k) {
+            if (cl[k] < fic::kChunkLog2Min || cl[k] > fic::kChunkLog2Max || fl[k] < 0 || fl[k] > 256)
+                return FIC_ERR_INVALID_ARG;
+            t.row.chunk_log2[k] = (int8_t)cl[k];
+            t.row.flush_at[k] = (int16_t)fl[k];
+        }
+        rows.push_back(t);
+        p = q;
+    }
+    ctx->tune.clear();
+    for (const auto &t : rows) set_tune_row(ctx, t.b, t.dlog, t.row);
+    if (ctx->device >= 0 && enter(ctx) == FIC_OK) drop_graphs(ctx);
+    return FIC_OK;
 }
 
 }  // extern "C"

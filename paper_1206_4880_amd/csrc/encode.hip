@@ -46,12 +46,10 @@ namespace fic {
 
 namespace {
 
-// Columns per work item. Each item reloads its group's A rows, so wide items
-// cut that traffic, while narrow items balance the uneven work of pooled
-// searches: exhaustive jobs take 16384 columns (at 1024^2 the same time as
-// 4096 at 45% of the L2 fetches), pooled jobs 4096.
-constexpr int kChunkExhaustive = 16384;
-constexpr int kChunkPooled = 4096;
+// Columns per work item: 2^chunk_log2 from the image's tuning row and pool-
+// fraction bucket, chosen on the device (TuneRow). Each item reloads its
+// group's A rows, so wide items cut that traffic, while narrow items balance
+// the uneven work of pooled searches.
 constexpr int kBminBlock = 1024; // perm entries per block-minimum
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -439,18 +437,22 @@ struct SearchArgs {
     const uint32_t *n_items;
     u64 *keys;
     int shift;
+    int flush_at;                // early flush trigger (0: only when the queue is full)
 };
 
 // Per group: the union [L, H) of its active ranges' intervals (rounded to
 // column blocks of width bw, a power of two) and their intersection
 // [ilo, ihi) (blocks inside it need no per-range mask). Groups without an
 // active range get L = H = Dp.
+// Also adds the group's pool sizes to *pool_sum (zeroed before), from which
+// the work list picks its parameters.
 __global__ void k_group_bounds(const RangeStat *__restrict__ rs, int64_t G, int GR, uint32_t Dp,
-                               uint32_t bw, uint4 *__restrict__ grp)
+                               uint32_t bw, uint4 *__restrict__ grp, u64 *pool_sum)
 {
     const int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gi >= G) return;
     uint32_t L = 0xffffffffu, H = 0, ilo = 0, ihi = 0xffffffffu;
+    u64 psum = 0;
     bool any = false;
     for (int r = 0; r < GR; ++r) {
         const RangeStat st = rs[gi * GR + r];
@@ -460,18 +462,42 @@ __global__ void k_group_bounds(const RangeStat *__restrict__ rs, int64_t G, int 
         H = max(H, st.hi);
         ilo = max(ilo, st.lo);
         ihi = min(ihi, st.hi);
+        psum += st.hi - st.lo;
     }
     grp[gi] = any ? make_uint4(L & ~(bw - 1u), (H + bw - 1u) & ~(bw - 1u), ilo, ihi)
                   : make_uint4(Dp, Dp, 0, 0);
+    if (psum) atomicAdd(pool_sum, psum);
+}
+
+// Columns per work item and flush trigger of an image, from its tuning row
+// and the pool-fraction bucket of its pool sizes (exact integer sum).
+struct ItemParams { uint32_t chunk; int flush_at; };
+__device__ inline ItemParams item_params(const TuneRow &t, int pooled, const u64 *pool_sum,
+                                         int64_t R, int64_t D)
+{
+    const int b = tune_bucket(pooled, pooled ? *pool_sum : 0ull, R, D);
+    ItemParams ip;
+    ip.chunk = 1u << t.chunk_log2[b];
+    ip.flush_at = t.flush_at[b];
+    return ip;
 }
 
 // Per column chunk c: the run of groups [gf, gl] that touch it (both ends
 // of the group intervals are monotone in the group index), and its length.
-__global__ void k_chunk_span(const uint4 *__restrict__ grp, int64_t G, int64_t NC, uint32_t chunk,
+// NC counts chunks of the narrowest item width; with wider items the chunks
+// past the lattice get no groups.
+__global__ void k_chunk_span(const uint4 *__restrict__ grp, int64_t G, int64_t NC, TuneRow tune,
+                             int pooled, const u64 *__restrict__ pool_sum, int64_t R, int64_t D,
                              uint32_t *__restrict__ cnt, uint32_t *__restrict__ gfirst)
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= NC) return;
+    const uint32_t chunk = item_params(tune, pooled, pool_sum, R, D).chunk;
+    if ((uint64_t)c * chunk >= (uint64_t)D) {   // past the lattice (also past its padding)
+        cnt[c] = 0;
+        gfirst[c] = 0;
+        return;
+    }
     const uint32_t c0 = (uint32_t)c * chunk, c1 = c0 + chunk;
     int64_t a = 0, b = G;                    // active groups: a prefix [0, G_act)
     while (a < b) { const int64_t m = (a + b) >> 1; if (grp[m].x < grp[m].y) a = m + 1; else b = m; }
@@ -492,13 +518,19 @@ __global__ void k_chunk_span(const uint4 *__restrict__ grp, int64_t G, int64_t N
 // in each XCD's L2.
 // Thread 0 also publishes the image's table entry.
 __global__ void k_emit_items(const uint4 *__restrict__ grp, const uint32_t *__restrict__ chunkoff,
-                             const uint32_t *__restrict__ gfirst, int64_t NC, uint32_t chunk,
+                             const uint32_t *__restrict__ gfirst, int64_t NC, TuneRow tune,
+                             int pooled, const u64 *__restrict__ pool_sum, int64_t R, int64_t D,
                              const uint32_t *__restrict__ total, int64_t max_items,
                              WorkItem *__restrict__ items, SearchArgs args,
                              SearchArgs *__restrict__ slot)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) *slot = args;
+    const ItemParams ip = item_params(tune, pooled, pool_sum, R, D);
+    const uint32_t chunk = ip.chunk;
+    if (i == 0) {
+        args.flush_at = ip.flush_at;
+        *slot = args;
+    }
     if (i >= max_items || i >= (int64_t)*total) return;
     int64_t a = 0, b = NC;                   // last c with chunkoff[c] <= i
     while (b - a > 1) { const int64_t m = (a + b) >> 1; if (chunkoff[m] <= (uint32_t)i) a = m; else b = m; }
@@ -555,11 +587,12 @@ __global__ __launch_bounds__(256) void k_item_bases(const SearchArgs *__restrict
 constexpr int kQueue = 256;          // queued cells per wave (capacity)
 // 16x16 ranges pass few cells: half the capacity leaves LDS for wider stages
 template <int B> constexpr int queue16_cap() { return B == 16 ? 128 : kQueue; }
-// At 8x8, a block that leaves a wave's worth of cells queued flushes them at
-// once: every flush publishes the wave's best keys, takes the other waves',
-// and tightens the thresholds (narrow pools pass many cells early). At 4x4
-// and 16x16 the extra flushes cost more than they save.
-constexpr int kFlushAt = 64;
+// A block that leaves at least flush_at cells queued (SearchArgs::flush_at,
+// chosen per image; 0 = only when the queue is full) flushes them at once:
+// every flush publishes the wave's best keys, takes the other waves', and
+// tightens the thresholds (narrow pools pass many cells early). By default
+// only 8x8 ranges flush early (at 64): at 4x4 and 16x16 the extra flushes
+// cost more than they save.
 // Word 3 of a raw buffer descriptor on gfx9-family GPUs (32-bit data format,
 // no swizzle): byte offsets, no stride.
 constexpr int kBufWord3 = 0x00020000;
@@ -617,6 +650,7 @@ template <int B> struct WaveState {
     uint32_t lo[Cfg<B>::MB], hi[Cfg<B>::MB];
     uint32_t grp;
     uint32_t qn;                     // queued half cells (wave-uniform)
+    uint32_t flush_at;               // early flush trigger (0: off)
     u64 survivors;
     u64 screened;
 };
@@ -841,7 +875,7 @@ __device__ __forceinline__ void screen_acc(const SearchArgs *ta, WaveState<B> &s
     if (!wave_any(hit)) return;
 #pragma unroll
     for (int b = 0; b < MW; ++b) queue_rowblock<B>(ta, st, qu, b, pass[b], acc[b], p);
-    if (st.qn >= (uint32_t)kFlushAt) flush_and_refresh16<B>(ta, st, qu);
+    if (st.flush_at && st.qn >= st.flush_at) flush_and_refresh16<B>(ta, st, qu);
 }
 
 template <int B, bool MASK>
@@ -883,21 +917,81 @@ __device__ __forceinline__ void mma_block_lds(const WaveState<B> &st,
     for (int ks = 0; ks < KS; ++ks) __builtin_amdgcn_sched_group_barrier(0x008, MW, 0);   // MFMAs
 }
 
+// Rounding check of the one-accumulator screen on the matrix cores (the
+// context's verify switch): every value of the block is recomputed from the
+// exact 64-term chunks, summed in int32 (exact), and its distance from the
+// one-accumulator FP32 sum is compared with the bound the threshold is
+// lowered by, e*u + e/2 with e = (n + KS) 2^-23 sqrt(n) ||A|| (screen_t_b;
+// ||B|| <= sqrt(n) (u + 1/2), u undone from its rounding down). Counts, in
+// vc: [0] values over the bound, [1] values checked, [2] the largest
+// error / bound seen, in units of 2^-20 (atomic maximum).
+template <int B>
+__device__ __noinline__ void verify_block_lds(const WaveState<B> &st, const Queue16<B> *qu,
+                                              const typename WaveState<B>::frag_t *lb,
+                                              const float4_t (&acc)[Cfg<B>::MB], float u, u64 *vc)
+{
+    using C = Cfg<B>;
+    constexpr int MW = C::MB, KS = C::KS, NCH = C::NCH, KPC = KS / NCH, n = C::n;
+    const int lane = threadIdx.x & 63;
+    u64 bad = 0, seen = 0, worst = 0;
+#pragma unroll
+    for (int b = 0; b < MW; ++b) {
+        float4_t ax[NCH];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c)
+#pragma unroll
+            for (int kk = 0; kk < KPC; ++kk) {
+                const float4_t z = {0.f, 0.f, 0.f, 0.f};
+                ax[c] = mma(st.af[b][c * KPC + kk], lb[(c * KPC + kk) * 64 + lane], kk ? ax[c] : z);
+            }
+        const double srr = (double)qu->srr[tile_range<B>(b, lane)];
+        const double na = sqrt(srr / n + n / 4.0);
+        const double e = (double)(n + KS) * 0x1p-23 * sqrt((double)n) * na;
+        const double bound = e * ((double)u * (1.0 + 0x1p-19)) + e * 0.5;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            int32_t sx = 0;
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) sx += (int32_t)ax[c][v];
+            const double err = fabs((double)acc[b][v] - (double)sx);
+            seen += 1;
+            if (err > bound) bad += 1;
+            const double ratio = bound > 0.0 ? err / bound : (err > 0.0 ? 1e9 : 0.0);
+            const u64 q = (u64)fmin(ratio * 1048576.0, 1e18);
+            worst = q > worst ? q : worst;
+        }
+    }
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        bad += __shfl_xor(bad, off);
+        seen += __shfl_xor(seen, off);
+        const u64 o = __shfl_xor(worst, off);
+        worst = o > worst ? o : worst;
+    }
+    if (lane == 0 && vc) {
+        atomicAdd(&vc[0], bad);
+        atomicAdd(&vc[1], seen);
+        atomicMax(&vc[2], worst);
+    }
+}
+
 // 16x16 ranges, B fragments of the block in LDS (lane order). The hot test
 // screens the one-accumulator sums; only a block where some lane passes
 // recomputes the exact 64-term chunk sums (re-reading its fragments) and
 // goes through the exact screen and queue.
-template <int B, bool MASK>
+template <int B, bool MASK, bool VERIFY>
 __device__ __forceinline__ void screen_block_lds(const SearchArgs *ta, WaveState<B> &st,
                                                  Queue16<B> *qu,
                                                  const typename WaveState<B>::frag_t *lb,
-                                                 const float4_t (&acc)[Cfg<B>::MB], float u, int cb)
+                                                 const float4_t (&acc)[Cfg<B>::MB], float u, int cb,
+                                                 u64 *vc)
 {
     using C = Cfg<B>;
     constexpr int MW = C::MB, KS = C::KS;
     const int lane = threadIdx.x & 63, col = lane & 15;
     const float slack = screen_slack<B>();
     const uint32_t p = (uint32_t)cb * 16 + col;
+    if constexpr (VERIFY) verify_block_lds<B>(st, qu, lb, acc, u, vc);
     bool hit = false;
     float dmax = -__builtin_inff();
 #pragma unroll
@@ -931,6 +1025,7 @@ __device__ __forceinline__ void screen_block_lds(const SearchArgs *ta, WaveState
         if (MASK) h = h && p >= st.lo[b] && p < st.hi[b];
         queue_rowblock<B>(ta, st, qu, b, h, ax, p);
     }
+    if (st.flush_at && st.qn >= st.flush_at) flush_and_refresh16<B>(ta, st, qu);
 }
 
 // Column blocks [cb_begin, cb_end) against the wave's A rows. The B
@@ -1019,7 +1114,7 @@ template <int B>
 __global__ __launch_bounds__(256, 2) void k_search_mfma(const SearchArgs *__restrict__ tab,
                                                         const uint32_t *__restrict__ base,
                                                         int32_t n_img, uint32_t *item_ctr,
-                                                        u64 *counters)
+                                                        u64 *counters, uint32_t dbg)
 {
     using C = Cfg<B>;
     constexpr int MW = C::MB, KS = C::KS, GR = C::GR;
@@ -1038,6 +1133,7 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma(const SearchArgs *__rest
         if (lane == 0) item = atomicAdd(item_ctr, 1u);
         item = __builtin_amdgcn_readfirstlane(item);
         if (item >= nitems) break;
+        if (dbg & kDbgReverse) item = nitems - 1u - item;   // order-independence check
         int ia = 0, ib = n_img;              // last image whose base <= item
         while (ib - ia > 1) {
             const int m = (ia + ib) >> 1;
@@ -1047,6 +1143,7 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma(const SearchArgs *__rest
         const SearchArgs *ta = tab + ia;
         const SearchArgs a = *ta;
         const WorkItem wi = a.items[item - base[ia]];
+        st.flush_at = (uint32_t)a.flush_at;
         st.grp = wi.grp;
         const frag_t *ap = (const frag_t *)a.A + (int64_t)st.grp * MW * KS * 64 + lane;
 #pragma unroll
@@ -1117,11 +1214,11 @@ constexpr int kStage16 = 4;          // 16-column blocks per LDS stage
 
 typedef __attribute__((address_space(3))) void lds_void;
 
-template <int B>
+template <int B, bool VERIFY>
 __global__ __launch_bounds__(256, 2) void k_search_lds16(const SearchArgs *__restrict__ tab,
                                                          const uint32_t *__restrict__ base,
                                                          int32_t n_img, uint32_t *item_ctr,
-                                                         u64 *counters)
+                                                         u64 *counters, uint32_t dbg)
 {
     using C = Cfg<B>;
     constexpr int MW = C::MB, KS = C::KS, GR = C::GR, SB = kStage16, FR = SB * KS;
@@ -1142,9 +1239,10 @@ __global__ __launch_bounds__(256, 2) void k_search_lds16(const SearchArgs *__res
     for (;;) {
         if (threadIdx.x == 0) sItem = atomicAdd(item_ctr, 1u);
         __syncthreads();
-        const uint32_t item = sItem;
+        uint32_t item = sItem;
         __syncthreads();
         if (item >= nitems) break;
+        if (dbg & kDbgReverse) item = nitems - 1u - item;   // order-independence check
         int ia = 0, ib = n_img;              // last image whose base <= item
         while (ib - ia > 1) {
             const int m = (ia + ib) >> 1;
@@ -1154,6 +1252,7 @@ __global__ __launch_bounds__(256, 2) void k_search_lds16(const SearchArgs *__res
         const SearchArgs *ta = tab + ia;
         const SearchArgs a = *ta;
         const WorkItem wi = a.items[item - base[ia]];
+        st.flush_at = (uint32_t)a.flush_at;
         st.grp = __builtin_amdgcn_readfirstlane(wi.grp) * 4 + (uint32_t)w;
         const frag_t *ap = (const frag_t *)a.A + (int64_t)st.grp * MW * KS * 64 + lane;
 #pragma unroll
@@ -1242,9 +1341,11 @@ __global__ __launch_bounds__(256, 2) void k_search_lds16(const SearchArgs *__res
                 float4_t acc[MW];
                 mma_block_lds<B>(st, cB + j * KS * 64, acc);
                 if (cb >= ib0 && cb < ib1)
-                    screen_block_lds<B, false>(ta, st, qu, cB + j * KS * 64, acc, u, cb);
+                    screen_block_lds<B, false, VERIFY>(ta, st, qu, cB + j * KS * 64, acc, u, cb,
+                                                       counters ? counters + 4 : nullptr);
                 else
-                    screen_block_lds<B, true>(ta, st, qu, cB + j * KS * 64, acc, u, cb);
+                    screen_block_lds<B, true, VERIFY>(ta, st, qu, cB + j * KS * 64, acc, u, cb,
+                                                      counters ? counters + 4 : nullptr);
             }
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
@@ -1294,6 +1395,7 @@ template <int B> struct Wave32 {
     uint32_t lo[MB][2], hi[MB][2];
     uint32_t grp;
     uint32_t qn;                     // queued cells (wave-uniform)
+    uint32_t flush_at;               // early flush trigger (0: off)
     u64 survivors, screened;
 };
 
@@ -1462,6 +1564,7 @@ __device__ __forceinline__ void screen32(const SearchArgs &a, const SearchArgs *
             }
             st.qn += cnt;
         }
+    if (st.flush_at && st.qn >= st.flush_at) flush_and_refresh<B>(ta, st, qu);
 }
 
 // Column blocks [cb_begin, cb_end): the B fragments and u of the block PD
@@ -1554,7 +1657,7 @@ template <int B>
 __global__ __launch_bounds__(256, 2) void k_search_mfma32(const SearchArgs *__restrict__ tab,
                                                           const uint32_t *__restrict__ base,
                                                           int32_t n_img, uint32_t *item_ctr,
-                                                          u64 *counters)
+                                                          u64 *counters, uint32_t dbg)
 {
     constexpr int MB = Cfg<B>::MB, KS = Cfg<B>::KS, GR = Cfg<B>::GR;
     __shared__ Queue32<B> queues[4];
@@ -1571,6 +1674,7 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma32(const SearchArgs *__re
         if (lane == 0) item = atomicAdd(item_ctr, 1u);
         item = __builtin_amdgcn_readfirstlane(item);
         if (item >= nitems) break;
+        if (dbg & kDbgReverse) item = nitems - 1u - item;   // order-independence check
         int ia = 0, ib = n_img;              // last image whose base <= item
         while (ib - ia > 1) {
             const int m = (ia + ib) >> 1;
@@ -1580,6 +1684,7 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma32(const SearchArgs *__re
         const SearchArgs *ta = tab + ia;
         const SearchArgs a = *ta;
         const WorkItem wi = a.items[item - base[ia]];
+        st.flush_at = (uint32_t)a.flush_at;
         st.grp = wi.grp;
         const half8_t *ap = (const half8_t *)a.A + (int64_t)st.grp * MB * KS * 64 + lane;
 #pragma unroll
@@ -1648,7 +1753,7 @@ template <int B> const void *search_kernel()
     if constexpr (Cfg<B>::MR == 32)
         return reinterpret_cast<const void *>(&k_search_mfma32<B>);
     else if constexpr (B == 16)
-        return reinterpret_cast<const void *>(&k_search_lds16<B>);
+        return reinterpret_cast<const void *>(&k_search_lds16<B, false>);
     else
         return reinterpret_cast<const void *>(&k_search_mfma<B>);
 }
@@ -1886,19 +1991,20 @@ hipError_t prep_b(const EncodePlan &p, const uint8_t *img, const uint32_t *perm,
     trace(tr, FIC_STAGE_WORKLIST, 1, s);
     hipLaunchKernelGGL(k_seed<B>, dim3(blocks_for(p.Rp * 64, th)), dim3(th), 0, s, A, Bm, rs, eps,
                        sdd, dom, p.Rp, perm, bmin, p.shift, keys, counters);
+    u64 *pool_sum = (u64 *)(ctr + 8);     // zeroed with the counters above
     hipLaunchKernelGGL(k_group_bounds, dim3(blocks_for(p.IG, th)), dim3(th), 0, s, rs, p.IG,
-                       (int)(p.GR * p.IGW), (uint32_t)p.Dp, (uint32_t)Cfg<B>::MR, grp);
+                       (int)(p.GR * p.IGW), (uint32_t)p.Dp, (uint32_t)Cfg<B>::MR, grp, pool_sum);
     hipLaunchKernelGGL(k_chunk_span, dim3(blocks_for(p.NC, th)), dim3(th), 0, s, grp, p.IG, p.NC,
-                       (uint32_t)p.chunk, chunkcnt, chunkfill);
+                       p.tune, p.pooled, (const u64 *)pool_sum, g.R, g.D, chunkcnt, chunkfill);
     // exclusive scan of the per-chunk counts; the total is the item count
     const hipError_t se = scan_u32(chunkcnt, p.NC, ctr + 1, w + p.off_scan, s);
     if (se != hipSuccess) return se;
     SearchArgs a;
     a.A = A; a.Bm = Bm; a.u = u; a.eps = eps; a.sdd = sdd; a.dom = dom; a.rs = rs; a.grp = grp;
-    a.items = items; a.n_items = ctr + 1; a.keys = keys; a.shift = p.shift;
+    a.items = items; a.n_items = ctr + 1; a.keys = keys; a.shift = p.shift; a.flush_at = 0;
     hipLaunchKernelGGL(k_emit_items, dim3(blocks_for(p.max_items, th)), dim3(th), 0, s, grp,
-                       chunkcnt, chunkfill, p.NC, (uint32_t)p.chunk, ctr + 1, p.max_items, items, a,
-                       slot);
+                       chunkcnt, chunkfill, p.NC, p.tune, p.pooled, (const u64 *)pool_sum, g.R,
+                       g.D, ctr + 1, p.max_items, items, a, slot);
     trace(tr, FIC_STAGE_WORKLIST, 0, s);
     return hipGetLastError();
 }
@@ -1919,7 +2025,7 @@ template <int B> hipError_t occupancy_of(int &out)
 // B). item_ctr must read 0; base holds n + 1 entries.
 template <int B>
 hipError_t search_b(const SearchArgs *tab, int32_t n, uint32_t *base, uint32_t *item_ctr,
-                    int num_cu, u64 *counters, hipStream_t s, const Tracer *tr)
+                    int num_cu, u64 *counters, uint32_t dbg, hipStream_t s, const Tracer *tr)
 {
     // persistent grid: as many workgroups as stay resident on every CU
     const int per_cu = g_per_cu[B == 4 ? 0 : B == 8 ? 1 : 2];
@@ -1928,13 +2034,17 @@ hipError_t search_b(const SearchArgs *tab, int32_t n, uint32_t *base, uint32_t *
     trace(tr, FIC_STAGE_SEARCH, 1, s);
     if constexpr (Cfg<B>::MR == 32)
         hipLaunchKernelGGL(k_search_mfma32<B>, dim3(per_cu * num_cu), dim3(256), 0, s, tab,
-                           (const uint32_t *)base, n, item_ctr, counters);
-    else if constexpr (B == 16)
-        hipLaunchKernelGGL(k_search_lds16<B>, dim3(per_cu * num_cu), dim3(256), 0, s, tab,
-                           (const uint32_t *)base, n, item_ctr, counters);
-    else
+                           (const uint32_t *)base, n, item_ctr, counters, dbg);
+    else if constexpr (B == 16) {
+        if (dbg & kDbgVerify16)
+            hipLaunchKernelGGL((k_search_lds16<B, true>), dim3(per_cu * num_cu), dim3(256), 0, s,
+                               tab, (const uint32_t *)base, n, item_ctr, counters, dbg);
+        else
+            hipLaunchKernelGGL((k_search_lds16<B, false>), dim3(per_cu * num_cu), dim3(256), 0, s,
+                               tab, (const uint32_t *)base, n, item_ctr, counters, dbg);
+    } else
         hipLaunchKernelGGL(k_search_mfma<B>, dim3(per_cu * num_cu), dim3(256), 0, s, tab,
-                           (const uint32_t *)base, n, item_ctr, counters);
+                           (const uint32_t *)base, n, item_ctr, counters, dbg);
     trace(tr, FIC_STAGE_SEARCH, 0, s);
     return hipGetLastError();
 }
@@ -1962,7 +2072,7 @@ hipError_t run_encode_b(const EncodePlan &p, const uint8_t *img, const uint32_t 
     uint32_t *ctr = (uint32_t *)(w + p.off_ctr);   // [0] item counter, [1] items, [2..3] bases
     SearchArgs *slot = (SearchArgs *)(w + p.off_args);
     hipError_t e = prep_b<B>(p, img, perm, lo, hi, ws, counters, slot, s, tr);
-    if (e == hipSuccess) e = search_b<B>(slot, 1, ctr + 2, ctr, num_cu, counters, s, tr);
+    if (e == hipSuccess) e = search_b<B>(slot, 1, ctr + 2, ctr, num_cu, counters, p.dbg, s, tr);
     if (e == hipSuccess) e = finalize_b<B>(p, img, ws, codes, s, tr);
     return e;
 }
@@ -1999,8 +2109,7 @@ void plan_encode(const Geom &g, int pooled, EncodePlan &p)
     p.G = p.Rp / p.GR;
     p.IG = p.G / p.IGW;
     p.Dp = (g.D + mr - 1) / mr * mr;
-    p.chunk = pooled ? kChunkPooled : kChunkExhaustive;
-    p.NC = (p.Dp + p.chunk - 1) / p.chunk;
+    p.NC = (p.Dp + ((int64_t)1 << kChunkLog2Min) - 1) >> kChunkLog2Min;
     p.max_items = p.IG * p.NC;
     int dbits = 1;
     while (((int64_t)1 << dbits) < g.D) ++dbits;
@@ -2029,6 +2138,8 @@ void plan_encode(const Geom &g, int pooled, EncodePlan &p)
     p.off_scan = take(scan_ws_bytes(p.NC));
     p.total = o;
     p.sel = nullptr;
+    p.tune = default_tune_row(g.b);
+    p.dbg = 0;
 }
 
 hipError_t run_encode(const EncodePlan &p, const uint8_t *img, const uint32_t *perm,
@@ -2057,6 +2168,7 @@ int size_group(int b) { return b == 4 ? 0 : b == 8 ? 1 : 2; }
 void plan_batch(const BatchJob *jobs, int32_t n, BatchPlan &bp)
 {
     bp.n = n;
+    bp.dbg = 0;
     bp.slot.assign(n, 0);
     bp.part.assign(n, BatchPart{});
     std::vector<int32_t> idx(n);
@@ -2154,9 +2266,9 @@ hipError_t run_encode_batch(const BatchJob *jobs, const BatchPlan &bp, void *ws,
         uint32_t *gb = base + (size_t)gi * (bp.n + 1);
         uint32_t *gc = ctr + gi * 64;
         switch (kSizes[gi]) {
-        case 4: e = search_b<4>(t, bp.group_count[gi], gb, gc, num_cu, counters, s, tr); break;
-        case 8: e = search_b<8>(t, bp.group_count[gi], gb, gc, num_cu, counters, s, tr); break;
-        default: e = search_b<16>(t, bp.group_count[gi], gb, gc, num_cu, counters, s, tr); break;
+        case 4: e = search_b<4>(t, bp.group_count[gi], gb, gc, num_cu, counters, bp.dbg, s, tr); break;
+        case 8: e = search_b<8>(t, bp.group_count[gi], gb, gc, num_cu, counters, bp.dbg, s, tr); break;
+        default: e = search_b<16>(t, bp.group_count[gi], gb, gc, num_cu, counters, bp.dbg, s, tr); break;
         }
     }
     for (int32_t k = 0; k < bp.n && e == hipSuccess; ++k) {

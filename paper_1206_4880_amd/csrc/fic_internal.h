@@ -99,6 +99,57 @@ constexpr uint32_t kIdle = kFlat | kPad | kEmpty | kSkip;             // never s
 struct WorkItem { uint32_t grp, c0, c1, pad; };
 
 // ---------------------------------------------------------------------------
+// Search parameters chosen per image ON THE DEVICE from its pool fraction:
+// bucket 0 is exhaustive search; a pooled image with
+// f = (sum of pool sizes) / (R * D) falls in bucket 1 + floor(-log2 f),
+// clamped to [1, kTuneBuckets - 1]. Per bucket: the columns of a work item
+// (2^chunk_log2, kChunkLog2Min..kChunkLog2Max) and the early flush trigger of
+// the search queue (flush once at least flush_at half cells (4x4: cells) are
+// queued; 0 = only when the queue is full). A row serves one (range size,
+// log2 D) class; the autotuner fills rows, defaults are below.
+constexpr int kTuneBuckets = 6;
+constexpr int kChunkLog2Min = 11, kChunkLog2Max = 16;
+struct TuneRow {
+    int8_t chunk_log2[kTuneBuckets];
+    int16_t flush_at[kTuneBuckets];
+};
+// Exhaustive jobs 16384-column items, pooled 4096 (narrow pools need the
+// finer balance); the early flush at 64 queued half cells only at 8x8.
+inline TuneRow default_tune_row(int b)
+{
+    TuneRow r;
+    for (int k = 0; k < kTuneBuckets; ++k) {
+        r.chunk_log2[k] = (int8_t)(k == 0 ? 14 : 12);
+        r.flush_at[k] = (int16_t)(b == 8 ? 64 : 0);
+    }
+    return r;
+}
+// Bucket of a pooled image's pool fraction f (1 for f >= 1/2, 2 for
+// [1/4, 1/2), ..., kTuneBuckets - 1 below).
+__host__ __device__ inline int tune_bucket_of_fraction(double f)
+{
+    int b = 1;
+    double edge = 0.5;
+    while (b < kTuneBuckets - 1 && f < edge) {
+        ++b;
+        edge *= 0.5;
+    }
+    return b;
+}
+// The bucket of an image: 0 when exhaustive, else that of
+// f = pool_sum / (R * D) in fp64 (pool_sum: the exact integer sum of the
+// searched ranges' pool sizes). Host and device use this same rule.
+__host__ __device__ inline int tune_bucket(int pooled, uint64_t pool_sum, int64_t R, int64_t D)
+{
+    if (!pooled) return 0;
+    return tune_bucket_of_fraction((double)pool_sum / ((double)R * (double)D));
+}
+
+// Debug switches of a context (fic_set_debug): consume the work items in
+// reverse order; run the 16x16 search's rounding check.
+constexpr uint32_t kDbgReverse = 1u, kDbgVerify16 = 2u;
+
+// ---------------------------------------------------------------------------
 // The isometries: T_q(d)[i][j] = d[src], src per q (0 identity, 1 rot90 cw,
 // 2 rot180, 3 rot270 cw, 4 mirror left-right, 5 mirror up-down, 6 transpose,
 // 7 anti-transpose).
@@ -244,7 +295,7 @@ struct EncodePlan {
     int pooled;
     int64_t Rp, Dp, G, GR, NC;   // padded ranges/columns, groups, ranges per group, chunks
     int64_t IGW, IG;              // groups per work item (one per wave of a workgroup), item groups
-    int32_t chunk, shift;
+    int32_t shift;                // NC: chunks at the narrowest item (2^kChunkLog2Min columns)
     int64_t max_items;
     size_t off_A, off_rs, off_order, off_B, off_u, off_eps, off_sdd, off_dom, off_keys,
         off_items, off_ctr, off_args, off_chunkcnt, off_chunkfill, off_grp, off_bmin, off_S,
@@ -252,6 +303,8 @@ struct EncodePlan {
     // (dev) per range, raster order: 0 = not coded (its code gets flag bit 2);
     // null = every range. Set by the caller after plan_encode.
     const uint8_t *sel;
+    TuneRow tune;                 // parameters per pool-fraction bucket
+    uint32_t dbg;                 // kDbg* switches
 };
 hipError_t init_search_occupancy();   // once per process, before any search launch
 void plan_encode(const Geom &g, int pooled, EncodePlan &p);
@@ -280,6 +333,7 @@ struct BatchPlan {
     int32_t group_first[3], group_count[3];   // table runs for B = 4, 8, 16
     size_t off_tab, off_base, off_ctr, total;
     int64_t items;                   // upper bound on the work items of all images
+    uint32_t dbg;                    // kDbg* switches of the searches
 };
 // Side streams for the per-image preparation of a batch: forked from the
 // calling stream by one event and joined back before the searches (under

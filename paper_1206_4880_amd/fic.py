@@ -39,6 +39,17 @@ class ImageDesc(ctypes.Structure):
                 ("codes", ctypes.c_void_p)]
 
 
+class TuneEntry(ctypes.Structure):
+    _fields_ = [("range_size", ctypes.c_int32), ("dlog2", ctypes.c_int32),
+                ("bucket", ctypes.c_int32), ("images", ctypes.c_int32),
+                ("chunk_log2", ctypes.c_int32), ("flush_at", ctypes.c_int32),
+                ("base_chunk_log2", ctypes.c_int32), ("base_flush_at", ctypes.c_int32),
+                ("base_ms", ctypes.c_float), ("tuned_ms", ctypes.c_float)]
+
+
+DEBUG_REVERSE_ITEMS, DEBUG_VERIFY16 = 1, 2
+
+
 _lib = None
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
@@ -90,6 +101,16 @@ def lib():
         "fic_decode_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Geom)]),
         "fic_decode_pifs": (_st, [_vp, _vp, ctypes.POINTER(Geom), _i32, _vp, _vp, _vp,
                                   ctypes.c_size_t, _vp, _vp]),
+        "fic_set_debug": (_st, [_vp, ctypes.c_uint32]),
+        "fic_autotune_workspace_bytes": (ctypes.c_size_t, [_i32, ctypes.POINTER(ImageDesc)]),
+        "fic_autotune": (_st, [_vp, _i32, ctypes.POINTER(ImageDesc), _vp, ctypes.c_size_t, _i32,
+                               ctypes.POINTER(TuneEntry), _i32, ctypes.POINTER(_i32), _vp]),
+        "fic_tune_save": (_st, [_vp, ctypes.c_char_p]),
+        "fic_tune_load": (_st, [_vp, ctypes.c_char_p]),
+        "fic_tune_reset": (_st, [_vp]),
+        "fic_tune_query": (_st, [_vp, ctypes.POINTER(Geom), _i32, ctypes.c_double,
+                                 ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+        "fic_kernel_hash": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -106,7 +127,9 @@ EXPORTED = ("fic_create", "fic_destroy", "fic_status_string", "fic_set_counters"
             "fic_batch_workspace_bytes", "fic_encode_pifs_batch", "fic_set_batch_graph",
             "fic_decode_workspace_bytes", "fic_decode_pifs", "fic_quadtree_workspace_bytes",
             "fic_encode_quadtree", "fic_decode_quadtree", "fic_packed_words", "fic_pack_codes",
-            "fic_unpack_codes", "fic_color_workspace_bytes", "fic_encode_color")
+            "fic_unpack_codes", "fic_color_workspace_bytes", "fic_encode_color",
+            "fic_set_debug", "fic_autotune_workspace_bytes", "fic_autotune", "fic_tune_save",
+            "fic_tune_load", "fic_tune_reset", "fic_tune_query", "fic_kernel_hash")
 
 
 def status_string(status):
@@ -167,6 +190,29 @@ class Context:
 
     def set_batch_graph(self, enable):
         _check(lib().fic_set_batch_graph(self.handle, 1 if enable else 0), "fic_set_batch_graph")
+
+    def set_debug(self, flags):
+        _check(lib().fic_set_debug(self.handle, int(flags)), "fic_set_debug")
+
+    def tune_save(self, path):
+        _check(lib().fic_tune_save(self.handle, os.fsencode(path)), "fic_tune_save")
+
+    def tune_load(self, path):
+        """Load a tuning cache; returns the status (OK, ERR_UNSUPPORTED for a
+        cache of another device or other kernels, ERR_INVALID_ARG)."""
+        return int(lib().fic_tune_load(self.handle, os.fsencode(path)))
+
+    def tune_reset(self):
+        _check(lib().fic_tune_reset(self.handle), "fic_tune_reset")
+
+    def tune_query(self, height, width, range_size, domain_step, pooled=False, pool_fraction=1.0):
+        """(chunk_log2, flush_at) an encode of this geometry would use."""
+        g = make_geom(height, width, range_size, domain_step)
+        cl, fl = _i32(0), _i32(0)
+        _check(lib().fic_tune_query(self.handle, ctypes.byref(g), 1 if pooled else 0,
+                                    float(pool_fraction), ctypes.byref(cl), ctypes.byref(fl)),
+               "fic_tune_query")
+        return int(cl.value), int(fl.value)
 
 
 _contexts = {}
@@ -323,6 +369,43 @@ def encode_batch(images, jobs, codes=None, ws=None, graph=True):
     _check(lib().fic_encode_pifs_batch(ctx.handle, n, descs, buf.data_ptr(), wsb, _stream()),
            "fic_encode_pifs_batch")
     return outs
+
+
+def _descs(images, jobs, codes):
+    n = len(images)
+    descs = (ImageDesc * n)()
+    for i, (img, (b, t, tol)) in enumerate(zip(images, jobs)):
+        _need_cuda_u8(img)
+        descs[i].img = img.data_ptr()
+        descs[i].geom = _geom_of(img, b, t)
+        descs[i].tol = float("inf") if tol is None else float(tol)
+        descs[i].codes = codes[i].data_ptr()
+    return descs
+
+
+def autotune(images, jobs, reps=2):
+    """Time candidate search parameters on these images (see fic_autotune)
+    and keep the winners in the device's context. Returns a list of dicts,
+    one per tuning class. Blocks the host."""
+    import torch
+    n = len(images)
+    codes = [torch.empty((num_ranges(im.shape[0], im.shape[1], b), 16), dtype=torch.uint8,
+                         device=im.device) for im, (b, _, _) in zip(images, jobs)]
+    descs = _descs(images, jobs, codes)
+    wsb = lib().fic_autotune_workspace_bytes(n, descs)
+    if wsb == 0:
+        raise FicError(ERR_INVALID_ARG, "fic_autotune_workspace_bytes")
+    buf = _ws.get(wsb, images[0].device)
+    rep_ = (TuneEntry * max(n, 1))()
+    cnt = _i32(0)
+    ctx = context(images[0].device.index)
+    _check(lib().fic_autotune(ctx.handle, n, descs, buf.data_ptr(), wsb, int(reps), rep_, n,
+                              ctypes.byref(cnt), _stream()), "fic_autotune")
+    return [{f: getattr(rep_[i], f) for f, _ in TuneEntry._fields_} for i in range(cnt.value)]
+
+
+def kernel_hash():
+    return lib().fic_kernel_hash().decode()
 
 
 def batch_workspace_bytes(images, jobs):

@@ -271,3 +271,101 @@ def test_color_validation(L, hctx):
     assert C(tol=float("nan")) == fic.ERR_INVALID_ARG
     assert C(gg=fic.make_geom(128, 96, 8, 2, pitch=96)) == fic.ERR_INVALID_ARG   # not 3 bytes a pixel
     assert L.fic_color_workspace_bytes(ctypes.byref(fic.make_geom(128, 96, 8, 2, pitch=200)), 0.05) == 0
+
+
+def test_debug_switch_validation(L, hctx):
+    assert L.fic_set_debug(hctx.handle, 0) == fic.OK
+    assert L.fic_set_debug(hctx.handle, fic.DEBUG_REVERSE_ITEMS | fic.DEBUG_VERIFY16) == fic.OK
+    assert L.fic_set_debug(hctx.handle, 4) == fic.ERR_INVALID_ARG
+    assert L.fic_set_debug(None, 0) == fic.ERR_INVALID_ARG
+    assert L.fic_set_debug(hctx.handle, 0) == fic.OK
+
+
+def _tune_file(path, arch, khash, rows):
+    import json
+    doc = {"format": "fic-tune-1", "arch": arch, "kernel_hash": khash,
+           "rows": [{"range_size": b, "dlog2": dl, "chunk_log2": cl, "flush_at": fl}
+                    for b, dl, cl, fl in rows]}
+    with open(path, "w") as f:
+        json.dump(doc, f)
+
+
+def test_tune_defaults_and_bucket_rule(L, tmp_path):
+    """Defaults: exhaustive items 2^14 columns, pooled 2^12, early flush 64
+    at 8x8 only. A loaded row is used per pool-fraction bucket: 0 for
+    exhaustive, 1 for f >= 1/2, 2 for [1/4, 1/2), ... 5 below 1/16."""
+    c = fic.Context(-1)
+    try:
+        assert c.tune_query(1024, 1024, 8, 1) == (14, 64)
+        assert c.tune_query(1024, 1024, 8, 1, pooled=True, pool_fraction=0.3) == (12, 64)
+        assert c.tune_query(512, 512, 4, 2, pooled=True, pool_fraction=0.3) == (12, 0)
+        assert c.tune_query(2048, 2048, 16, 4) == (14, 0)
+        g = fic.make_geom(1024, 1024, 8, 1)
+        dl = int(L.fic_num_domains(ctypes.byref(g))).bit_length() - 1     # floor(log2 D)
+        p = str(tmp_path / "t.json")
+        _tune_file(p, "none", fic.kernel_hash(),
+                   [(8, dl, [11, 12, 13, 14, 15, 16], [0, 32, 64, 128, 192, 256])])
+        assert c.tune_load(p) == fic.OK
+        q = lambda f: c.tune_query(1024, 1024, 8, 1, pooled=True, pool_fraction=f)
+        assert c.tune_query(1024, 1024, 8, 1) == (11, 0)
+        assert q(1.0) == (12, 32) and q(0.5) == (12, 32)
+        assert q(0.4999) == (13, 64) and q(0.25) == (13, 64)
+        assert q(0.2499) == (14, 128) and q(0.125) == (14, 128)
+        assert q(0.1249) == (15, 192) and q(0.0625) == (15, 192)
+        assert q(0.0624) == (16, 256) and q(0.0) == (16, 256)
+        # another lattice class keeps the defaults
+        assert c.tune_query(512, 512, 8, 1) == (14, 64)
+        # save -> reset -> load round trip
+        p2 = str(tmp_path / "t2.json")
+        c.tune_save(p2)
+        c.tune_reset()
+        assert c.tune_query(1024, 1024, 8, 1) == (14, 64)
+        assert c.tune_load(p2) == fic.OK
+        assert q(0.3) == (13, 64)
+    finally:
+        c.close()
+
+
+def test_tune_cache_rejections(L, tmp_path):
+    c = fic.Context(-1)
+    try:
+        row = [(8, 20, [12] * 6, [64] * 6)]
+        p = str(tmp_path / "a.json")
+        _tune_file(p, "gfx942", fic.kernel_hash(), row)
+        assert c.tune_load(p) == fic.ERR_UNSUPPORTED              # another architecture
+        _tune_file(p, "none", "0000000000000000", row)
+        assert c.tune_load(p) == fic.ERR_UNSUPPORTED              # other kernels
+        _tune_file(p, "none", fic.kernel_hash(), [(8, 20, [10] * 6, [64] * 6)])
+        assert c.tune_load(p) == fic.ERR_INVALID_ARG              # item width out of range
+        _tune_file(p, "none", fic.kernel_hash(), [(6, 20, [12] * 6, [64] * 6)])
+        assert c.tune_load(p) == fic.ERR_INVALID_ARG              # range size
+        with open(p, "w") as f:
+            f.write("not json")
+        assert c.tune_load(p) == fic.ERR_INVALID_ARG
+        assert c.tune_load(str(tmp_path / "missing.json")) == fic.ERR_INVALID_ARG
+        assert c.tune_query(1024, 1024, 8, 1) == (14, 64)          # unchanged
+    finally:
+        c.close()
+
+
+def test_autotune_validation(L, hctx):
+    descs = (fic.ImageDesc * 2)()
+    for i in range(2):
+        descs[i].img = 1
+        descs[i].geom = fic.make_geom(128, 128, 4 + 4 * i, 2)
+        descs[i].tol = 0.05
+        descs[i].codes = 1
+    wsb = L.fic_autotune_workspace_bytes(2, descs)
+    assert 0 < wsb < L.fic_batch_workspace_bytes(2, descs)
+    cnt = ctypes.c_int32(-1)
+    rep = (fic.TuneEntry * 2)()
+    A = lambda n=2, ws=wsb, reps=2, r=rep, cap=2: L.fic_autotune(
+        hctx.handle, n, descs, 1, ws, reps, r, cap, ctypes.byref(cnt), None)
+    assert A() == fic.ERR_DEVICE
+    assert A(ws=wsb - 1) == fic.ERR_WORKSPACE
+    assert A(reps=0) == fic.ERR_INVALID_ARG
+    assert A(n=0) == fic.ERR_INVALID_ARG
+    assert A(r=None, cap=2) == fic.ERR_INVALID_ARG
+    assert A(r=None, cap=0) == fic.ERR_DEVICE
+    descs[0].tol = float("nan")
+    assert A() == fic.ERR_INVALID_ARG
