@@ -223,6 +223,27 @@ fic_status fic_encode_pifs(fic_ctx *ctx, const uint8_t *img, const fic_geom *g,
                            void *ws, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
+ * fic_encode_pifs_noalloc -- fic_encode_pifs for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same search and the same codes, with
+ * the workspace taken from a static device array of the library instead of
+ * a caller buffer. It calls no hipMalloc / hipFree or other allocating
+ * routine and records no stage events.
+ *   Arguments as fic_encode_pifs, without ws / ws_bytes.
+ *   FIC_ERR_WORKSPACE when fic_encode_workspace_bytes(g, pooled) exceeds
+ *   fic_noalloc_scratch_bytes() (64 MiB: e.g. any 512 x 512 job, 1024 x 1024
+ *   at domain step 2).
+ * The array exists once per GPU (held until the process ends) and is shared
+ * by every call on that GPU: calls that overlap on one GPU (other streams,
+ * other host threads or contexts) race and must be serialised by the caller.
+ * Each call initialises what it reads, so no clearing is needed in between.
+ * ---------------------------------------------------------------------- */
+size_t fic_noalloc_scratch_bytes(void);
+fic_status fic_encode_pifs_noalloc(fic_ctx *ctx, const uint8_t *img, const fic_geom *g,
+                                   const uint32_t *perm, const uint32_t *lo, const uint32_t *hi,
+                                   int32_t kernel, fic_code *codes, void *stream);
+
+/* ------------------------------------------------------------------------
  * fic_encode_pifs_batch -- the encoder of Sec. 1 - Sec. 3.1 (classify, pool
  * when tol is finite or negative, search) for n_images images, each with its
  * own geometry and tolerance. Every image is prepared on its own workspace

@@ -19,6 +19,14 @@
 using fic::Geom;
 using fic::u64;
 
+// Device scratch of fic_encode_pifs_noalloc: one copy on every GPU the
+// library runs on, held until the process ends. In host code this name is a
+// host-side stand-in, not a device address: fic_create looks the device
+// address up with hipGetSymbolAddress (with the context's device current)
+// and only that address is ever passed to kernels.
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
 struct fic_ctx {
     int32_t device;      // -1: host-only context
     int32_t num_cu;
@@ -39,6 +47,7 @@ struct fic_ctx {
     hipStream_t cap;     // capture stream, created with the first graph
     fic::BatchStreams side;   // batch preparation streams (side.ns == 0 until created)
     uint32_t dbg;        // fic_set_debug switches
+    void *scratch_dev;   // device address of `scratch` on this device (null: host-only)
     char arch[64];       // gcnArchName of the device (tuning cache key)
     // tuned search parameters per (range size, floor(log2 D)); classes
     // without a row use fic::default_tune_row
@@ -302,6 +311,7 @@ fic_status fic_create(int32_t device, fic_ctx **out)
     c->cap = nullptr;
     c->side.ns = 0;
     c->dbg = 0;
+    c->scratch_dev = nullptr;
     snprintf(c->arch, sizeof c->arch, "%s", "none");
     if (device >= 0) {
         int n = 0;
@@ -324,6 +334,13 @@ fic_status fic_create(int32_t device, fic_ctx **out)
             delete c;
             return FIC_ERR_DEVICE;
         }
+        // this device's copy of the no-allocation scratch
+        void *sp = nullptr;
+        if (hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)) != hipSuccess || !sp) {
+            delete c;
+            return FIC_ERR_DEVICE;
+        }
+        c->scratch_dev = sp;
         // tuned parameters from the cache file named by FIC_TUNE_CACHE, when
         // it was written for this architecture and these kernels
         const char *cache = getenv("FIC_TUNE_CACHE");
@@ -449,6 +466,31 @@ fic_status fic_encode_pifs(fic_ctx *ctx, const uint8_t *img, const fic_geom *g,
     if (st != FIC_OK) return st;
     return dev_status(fic::run_encode(p, img, perm, lo, hi, kernel, codes, ws, ctx->num_cu,
                                       ctx->counters, (hipStream_t)stream, tracer_of(ctx)));
+}
+
+size_t fic_noalloc_scratch_bytes(void) { return kNoAllocScratchBytes; }
+
+fic_status fic_encode_pifs_noalloc(fic_ctx *ctx, const uint8_t *img, const fic_geom *g,
+                                   const uint32_t *perm, const uint32_t *lo, const uint32_t *hi,
+                                   int32_t kernel, fic_code *codes, void *stream)
+{
+    if (!ctx || !img || !codes || !geom_ok(g)) return FIC_ERR_INVALID_ARG;
+    const int nset = (perm != nullptr) + (lo != nullptr) + (hi != nullptr);
+    if (nset != 0 && nset != 3) return FIC_ERR_INVALID_ARG;
+    if (kernel != FIC_KERNEL_MFMA && kernel != FIC_KERNEL_PLAIN) return FIC_ERR_INVALID_ARG;
+    const Geom gg = to_geom(g);
+    if (!key_fits(gg)) return FIC_ERR_CAPACITY;
+    fic::EncodePlan p;
+    fic::plan_encode(gg, nset == 3, p);
+    if (p.total > kNoAllocScratchBytes) return FIC_ERR_WORKSPACE;
+    apply_ctx(ctx, p);
+    fic_status st = enter(ctx);
+    if (st != FIC_OK) return st;
+    if (!ctx->scratch_dev) return FIC_ERR_DEVICE;
+    // the same kernels as fic_encode_pifs, on the static scratch; no stage
+    // events (creating them could allocate)
+    return dev_status(fic::run_encode(p, img, perm, lo, hi, kernel, codes, ctx->scratch_dev,
+                                      ctx->num_cu, ctx->counters, (hipStream_t)stream, nullptr));
 }
 
 size_t fic_batch_workspace_bytes(int32_t n_images, const fic_image_desc *descs)

@@ -111,6 +111,9 @@ def lib():
         "fic_tune_query": (_st, [_vp, ctypes.POINTER(Geom), _i32, ctypes.c_double,
                                  ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
         "fic_kernel_hash": (ctypes.c_char_p, []),
+        "fic_noalloc_scratch_bytes": (ctypes.c_size_t, []),
+        "fic_encode_pifs_noalloc": (_st, [_vp, _vp, ctypes.POINTER(Geom), _vp, _vp, _vp, _i32, _vp,
+                                          _vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -129,7 +132,8 @@ EXPORTED = ("fic_create", "fic_destroy", "fic_status_string", "fic_set_counters"
             "fic_encode_quadtree", "fic_decode_quadtree", "fic_packed_words", "fic_pack_codes",
             "fic_unpack_codes", "fic_color_workspace_bytes", "fic_encode_color",
             "fic_set_debug", "fic_autotune_workspace_bytes", "fic_autotune", "fic_tune_save",
-            "fic_tune_load", "fic_tune_reset", "fic_tune_query", "fic_kernel_hash")
+            "fic_tune_load", "fic_tune_reset", "fic_tune_query", "fic_kernel_hash",
+            "fic_noalloc_scratch_bytes", "fic_encode_pifs_noalloc")
 
 
 def status_string(status):
@@ -323,6 +327,29 @@ def encode_pifs(img, range_size, domain_step, pool=None, kernel="mfma", codes=No
                                  hi.data_ptr() if pooled else None,
                                  kern, codes.data_ptr(), buf.data_ptr(), wsb, _stream()),
            "fic_encode_pifs")
+    return codes
+
+
+def encode_pifs_noalloc(img, range_size, domain_step, pool=None, kernel="mfma", codes=None):
+    """encode_pifs on the library's static device scratch (no workspace
+    argument, nothing allocated by the library)."""
+    import torch
+    _need_cuda_u8(img)
+    g = _geom_of(img, range_size, domain_step)
+    nr = int(lib().fic_num_ranges(ctypes.byref(g)))
+    if nr <= 0:
+        raise FicError(ERR_INVALID_ARG, "geometry")
+    if codes is None:
+        codes = torch.empty((nr, 16), dtype=torch.uint8, device=img.device)
+    kern = KERNEL_MFMA if kernel == "mfma" else KERNEL_PLAIN if kernel == "plain" else int(kernel)
+    pooled = pool is not None
+    perm, lo, hi = pool if pooled else (None, None, None)
+    _check(lib().fic_encode_pifs_noalloc(context(img.device.index).handle, img.data_ptr(),
+                                         ctypes.byref(g), perm.data_ptr() if pooled else None,
+                                         lo.data_ptr() if pooled else None,
+                                         hi.data_ptr() if pooled else None, kern,
+                                         codes.data_ptr(), _stream()),
+           "fic_encode_pifs_noalloc")
     return codes
 
 

@@ -369,3 +369,24 @@ def test_autotune_validation(L, hctx):
     assert A(r=None, cap=0) == fic.ERR_DEVICE
     descs[0].tol = float("nan")
     assert A() == fic.ERR_INVALID_ARG
+
+
+def test_noalloc_validation(L, hctx):
+    """The no-allocation encode validates like fic_encode_pifs and rejects
+    geometries whose workspace exceeds its static scratch."""
+    lim = L.fic_noalloc_scratch_bytes()
+    assert lim == 64 << 20
+    N = lambda g, perm=None, lo=None, hi=None, kernel=0, img=1, codes=1: L.fic_encode_pifs_noalloc(
+        hctx.handle, img, ctypes.byref(g), perm, lo, hi, kernel, codes, None)
+    small = fic.make_geom(512, 512, 8, 1)
+    big = fic.make_geom(1024, 1024, 8, 1)
+    assert L.fic_encode_workspace_bytes(ctypes.byref(small), 1) <= lim
+    assert L.fic_encode_workspace_bytes(ctypes.byref(big), 0) > lim
+    assert N(small) == fic.ERR_DEVICE                        # valid, no device
+    assert N(small, perm=1, lo=1, hi=1) == fic.ERR_DEVICE
+    assert N(big) == fic.ERR_WORKSPACE
+    assert N(small, perm=1) == fic.ERR_INVALID_ARG
+    assert N(small, kernel=3) == fic.ERR_INVALID_ARG
+    assert N(small, img=None) == fic.ERR_INVALID_ARG
+    assert N(fic.make_geom(60, 64, 8, 1)) == fic.ERR_INVALID_ARG
+    assert N(fic.make_geom(8192, 8192, 16, 4)) == fic.ERR_CAPACITY
