@@ -78,6 +78,10 @@ def parse():
                     help="run only this job per step (e.g. 'exhaustive'), for profiling")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a device copy of this many MiB (counter calibration)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="time the built-in search parameters (skip the autotuner)")
+    ap.add_argument("--tune-reps", type=int, default=2,
+                    help="encodes per candidate in the autotuner (best of)")
     return ap.parse_args()
 
 
@@ -182,6 +186,47 @@ def oracle_single_thread():
                       "%.3f s)" % (pairs, best)}
 
 
+def pool_margin(fr_t, fd_t, tol):
+    """Smallest distance of any |fd_d - fd_r| from the window edge tol + 1e-9
+    over the GPU's own fp64 dimensions (tol < 0: (max - min) / 3 of the
+    domain values): how far the closest pool decision is from flipping."""
+    import numpy as np
+    fr = fr_t.cpu().numpy()
+    fd = np.sort(fd_t.cpu().numpy())
+    te = tol if tol >= 0 else (float(fd[-1]) - float(fd[0])) / 3.0
+    edge = te + 1e-9
+    best = np.inf
+    for sign in (-1.0, 1.0):
+        pos = np.searchsorted(fd, fr + sign * edge)
+        for off in (-1, 0):
+            p = np.clip(pos + off, 0, fd.size - 1)
+            best = min(best, float(np.abs(np.abs(fd[p] - fr) - edge).min()))
+    return best
+
+
+def run_autotune(args, fic, images, jobs):
+    """The library's autotuner on the workload's own images (untimed); the
+    timed steps then run with its choices. Returns the report."""
+    if args.no_tune:
+        return {"tuned": False}
+    t0 = time.perf_counter()
+    rep = fic.fic.autotune(images, jobs, reps=max(1, args.tune_reps))
+    dt = time.perf_counter() - t0
+    for r in rep:
+        progress("autotune B=%d log2D=%d bucket %d (%d images): chunk 2^%d -> 2^%d, flush %d -> %d, "
+                 "%.3f -> %.3f ms" % (r["range_size"], r["dlog2"], r["bucket"], r["images"],
+                                      r["base_chunk_log2"], r["chunk_log2"], r["base_flush_at"],
+                                      r["flush_at"], r["base_ms"], r["tuned_ms"]))
+    return {"tuned": True, "seconds": round(dt, 2),
+            "classes": [{"range_size": r["range_size"], "log2_domains": r["dlog2"],
+                         "pool_bucket": r["bucket"], "images": r["images"],
+                         "chunk_log2": r["chunk_log2"], "flush_at": r["flush_at"],
+                         "default_chunk_log2": r["base_chunk_log2"],
+                         "default_flush_at": r["base_flush_at"],
+                         "default_ms": round(r["base_ms"], 4), "tuned_ms": round(r["tuned_ms"], 4)}
+                        for r in rep]}
+
+
 def search_kernel_name(b):
     """Name of the matrix-core search kernel the library runs for B x B ranges."""
     return {4: "k_search_mfma32<4>", 16: "k_search_lds16<16>"}.get(b, "k_search_mfma<%d>" % b)
@@ -232,9 +277,18 @@ def bench_image(args, fic, wl, img_np):
                             codes=codes[i])
         return pools
 
+    # the autotuner on this image's jobs, before anything is timed
+    tune = run_autotune(args, fic, [img] * len(jobs), jobs)
+
     # pair counts and pool sizes per job (from one untimed step)
     pools = step()
     torch.cuda.synchronize()
+    margins = {}
+    for (b, t, tol) in jobs:
+        if tol is not None:
+            fr, _ = fic.fd_classify(img, b, b, want_fp32=False)
+            fd, _ = fic.fd_classify(img, 2 * b, t, want_fp32=False)
+            margins[job_label(b, t, tol, multi)] = pool_margin(fr, fd, tol)
     pairs, sizes = [], []
     for (b, t, tol) in jobs:
         if tol is None:
@@ -343,6 +397,8 @@ def bench_image(args, fic, wl, img_np):
         "stage_ms_per_step": {k: round(v, 4) for k, v in stage_ms.items()},
         "roofline": roofline,
         "hbm_stages": hbm,
+        "autotune": tune,
+        "pool_margin": {k: float("%.3g" % v) for k, v in margins.items()},
         "bitstream": {"%dx%d_b%dt%d" % (H, W, b, t): {
             "bits_per_range": int(fic.fic.lib().fic_packed_words(
                 fic.fic.make_geom(H, W, b, t)) * 32 // R[b]),
@@ -362,6 +418,11 @@ def bench_image(args, fic, wl, img_np):
                          "work_items": int(c[2]), "seed_evaluations": int(c[3]),
                          "exact_fraction": float(c[1]) / pairs_step}
 
+    # every code of every job: no internal-check failure (flag bit 7)
+    torch.cuda.synchronize()
+    mfma_codes = [c.cpu().numpy() for c in codes]
+    out["codes_flag7"] = int(sum(int(np.count_nonzero(fic.unpack_codes(c)["flags"] & 0x80))
+                                 for c in codes))
     if not args.no_plain:
         ex = [i for i, j in enumerate(jobs) if j[2] is None]
         if ex:
@@ -380,7 +441,9 @@ def bench_image(args, fic, wl, img_np):
             out["plain"] = {"exhaustive_search_pairs_per_s": round(pairs[i] / p_search, 1),
                             "exhaustive_encode_s": round(p_total, 6),
                             "mfma_search_speedup": round(job_rate[lab] / (pairs[i] / p_search),
-                                                         3)}
+                                                         3),
+                            "codes_equal_mfma": bool(np.array_equal(codes[i].cpu().numpy(),
+                                                                    mfma_codes[i]))}
 
     if not args.no_cpu:
         out["cpu_baseline"] = oracle_rate(
@@ -600,8 +663,9 @@ def bench_batch(args, fic, wl):
     ws = torch.empty(fic.batch_workspace_bytes(imgs, jobs), dtype=torch.uint8, device=dev)
     codes = [torch.empty(((im.shape[0] // b) * (im.shape[1] // b), 16), dtype=torch.uint8,
                          device=dev) for (im, b, _, _) in items]
+    tune = run_autotune(args, fic, imgs, jobs)
     # pair counts: the same classification and pool kernels, image by image
-    sizes, pairs_b = [], {}
+    sizes, pairs_b, margin = [], {}, float("inf")
     for x, (b, t, tol) in zip(imgs, jobs):
         fr, _ = fic.fd_classify(x, b, b, want_fp32=False)
         fd, _ = fic.fd_classify(x, 2 * b, t, want_fp32=False)
@@ -609,6 +673,7 @@ def bench_batch(args, fic, wl):
         sz = (hi.long() - lo.long()).cpu().numpy()
         sizes.append(sz)
         pairs_b[b] = pairs_b.get(b, 0) + int(sz.sum()) * 8
+        margin = min(margin, pool_margin(fr, fd, tol))
     pairs_step = sum(pairs_b.values())
     progress("%s: %d images, %d pair evaluations per step" % (wl.name, len(items), pairs_step))
 
@@ -633,11 +698,23 @@ def bench_batch(args, fic, wl):
     ctx.timing(False)
     stage_ms = stage_sums(recs, 1)
     searches = [ms for (name, ms) in recs if name == "search"]
-    order = sorted(pairs_b)                 # one search launch per range size, ascending B
-    launches = {b: ms for b, ms in zip(order, searches)}
-    bd = max(launches, key=lambda b: launches[b])
-    roofline = roofline_of("%s (batch, all B=%d images)" % (search_kernel_name(bd), bd),
-                           pairs_b[bd] * 2 * bd * bd, launches[bd] / 1e3)
+    flops = {b: pairs_b[b] * 2 * b * b for b in pairs_b}
+    if 4 in pairs_b and 8 in pairs_b:
+        # one combined launch over the 4x4 and 8x8 images (then 16x16 alone)
+        launches = {"4+8": searches[0]}
+        lflops = {"4+8": flops[4] + flops[8]}
+        names = {"4+8": "k_search_mixed (batch, all 4x4 and 8x8 images)"}
+        rest = [b for b in sorted(pairs_b) if b not in (4, 8)]
+        searches = searches[1:]
+    else:
+        launches, lflops, names = {}, {}, {}
+        rest = sorted(pairs_b)              # one search launch per range size, ascending B
+    for b, ms in zip(rest, searches):
+        launches[str(b)] = ms
+        lflops[str(b)] = flops[b]
+        names[str(b)] = "%s (batch, all B=%d images)" % (search_kernel_name(b), b)
+    bd = max(launches, key=lambda k: launches[k])
+    roofline = roofline_of(names[bd], lflops[bd], launches[bd] / 1e3)
     out = {
         "metric": METRIC,
         "value": round(pairs_step / (ms_step / 1e3), 1),
@@ -650,9 +727,11 @@ def bench_batch(args, fic, wl):
                    "pairs_per_step": pairs_step,
                    "pairs_per_range_size": {str(b): v for b, v in pairs_b.items()}},
         "encode_s_per_image": round(ms_step / 1e3 / len(items), 6),
-        "search_ms_per_range_size": {str(b): round(v, 4) for b, v in launches.items()},
+        "search_ms_per_launch": {k: round(v, 4) for k, v in launches.items()},
         "eager_stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "roofline": roofline,
+        "autotune": tune,
+        "pool_margin_min": float("%.3g" % margin),
     }
     if not args.no_cpu:
         big = max(range(len(items)), key=lambda i: int(sizes[i].sum()))

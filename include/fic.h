@@ -133,9 +133,12 @@ fic_status fic_set_counters(fic_ctx *ctx, uint64_t *counters /* dev */);
    exact 64-term chunk sums of every block it screens and checks the rounding
    error of its one-accumulator FP32 sums against the bound its screen relies
    on, counting into counters [4]..[6] (much slower; codes unchanged).
+   FIC_DEBUG_SEPARATE_SEARCHES: a batch searches its 4x4 and its 8x8 images
+   in one persistent launch per range size instead of one combined launch
+   (codes unchanged; for comparisons).
    FIC_ERR_INVALID_ARG for unknown bits. Batch graphs are recorded per
    switch setting. */
-enum { FIC_DEBUG_REVERSE_ITEMS = 1, FIC_DEBUG_VERIFY16 = 2 };
+enum { FIC_DEBUG_REVERSE_ITEMS = 1, FIC_DEBUG_VERIFY16 = 2, FIC_DEBUG_SEPARATE_SEARCHES = 4 };
 fic_status fic_set_debug(fic_ctx *ctx, uint32_t flags);
 
 /* Stage tracing. With timing enabled, each later call records a pair of HIP
@@ -247,9 +250,10 @@ fic_status fic_encode_pifs_noalloc(fic_ctx *ctx, const uint8_t *img, const fic_g
  * fic_encode_pifs_batch -- the encoder of Sec. 1 - Sec. 3.1 (classify, pool
  * when tol is finite or negative, search) for n_images images, each with its
  * own geometry and tolerance. Every image is prepared on its own workspace
- * part; then the searches of all images of one range size run as ONE
- * persistent work-queue launch (items of all images in one queue, largest
- * images first); then the codes are written.
+ * part; then the searches run as ONE persistent work-queue launch over the
+ * items of all 4x4 and 8x8 images (8x8 images first, each size's images
+ * largest first; 16x16 images in a second launch of their own); then the
+ * codes are written.
  *   descs (host) fic_image_desc[n_images]; codes of image i go to
  *         descs[i].codes (dev). Codes equal fic_encode_pifs on each image.
  *   ws    (dev) >= fic_batch_workspace_bytes(n_images, descs) (the sum of

@@ -732,7 +732,8 @@ fic_status fic_decode_pifs(fic_ctx *ctx, const fic_code *codes, const fic_geom *
 // ---------------------------------------------------------------- debug switches
 fic_status fic_set_debug(fic_ctx *ctx, uint32_t flags)
 {
-    if (!ctx || (flags & ~(uint32_t)(FIC_DEBUG_REVERSE_ITEMS | FIC_DEBUG_VERIFY16)))
+    if (!ctx ||
+        (flags & ~(uint32_t)(FIC_DEBUG_REVERSE_ITEMS | FIC_DEBUG_VERIFY16 | FIC_DEBUG_SEPARATE_SEARCHES)))
         return FIC_ERR_INVALID_ARG;
     ctx->dbg = flags;
     return FIC_OK;

@@ -1105,6 +1105,94 @@ __device__ __forceinline__ void scan_blocks(const SearchArgs &a, const SearchArg
     if (cb < cb_end) screen_block<B, MASK>(ta, st, qu, b0, u0, cb);
 }
 
+// The image of global item `item` among n_img table entries with item bases
+// base[] (last entry whose base <= item), wave-uniform.
+__device__ __forceinline__ int image_of_item(const uint32_t *__restrict__ base, int32_t n_img,
+                                             uint32_t item)
+{
+    int ia = 0, ib = n_img;
+    while (ib - ia > 1) {
+        const int m = (ia + ib) >> 1;
+        if (base[m] <= item) ia = m; else ib = m;
+    }
+    return __builtin_amdgcn_readfirstlane(ia);
+}
+
+// One work item (a group of 2*MB ranges against a run of column blocks) of
+// the 16x16-tile search: load the group's A rows and thresholds, scan the
+// blocks (masked where some range's pool ends inside them), flush, publish
+// the keys.
+template <int B>
+__device__ __forceinline__ void item16(const SearchArgs *ta, const SearchArgs &a,
+                                       const WorkItem &wi, WaveState<B> &st, Queue16<B> *qu)
+{
+    using C = Cfg<B>;
+    constexpr int MW = C::MB, KS = C::KS, GR = C::GR;
+    typedef typename WaveState<B>::frag_t frag_t;
+    const int lane = threadIdx.x & 63;
+    st.flush_at = (uint32_t)a.flush_at;
+    st.grp = wi.grp;
+    const frag_t *ap = (const frag_t *)a.A + (int64_t)st.grp * MW * KS * 64 + lane;
+#pragma unroll
+    for (int b = 0; b < MW; ++b)
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) st.af[b][ks] = ap[(b * KS + ks) * 64];
+    if (lane < GR) {
+        // the flush re-screens queued cells against these thresholds
+        const int64_t slot = (int64_t)st.grp * GR + lane;
+        const u64 bk = a.keys[slot];
+        const int64_t srr = a.rs[slot].srr;
+        qu->best[lane] = bk;
+        qu->srr[lane] = srr;
+        qu->delta[lane] = a.rs[slot].delta;
+        qu->T[lane] = bk == kNoKey ? 0.0f : screen_t_b<B>(srr, (int64_t)(bk >> a.shift));
+    }
+#pragma unroll
+    for (int b = 0; b < MW; ++b) {
+        const int64_t slot = (int64_t)st.grp * GR + tile_range<B>(b, lane);
+        const RangeStat rsx = a.rs[slot];
+        const u64 bk = a.keys[slot];
+        st.lo[b] = rsx.lo;
+        st.hi[b] = rsx.hi;
+        const bool act = !(rsx.flags & kIdle);
+        st.T[b] = !act ? __builtin_inff()
+                       : (bk == kNoKey ? 0.0f : screen_t_b<B>(rsx.srr, (int64_t)(bk >> a.shift)));
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    const uint4 gb = a.grp[st.grp];
+    const int cb0 = (int)(wi.c0 >> 4), cb1 = (int)(wi.c1 >> 4);
+    // column blocks fully inside every active range's pool need no mask
+    int ib0 = (int)((gb.z + 15u) >> 4), ib1 = (int)(gb.w >> 4);
+    ib0 = min(max(ib0, cb0), cb1);
+    ib1 = max(min(ib1, cb1), ib0);
+    st.screened += (u64)(cb1 - cb0) * 16 * GR * 8;
+    scan_blocks<B, true>(a, ta, st, qu, cb0, ib0);
+    scan_blocks<B, false>(a, ta, st, qu, ib0, ib1);
+    scan_blocks<B, true>(a, ta, st, qu, ib1, cb1);
+    if (st.qn) flush_and_refresh16<B>(ta, st, qu);
+    if (lane < GR) {
+        const u64 bk = qu->best[lane];
+        if (bk != kNoKey) atomicMin(&a.keys[(int64_t)st.grp * GR + lane], bk);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
+// A wave's counters at the end of a persistent search.
+__device__ __forceinline__ void add_counters(u64 *counters, u64 screened, u64 survivors,
+                                             u64 items_done)
+{
+    if (!counters) return;
+    const int lane = threadIdx.x & 63;
+    u64 sv = survivors;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) sv += __shfl_xor(sv, off);
+    if (lane == 0) {
+        atomicAdd(&counters[0], screened);
+        atomicAdd(&counters[1], sv);
+        atomicAdd(&counters[2], items_done);
+    }
+}
+
 // Items of n_img images (table entries tab[0..n_img), item bases base[]) in
 // one queue: a wave claims an item, finds its image by binary search over
 // the bases, and loads that image's operands.
@@ -1116,9 +1204,6 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma(const SearchArgs *__rest
                                                         int32_t n_img, uint32_t *item_ctr,
                                                         u64 *counters, uint32_t dbg)
 {
-    using C = Cfg<B>;
-    constexpr int MW = C::MB, KS = C::KS, GR = C::GR;
-    typedef typename WaveState<B>::frag_t frag_t;
     __shared__ Queue16<B> queues[4];
     const int lane = threadIdx.x & 63;
     Queue16<B> *qu = &queues[threadIdx.x >> 6];
@@ -1134,72 +1219,13 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma(const SearchArgs *__rest
         item = __builtin_amdgcn_readfirstlane(item);
         if (item >= nitems) break;
         if (dbg & kDbgReverse) item = nitems - 1u - item;   // order-independence check
-        int ia = 0, ib = n_img;              // last image whose base <= item
-        while (ib - ia > 1) {
-            const int m = (ia + ib) >> 1;
-            if (base[m] <= item) ia = m; else ib = m;
-        }
-        ia = __builtin_amdgcn_readfirstlane(ia);
+        const int ia = image_of_item(base, n_img, item);
         const SearchArgs *ta = tab + ia;
         const SearchArgs a = *ta;
-        const WorkItem wi = a.items[item - base[ia]];
-        st.flush_at = (uint32_t)a.flush_at;
-        st.grp = wi.grp;
-        const frag_t *ap = (const frag_t *)a.A + (int64_t)st.grp * MW * KS * 64 + lane;
-#pragma unroll
-        for (int b = 0; b < MW; ++b)
-#pragma unroll
-            for (int ks = 0; ks < KS; ++ks) st.af[b][ks] = ap[(b * KS + ks) * 64];
-        if (lane < GR) {
-            // the flush re-screens queued cells against these thresholds
-            const int64_t slot = (int64_t)st.grp * GR + lane;
-            const u64 bk = a.keys[slot];
-            const int64_t srr = a.rs[slot].srr;
-            qu->best[lane] = bk;
-            qu->srr[lane] = srr;
-            qu->delta[lane] = a.rs[slot].delta;
-            qu->T[lane] = bk == kNoKey ? 0.0f : screen_t_b<B>(srr, (int64_t)(bk >> a.shift));
-        }
-#pragma unroll
-        for (int b = 0; b < MW; ++b) {
-            const int64_t slot = (int64_t)st.grp * GR + tile_range<B>(b, lane);
-            const RangeStat rsx = a.rs[slot];
-            const u64 bk = a.keys[slot];
-            st.lo[b] = rsx.lo;
-            st.hi[b] = rsx.hi;
-            const bool act = !(rsx.flags & kIdle);
-            st.T[b] = !act ? __builtin_inff()
-                           : (bk == kNoKey ? 0.0f : screen_t_b<B>(rsx.srr, (int64_t)(bk >> a.shift)));
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        const uint4 gb = a.grp[st.grp];
-        const int cb0 = (int)(wi.c0 >> 4), cb1 = (int)(wi.c1 >> 4);
-        // column blocks fully inside every active range's pool need no mask
-        int ib0 = (int)((gb.z + 15u) >> 4), ib1 = (int)(gb.w >> 4);
-        ib0 = min(max(ib0, cb0), cb1);
-        ib1 = max(min(ib1, cb1), ib0);
-        st.screened += (u64)(cb1 - cb0) * 16 * GR * 8;
-        scan_blocks<B, true>(a, ta, st, qu, cb0, ib0);
-        scan_blocks<B, false>(a, ta, st, qu, ib0, ib1);
-        scan_blocks<B, true>(a, ta, st, qu, ib1, cb1);
-        if (st.qn) flush_and_refresh16<B>(ta, st, qu);
-        if (lane < GR) {
-            const u64 bk = qu->best[lane];
-            if (bk != kNoKey) atomicMin(&a.keys[(int64_t)st.grp * GR + lane], bk);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        item16<B>(ta, a, a.items[item - base[ia]], st, qu);
         items_done += 1;
     }
-    if (counters) {
-        u64 sv = st.survivors;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) sv += __shfl_xor(sv, off);
-        if (lane == 0) {
-            atomicAdd(&counters[0], st.screened);
-            atomicAdd(&counters[1], sv);
-            atomicAdd(&counters[2], items_done);
-        }
-    }
+    add_counters(counters, st.screened, st.survivors, items_done);
 }
 
 // ---------------- 16 x 16 tiles with B shared through LDS (16x16 ranges)
@@ -1653,15 +1679,71 @@ __device__ __forceinline__ void scan32(const SearchArgs &a, const SearchArgs *ta
     }
 }
 
+// One work item of the 32x32-tile search (4x4 ranges), as item16.
+template <int B>
+__device__ __forceinline__ void item32(const SearchArgs *ta, const SearchArgs &a,
+                                       const WorkItem &wi, Wave32<B> &st, Queue32<B> *qu)
+{
+    constexpr int MB = Cfg<B>::MB, KS = Cfg<B>::KS, GR = Cfg<B>::GR;
+    const int lane = threadIdx.x & 63, h = lane >> 5;
+    st.flush_at = (uint32_t)a.flush_at;
+    st.grp = wi.grp;
+    const half8_t *ap = (const half8_t *)a.A + (int64_t)st.grp * MB * KS * 64 + lane;
+#pragma unroll
+    for (int blk = 0; blk < MB; ++blk)
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) st.af[blk][ks] = ap[(blk * KS + ks) * 64];
+    if (lane < GR) {
+        // the flush re-screens queued cells against these thresholds
+        const int64_t slot = (int64_t)st.grp * GR + lane;
+        const u64 bk = a.keys[slot];
+        const int64_t srr = a.rs[slot].srr;
+        qu->best[lane] = bk;
+        qu->srr[lane] = srr;
+        qu->delta[lane] = a.rs[slot].delta;
+        qu->T[lane] = bk == kNoKey ? 0.0f : screen_t(srr, (int64_t)(bk >> a.shift));
+    }
+#pragma unroll
+    for (int blk = 0; blk < MB; ++blk)
+#pragma unroll
+        for (int hl = 0; hl < 2; ++hl) {
+            const int64_t slot = (int64_t)st.grp * GR + 4 * blk + 2 * h + hl;
+            const RangeStat rsx = a.rs[slot];
+            const u64 bk = a.keys[slot];
+            st.lo[blk][hl] = rsx.lo;
+            st.hi[blk][hl] = rsx.hi;
+            const bool act = !(rsx.flags & kIdle);
+            st.T[blk][hl] = !act ? __builtin_inff()
+                                 : (bk == kNoKey ? 0.0f
+                                                 : screen_t(rsx.srr, (int64_t)(bk >> a.shift)));
+        }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    const uint4 gb = a.grp[st.grp];
+    const int cb0 = (int)(wi.c0 >> 5), cb1 = (int)(wi.c1 >> 5);
+    // column blocks fully inside every active range's pool need no mask
+    int ib0 = (int)((gb.z + 31u) >> 5), ib1 = (int)(gb.w >> 5);
+    ib0 = min(max(ib0, cb0), cb1);
+    ib1 = max(min(ib1, cb1), ib0);
+    st.screened += (u64)(cb1 - cb0) * 32 * GR * 8;
+    scan32<B, true>(a, ta, st, qu, cb0, ib0);
+    scan32<B, false>(a, ta, st, qu, ib0, ib1);
+    scan32<B, true>(a, ta, st, qu, ib1, cb1);
+    if (st.qn) flush_and_refresh<B>(ta, st, qu);
+    if (lane < GR) {
+        const u64 bk = qu->best[lane];
+        if (bk != kNoKey) atomicMin(&a.keys[(int64_t)st.grp * GR + lane], bk);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
 template <int B>
 __global__ __launch_bounds__(256, 2) void k_search_mfma32(const SearchArgs *__restrict__ tab,
                                                           const uint32_t *__restrict__ base,
                                                           int32_t n_img, uint32_t *item_ctr,
                                                           u64 *counters, uint32_t dbg)
 {
-    constexpr int MB = Cfg<B>::MB, KS = Cfg<B>::KS, GR = Cfg<B>::GR;
     __shared__ Queue32<B> queues[4];
-    const int lane = threadIdx.x & 63, h = lane >> 5;
+    const int lane = threadIdx.x & 63;
     Queue32<B> *qu = &queues[threadIdx.x >> 6];
     const uint32_t nitems = base[n_img];
     Wave32<B> st;
@@ -1675,73 +1757,66 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma32(const SearchArgs *__re
         item = __builtin_amdgcn_readfirstlane(item);
         if (item >= nitems) break;
         if (dbg & kDbgReverse) item = nitems - 1u - item;   // order-independence check
-        int ia = 0, ib = n_img;              // last image whose base <= item
-        while (ib - ia > 1) {
-            const int m = (ia + ib) >> 1;
-            if (base[m] <= item) ia = m; else ib = m;
-        }
-        ia = __builtin_amdgcn_readfirstlane(ia);
+        const int ia = image_of_item(base, n_img, item);
         const SearchArgs *ta = tab + ia;
         const SearchArgs a = *ta;
-        const WorkItem wi = a.items[item - base[ia]];
-        st.flush_at = (uint32_t)a.flush_at;
-        st.grp = wi.grp;
-        const half8_t *ap = (const half8_t *)a.A + (int64_t)st.grp * MB * KS * 64 + lane;
-#pragma unroll
-        for (int blk = 0; blk < MB; ++blk)
-#pragma unroll
-            for (int ks = 0; ks < KS; ++ks) st.af[blk][ks] = ap[(blk * KS + ks) * 64];
-        if (lane < GR) {
-            // the flush re-screens queued cells against these thresholds
-            const int64_t slot = (int64_t)st.grp * GR + lane;
-            const u64 bk = a.keys[slot];
-            const int64_t srr = a.rs[slot].srr;
-            qu->best[lane] = bk;
-            qu->srr[lane] = srr;
-            qu->delta[lane] = a.rs[slot].delta;
-            qu->T[lane] = bk == kNoKey ? 0.0f : screen_t(srr, (int64_t)(bk >> a.shift));
-        }
-#pragma unroll
-        for (int blk = 0; blk < MB; ++blk)
-#pragma unroll
-            for (int hl = 0; hl < 2; ++hl) {
-                const int64_t slot = (int64_t)st.grp * GR + 4 * blk + 2 * h + hl;
-                const RangeStat rsx = a.rs[slot];
-                const u64 bk = a.keys[slot];
-                st.lo[blk][hl] = rsx.lo;
-                st.hi[blk][hl] = rsx.hi;
-                const bool act = !(rsx.flags & kIdle);
-                st.T[blk][hl] = !act ? __builtin_inff()
-                                     : (bk == kNoKey ? 0.0f
-                                                     : screen_t(rsx.srr, (int64_t)(bk >> a.shift)));
-            }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        const uint4 gb = a.grp[st.grp];
-        const int cb0 = (int)(wi.c0 >> 5), cb1 = (int)(wi.c1 >> 5);
-        // column blocks fully inside every active range's pool need no mask
-        int ib0 = (int)((gb.z + 31u) >> 5), ib1 = (int)(gb.w >> 5);
-        ib0 = min(max(ib0, cb0), cb1);
-        ib1 = max(min(ib1, cb1), ib0);
-        st.screened += (u64)(cb1 - cb0) * 32 * GR * 8;
-        scan32<B, true>(a, ta, st, qu, cb0, ib0);
-        scan32<B, false>(a, ta, st, qu, ib0, ib1);
-        scan32<B, true>(a, ta, st, qu, ib1, cb1);
-        if (st.qn) flush_and_refresh<B>(ta, st, qu);
-        if (lane < GR) {
-            const u64 bk = qu->best[lane];
-            if (bk != kNoKey) atomicMin(&a.keys[(int64_t)st.grp * GR + lane], bk);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        item32<B>(ta, a, a.items[item - base[ia]], st, qu);
         items_done += 1;
     }
-    if (counters) {
-        u64 sv = st.survivors;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) sv += __shfl_xor(sv, off);
-        if (lane == 0) {
-            atomicAdd(&counters[0], st.screened);
-            atomicAdd(&counters[1], sv);
-            atomicAdd(&counters[2], items_done);
+    add_counters(counters, st.screened, st.survivors, items_done);
+}
+
+// 4x4 and 8x8 images of a batch in ONE persistent launch: the items of the
+// 8x8 images (tab8, base8) come first in the queue, then those of the 4x4
+// images (tab4, base4); a wave runs each item with that range size's code.
+// Each wave's LDS queue is a union of the two sizes' queues (the waves of a
+// workgroup may run items of different sizes at the same time, so the
+// unions are per wave, never across waves).
+__global__ __launch_bounds__(256, 2) void k_search_mixed(const SearchArgs *__restrict__ tab8,
+                                                         const uint32_t *__restrict__ base8,
+                                                         int32_t n8,
+                                                         const SearchArgs *__restrict__ tab4,
+                                                         const uint32_t *__restrict__ base4,
+                                                         int32_t n4, uint32_t *item_ctr,
+                                                         u64 *counters, uint32_t dbg)
+{
+    union WaveQueue {
+        Queue16<8> q8;
+        Queue32<4> q4;
+    };
+    __shared__ WaveQueue qm[4];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint32_t ni8 = base8[n8];
+    const uint32_t nitems = ni8 + base4[n4];
+    for (;;) {
+        uint32_t item = 0;
+        if (lane == 0) item = atomicAdd(item_ctr, 1u);
+        item = __builtin_amdgcn_readfirstlane(item);
+        if (item >= nitems) break;
+        if (dbg & kDbgReverse) item = nitems - 1u - item;   // order-independence check
+        // per item: the queue is empty between items, and the counters are
+        // added per item (nothing but the loop is carried across items)
+        if (item < ni8) {
+            const int ia = image_of_item(base8, n8, item);
+            const SearchArgs *ta = tab8 + ia;
+            const SearchArgs a = *ta;
+            WaveState<8> s8;
+            s8.qn = 0;
+            s8.screened = 0;
+            s8.survivors = 0;
+            item16<8>(ta, a, a.items[item - base8[ia]], s8, &qm[w].q8);
+            add_counters(counters, s8.screened, s8.survivors, 1);
+        } else {
+            const uint32_t i4 = item - ni8;
+            const int ia = image_of_item(base4, n4, i4);
+            const SearchArgs *ta = tab4 + ia;
+            const SearchArgs a = *ta;
+            Wave32<4> s4;
+            s4.qn = 0;
+            s4.screened = 0;
+            s4.survivors = 0;
+            item32<4>(ta, a, a.items[i4 - base4[ia]], s4, &qm[w].q4);
+            add_counters(counters, s4.screened, s4.survivors, 1);
         }
     }
 }
@@ -2009,9 +2084,9 @@ hipError_t prep_b(const EncodePlan &p, const uint8_t *img, const uint32_t *perm,
     return hipGetLastError();
 }
 
-// Resident workgroups per CU of k_search_mfma<4, 8, 16>, queried once per
-// process (outside any stream capture).
-int g_per_cu[3] = {0, 0, 0};
+// Resident workgroups per CU of k_search_mfma<4, 8, 16> and k_search_mixed,
+// queried once per process (outside any stream capture).
+int g_per_cu[4] = {0, 0, 0, 0};
 
 template <int B> hipError_t occupancy_of(int &out)
 {
@@ -2093,6 +2168,12 @@ hipError_t init_search_occupancy()
     hipError_t e = occupancy_of<4>(g_per_cu[0]);
     if (e == hipSuccess) e = occupancy_of<8>(g_per_cu[1]);
     if (e == hipSuccess) e = occupancy_of<16>(g_per_cu[2]);
+    if (e == hipSuccess) {
+        int v = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &v, reinterpret_cast<const void *>(&k_search_mixed), 256, 0);
+        g_per_cu[3] = v < 1 ? 1 : v;
+    }
     return e;
 }
 
@@ -2259,9 +2340,24 @@ hipError_t run_encode_batch(const BatchJob *jobs, const BatchPlan &bp, void *ws,
         for (int q = 0; q < ns && e == hipSuccess; ++q) e = hipEventRecord(bs->join[q], bs->side[q]);
         for (int q = 0; q < ns && e == hipSuccess; ++q) e = hipStreamWaitEvent(s, bs->join[q], 0);
     }
-    // one persistent search per range size over all its images
+    // 4x4 and 8x8 images together: one persistent search over all their items
+    const bool mixed = bp.group_count[0] > 0 && bp.group_count[1] > 0 && !(bp.dbg & kDbgSeparate);
+    if (mixed && e == hipSuccess) {
+        if (g_per_cu[3] < 1) return hipErrorNotInitialized;
+        const SearchArgs *t4 = tab + bp.group_first[0], *t8 = tab + bp.group_first[1];
+        uint32_t *b4 = base, *b8 = base + (bp.n + 1);
+        hipLaunchKernelGGL(k_item_bases, dim3(1), dim3(256), 0, s, t4, bp.group_count[0], b4);
+        hipLaunchKernelGGL(k_item_bases, dim3(1), dim3(256), 0, s, t8, bp.group_count[1], b8);
+        trace(tr, FIC_STAGE_SEARCH, 1, s);
+        hipLaunchKernelGGL(k_search_mixed, dim3(g_per_cu[3] * num_cu), dim3(256), 0, s, t8,
+                           (const uint32_t *)b8, bp.group_count[1], t4, (const uint32_t *)b4,
+                           bp.group_count[0], ctr, counters, bp.dbg);
+        trace(tr, FIC_STAGE_SEARCH, 0, s);
+        e = hipGetLastError();
+    }
+    // otherwise one persistent search per range size over all its images
     for (int gi = 0; gi < 3 && e == hipSuccess; ++gi) {
-        if (bp.group_count[gi] == 0) continue;
+        if (bp.group_count[gi] == 0 || (mixed && gi < 2)) continue;
         const SearchArgs *t = tab + bp.group_first[gi];
         uint32_t *gb = base + (size_t)gi * (bp.n + 1);
         uint32_t *gc = ctr + gi * 64;

@@ -146,8 +146,10 @@ __host__ __device__ inline int tune_bucket(int pooled, uint64_t pool_sum, int64_
 }
 
 // Debug switches of a context (fic_set_debug): consume the work items in
-// reverse order; run the 16x16 search's rounding check.
-constexpr uint32_t kDbgReverse = 1u, kDbgVerify16 = 2u;
+// reverse order; run the 16x16 search's rounding check; search the 4x4 and
+// 8x8 images of a batch in one launch per range size instead of one
+// combined launch.
+constexpr uint32_t kDbgReverse = 1u, kDbgVerify16 = 2u, kDbgSeparate = 4u;
 
 // ---------------------------------------------------------------------------
 // The isometries: T_q(d)[i][j] = d[src], src per q (0 identity, 1 rot90 cw,

@@ -47,7 +47,7 @@ class TuneEntry(ctypes.Structure):
                 ("base_ms", ctypes.c_float), ("tuned_ms", ctypes.c_float)]
 
 
-DEBUG_REVERSE_ITEMS, DEBUG_VERIFY16 = 1, 2
+DEBUG_REVERSE_ITEMS, DEBUG_VERIFY16, DEBUG_SEPARATE_SEARCHES = 1, 2, 4
 
 
 _lib = None

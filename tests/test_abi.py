@@ -276,7 +276,8 @@ def test_color_validation(L, hctx):
 def test_debug_switch_validation(L, hctx):
     assert L.fic_set_debug(hctx.handle, 0) == fic.OK
     assert L.fic_set_debug(hctx.handle, fic.DEBUG_REVERSE_ITEMS | fic.DEBUG_VERIFY16) == fic.OK
-    assert L.fic_set_debug(hctx.handle, 4) == fic.ERR_INVALID_ARG
+    assert L.fic_set_debug(hctx.handle, fic.DEBUG_SEPARATE_SEARCHES) == fic.OK
+    assert L.fic_set_debug(hctx.handle, 8) == fic.ERR_INVALID_ARG
     assert L.fic_set_debug(None, 0) == fic.ERR_INVALID_ARG
     assert L.fic_set_debug(hctx.handle, 0) == fic.OK
 
