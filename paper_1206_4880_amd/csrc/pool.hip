@@ -10,34 +10,24 @@
 //
 // The sort is a stable LSD radix sort over 8-bit digits of an
 // order-preserving integer image of the keys: per block digit histograms, one
-// exclusive scan over (digit, block), and a scatter that ranks equal digits
-// by position with wave ballots, so every pass is stable.
+// exclusive scan over (digit, block), and a
+// scatter that ranks equal digits by position with wave ballots, so every
+// pass is stable. A pass whose digit is the same for every key is skipped
+// (decided on the device). Small arrays are sorted by one workgroup in LDS.
 #include "fic_internal.h"
 
 namespace fic {
 
 namespace {
 
-constexpr int kSortThreads = 256;
-constexpr int kSortPerThread = 16;
+constexpr int kSortThreads = 1024;
+constexpr int kSortPerThread = 4;
 constexpr int kSortTile = kSortThreads * kSortPerThread;   // keys per block
+constexpr int kSortWaves = kSortThreads / 64;
 
-__global__ __launch_bounds__(kSortThreads) void k_digit_hist(const u64 *__restrict__ keys,
-                                                              int64_t n, int shift,
-                                                              uint32_t *__restrict__ hist,
-                                                              int nblocks)
-{
-    __shared__ uint32_t h[256];
-    h[threadIdx.x] = 0;
-    __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kSortTile;
-    for (int r = 0; r < kSortPerThread; ++r) {
-        int64_t i = base + r * kSortThreads + threadIdx.x;
-        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
-    }
-    __syncthreads();
-    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
-}
+// Digit runs of the per-tile counts are padded to a multiple of 16 tiles,
+// so the scan gives every thread of a block 16-byte aligned runs.
+inline __host__ __device__ int64_t padded_tiles(int64_t nb) { return (nb + 15) & ~(int64_t)15; }
 
 // Exclusive scan of m uint32 entries in three launches: per-tile scans of
 // kScanTile entries, a scan of the tile totals, and the carry-in add.
@@ -64,8 +54,11 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t *sh, uint32
     return base + x - v;
 }
 
+// One tile's scan; with a single tile (gridDim.x == 1) the total also goes
+// to *grand (nullable), so no totals pass is needed.
 __global__ __launch_bounds__(kScanThreads) void k_scan_tiles(uint32_t *__restrict__ a, int64_t m,
-                                                             uint32_t *__restrict__ tile_tot)
+                                                             uint32_t *__restrict__ tile_tot,
+                                                             uint32_t *__restrict__ grand)
 {
     __shared__ uint32_t sh[4];
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
@@ -83,7 +76,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_tiles(uint32_t *__restric
         if (base + i < m) a[base + i] = run;
         run += v[i];
     }
-    if (threadIdx.x == 0) tile_tot[blockIdx.x] = total;
+    if (threadIdx.x == 0) {
+        tile_tot[blockIdx.x] = total;
+        if (grand && gridDim.x == 1) *grand = total;
+    }
 }
 
 // Scan of the tile totals (one block, any count), total to *total.
@@ -114,29 +110,135 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_add(uint32_t *__restrict_
         if (base + i < m) a[base + i] += off;
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_digit_scatter(
-    const u64 *__restrict__ kin, const uint32_t *__restrict__ vin, u64 *__restrict__ kout,
-    uint32_t *__restrict__ vout, int64_t n, int shift, const uint32_t *__restrict__ offs,
-    int nblocks)
+// Control words of one multi-block sort (in its workspace): cur[p] is where
+// the data is before pass p (0: the caller's arrays, 1: the alternate
+// ones); cur[0] = 0, and each pass's scatter writes the next entry.
+constexpr int kMaxPasses = 8;
+struct SortCtl {
+    uint32_t cur[kMaxPasses + 1];
+};
+
+__global__ void k_sort_init(SortCtl *ctl)
+{
+    uint32_t *w = (uint32_t *)ctl;
+    const int i = threadIdx.x;
+    if (i < (int)(sizeof(SortCtl) / 4)) w[i] = 0u;
+}
+
+// Exclusive scan over the 1024 threads of a block (16 waves); *total gets
+// the sum. All threads must call it.
+__device__ inline uint32_t block_scan_1024(uint32_t v, uint32_t *wsum, uint32_t &total)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[wave] = x;
+    __syncthreads();
+    uint32_t base = 0, all = 0;
+    for (int w = 0; w < kSortWaves; ++w) {
+        const uint32_t t = wsum[w];
+        if (w < wave) base += t;
+        all += t;
+    }
+    total = all;
+    __syncthreads();
+    return base + x - v;
+}
+
+// Pass `pass` (digit at bit `shift`) of the multi-block sort, step 1: per
+// tile digit counts into cnt (digit-major: cnt[d * nbp + tile], nbp = nb
+// padded to 16).
+__global__ __launch_bounds__(kSortThreads) void k_sort_hist(const u64 *__restrict__ ka,
+                                                            const u64 *__restrict__ kb, int64_t n,
+                                                            int shift, int pass,
+                                                            uint32_t *__restrict__ cnt, int nb,
+                                                            const SortCtl *ctl)
+{
+    __shared__ uint32_t h[256];
+    const int tid = threadIdx.x;
+    const u64 *keys = ctl->cur[pass] ? kb : ka;     // written by the previous pass's scatter
+    if (tid < 256) h[tid] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+#pragma unroll
+    for (int r = 0; r < kSortPerThread; ++r) {
+        const int64_t i = base + r * kSortThreads + tid;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    if (tid < 256) cnt[(int64_t)tid * padded_tiles(nb) + blockIdx.x] = h[tid];
+}
+
+// Step 2: one workgroup per digit d scans its run of tile counts in place
+// (exclusive; the position of each tile's keys among the digit's keys) and
+// writes the digit's total to tot[d].
+__global__ __launch_bounds__(256) void k_sort_scan(uint32_t *__restrict__ cnt, int nb,
+                                                   uint32_t *__restrict__ tot)
+{
+    __shared__ uint32_t sh[4];
+    const int d = blockIdx.x, tid = threadIdx.x;
+    uint32_t *row = cnt + (int64_t)d * padded_tiles(nb);
+    uint32_t carry = 0;
+    for (int t0 = 0; t0 < nb; t0 += 256) {
+        const int t = t0 + tid;
+        const uint32_t v = t < nb ? row[t] : 0u;
+        uint32_t all;
+        const uint32_t ex = block_exclusive_scan(v, sh, all);
+        if (t < nb) row[t] = carry + ex;
+        carry += all;
+    }
+    if (tid == 0) tot[d] = carry;
+}
+
+// Step 3: stable scatter of each tile by the digit: equal digits are ranked
+// by position with wave ballots, waves in order, rounds in order. A tile's
+// start position of digit d is (keys of smaller digits) + (keys of digit d in
+// earlier tiles). A pass in which one digit holds all n keys would not change
+// the order and is skipped; block 0 records where the data is for the next
+// pass.
+__global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
+    u64 *__restrict__ ka, uint32_t *__restrict__ va, u64 *__restrict__ kb,
+    uint32_t *__restrict__ vb, int64_t n, int shift, int pass, const uint32_t *__restrict__ offs,
+    const uint32_t *__restrict__ tot, int nb, SortCtl *ctl)
 {
     __shared__ uint32_t run[256];
-    __shared__ uint32_t wc[kSortThreads / kWave][256];
+    __shared__ uint32_t wc[kSortWaves][256];
+    __shared__ uint32_t wsum[kSortWaves];
+    __shared__ int skip;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    run[tid] = offs[(int64_t)tid * nblocks + blockIdx.x];
-    for (int w = 0; w < kSortThreads / kWave; ++w) wc[w][tid] = 0;
+    if (tid == 0) skip = 0;
+    for (int i = tid; i < kSortWaves * 256; i += kSortThreads) (&wc[0][0])[i] = 0u;
+    __syncthreads();
+    const uint32_t t = tid < 256 ? tot[tid] : 0u;
+    if (tid < 256 && (int64_t)t == n) skip = 1;
+    uint32_t all;
+    const uint32_t dbase = block_scan_1024(t, wsum, all);     // digits >= 256 add 0
+    const uint32_t cur = ctl->cur[pass];
+    const bool skipped = skip != 0;
+    if (blockIdx.x == 0 && tid == 0) ctl->cur[pass + 1] = skipped ? cur : (cur ^ 1u);
+    if (skipped) return;                            // block-uniform
+    const u64 *kin = cur ? kb : ka;
+    const uint32_t *vin = cur ? vb : va;
+    u64 *kout = cur ? ka : kb;
+    uint32_t *vout = cur ? va : vb;
+    if (tid < 256) run[tid] = dbase + offs[(int64_t)tid * padded_tiles(nb) + blockIdx.x];
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
     const u64 lt = (1ull << lane) - 1ull;
     for (int r = 0; r < kSortPerThread; ++r) {
         const int64_t i = base + r * kSortThreads + tid;
         const bool valid = i < n;
-        u64 key = valid ? kin[i] : 0ull;
-        uint32_t val = valid ? vin[i] : 0u;
-        uint32_t d = (uint32_t)(key >> shift) & 255u;
+        const u64 key = valid ? kin[i] : 0ull;
+        const uint32_t val = valid ? vin[i] : 0u;
+        const uint32_t d = (uint32_t)(key >> shift) & 255u;
         u64 peers = __ballot(valid);
 #pragma unroll
         for (int bit = 0; bit < 8; ++bit) {
-            u64 bb = __ballot((d >> bit) & 1u);
+            const u64 bb = __ballot((d >> bit) & 1u);
             peers &= ((d >> bit) & 1u) ? bb : ~bb;
         }
         const uint32_t rank = __popcll(peers & lt);
@@ -149,13 +251,119 @@ __global__ __launch_bounds__(kSortThreads) void k_digit_scatter(
             vout[pos] = val;
         }
         __syncthreads();
-        uint32_t add = 0;
-        for (int w = 0; w < kSortThreads / kWave; ++w) {
-            add += wc[w][tid];
-            wc[w][tid] = 0;
+        if (tid < 256) {
+            uint32_t add = 0;
+            for (int w = 0; w < kSortWaves; ++w) {
+                add += wc[w][tid];
+                wc[w][tid] = 0u;
+            }
+            run[tid] += add;
         }
-        run[tid] += add;
         __syncthreads();
+    }
+}
+
+// The sorted data back into the caller's arrays when it ended in the
+// alternate ones.
+__global__ void k_sort_finish(u64 *__restrict__ ka, uint32_t *__restrict__ va,
+                              const u64 *__restrict__ kb, const uint32_t *__restrict__ vb,
+                              int64_t n, int passes, const SortCtl *ctl)
+{
+    if (ctl->cur[passes] == 0u) return;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    ka[i] = kb[i];
+    va[i] = vb[i];
+}
+
+// Up to kSmallSort pairs: the whole sort in one workgroup, in LDS. Per pass
+// a digit histogram, its scan (a pass where one digit holds every key is
+// skipped) and a stable scatter of the keys in index order, 1024 at a time:
+// ballot ranks inside a wave, per-wave digit counts across the 16 waves.
+constexpr int kSmallThreads = 1024;
+constexpr int kSmallSort = 4096;
+
+__global__ __launch_bounds__(kSmallThreads) void k_sort_small(u64 *__restrict__ keys,
+                                                              uint32_t *__restrict__ vals, int n,
+                                                              int passes)
+{
+    __shared__ u64 sk[2][kSmallSort];
+    __shared__ uint32_t sv[2][kSmallSort];
+    __shared__ uint32_t hist[256], run[256], wsum[4];
+    __shared__ uint32_t wc[kSmallThreads / kWave][256];
+    __shared__ int skip;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    for (int i = tid; i < n; i += kSmallThreads) {
+        sk[0][i] = keys[i];
+        sv[0][i] = vals[i];
+    }
+    for (int i = tid; i < (kSmallThreads / kWave) * 256; i += kSmallThreads) (&wc[0][0])[i] = 0u;
+    int cur = 0;
+    const u64 lt = (1ull << lane) - 1ull;
+    for (int pass = 0; pass < passes; ++pass) {
+        const int shift = 8 * pass;
+        if (tid < 256) hist[tid] = 0u;
+        if (tid == 0) skip = 0;
+        __syncthreads();
+        for (int i = tid; i < n; i += kSmallThreads) atomicAdd(&hist[(sk[cur][i] >> shift) & 255u], 1u);
+        __syncthreads();
+        // exclusive scan of the 256 counts by waves 0..3
+        const uint32_t v = tid < 256 ? hist[tid] : 0u;
+        uint32_t x = v;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(x, off);
+            if (lane >= off) x += y;
+        }
+        if (tid < 256 && lane == 63) wsum[wave] = x;
+        if (tid < 256 && (int)v == n) skip = 1;
+        __syncthreads();
+        if (tid < 256) {
+            uint32_t b = 0;
+            for (int w = 0; w < wave; ++w) b += wsum[w];
+            run[tid] = b + x - v;
+        }
+        __syncthreads();
+        const int skipped = skip;
+        __syncthreads();                             // read by all before the next pass clears it
+        if (skipped) continue;                       // block-uniform
+        for (int base = 0; base < n; base += kSmallThreads) {
+            const int i = base + tid;
+            const bool valid = i < n;
+            const u64 key = valid ? sk[cur][i] : 0ull;
+            const uint32_t val = valid ? sv[cur][i] : 0u;
+            const uint32_t d = (uint32_t)(key >> shift) & 255u;
+            u64 peers = __ballot(valid);
+#pragma unroll
+            for (int bit = 0; bit < 8; ++bit) {
+                const u64 bb = __ballot((d >> bit) & 1u);
+                peers &= ((d >> bit) & 1u) ? bb : ~bb;
+            }
+            const uint32_t rank = __popcll(peers & lt);
+            if (valid && rank == 0) wc[wave][d] = __popcll(peers);
+            __syncthreads();
+            if (valid) {
+                uint32_t pos = run[d] + rank;
+                for (int w = 0; w < wave; ++w) pos += wc[w][d];
+                sk[cur ^ 1][pos] = key;
+                sv[cur ^ 1][pos] = val;
+            }
+            __syncthreads();
+            if (tid < 256) {
+                uint32_t add = 0;
+                for (int w = 0; w < kSmallThreads / kWave; ++w) {
+                    add += wc[w][tid];
+                    wc[w][tid] = 0u;
+                }
+                run[tid] += add;
+            }
+            __syncthreads();
+        }
+        cur ^= 1;
+    }
+    for (int i = tid; i < n; i += kSmallThreads) {
+        keys[i] = sk[cur][i];
+        vals[i] = sv[cur][i];
     }
 }
 
@@ -232,15 +440,6 @@ __global__ void k_bounds(const double *__restrict__ fdr, int32_t nr,
     hi[r] = (uint32_t)c;
 }
 
-__global__ void k_copy_pairs(const u64 *__restrict__ ks, const uint32_t *__restrict__ vs,
-                             u64 *__restrict__ kd, uint32_t *__restrict__ vd, int64_t n)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    kd[i] = ks[i];
-    vd[i] = vs[i];
-}
-
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
@@ -251,48 +450,68 @@ size_t sort_ws_bytes(int64_t n)
 {
     int64_t nb = (n + kSortTile - 1) / kSortTile;
     if (nb < 1) nb = 1;
-    return align256((size_t)n * 8) + align256((size_t)n * 4) + align256((size_t)nb * 256 * 4) +
-           scan_ws_bytes(nb * 256) + 256;
+    const int64_t nbp = padded_tiles(nb);
+    return align256((size_t)n * 8) + align256((size_t)n * 4) +
+           (size_t)kMaxPasses * (align256((size_t)nbp * 256 * 4) + 1024) + align256(sizeof(SortCtl));
 }
 
 hipError_t scan_u32(uint32_t *a, int64_t m, uint32_t *total, void *ws, hipStream_t s)
 {
     const int64_t nt = (m + kScanTile - 1) / kScanTile;
     uint32_t *tt = (uint32_t *)ws;
+    if (nt == 1) {           // one tile: its scan is the whole scan
+        hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kScanThreads), 0, s, a, m, tt, total);
+        return hipGetLastError();
+    }
     if (nt > 0)
-        hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nt), dim3(kScanThreads), 0, s, a, m, tt);
+        hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nt), dim3(kScanThreads), 0, s, a, m, tt,
+                           (uint32_t *)nullptr);
     hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kScanThreads), 0, s, tt, nt, total);
     if (nt > 1)
         hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nt), dim3(kScanThreads), 0, s, a, m, tt);
     return hipGetLastError();
 }
 
+// Stable sort of n (key, value) pairs by the low key_bits bits of the keys
+// (LSD, 8-bit digits). Up to kSmallSort pairs: one launch (k_sort_small).
+// Otherwise three launches per digit (tile histograms, per-digit scans of
+// the tile counts, stable scatter), one to clear the control words and one
+// to copy the
+// result back when it ended in the alternate arrays; passes in which every
+// key has the same digit are skipped on the device. No workgroup waits on
+// another: every hand-over is a kernel boundary.
 hipError_t radix_sort_pairs(u64 *keys, uint32_t *vals, int64_t n, int key_bits, void *ws,
                             hipStream_t s)
 {
     if (n <= 1) return hipSuccess;
+    const int passes = (key_bits + 7) / 8;
+    if (passes > kMaxPasses) return hipErrorInvalidValue;
+    if (n <= kSmallSort) {
+        hipLaunchKernelGGL(k_sort_small, dim3(1), dim3(kSmallThreads), 0, s, keys, vals, (int)n,
+                           passes);
+        return hipGetLastError();
+    }
     const int nb = (int)((n + kSortTile - 1) / kSortTile);
     char *p = (char *)ws;
     u64 *kalt = (u64 *)p;                 p += align256((size_t)n * 8);
     uint32_t *valt = (uint32_t *)p;       p += align256((size_t)n * 4);
-    uint32_t *hist = (uint32_t *)p;       p += align256((size_t)nb * 256 * 4);
-    void *scanws = p;
-    const int passes = (key_bits + 7) / 8;
-    u64 *ka = keys, *kb = kalt;
-    uint32_t *va = vals, *vb = valt;
+    const size_t nbp = (size_t)padded_tiles(nb);
+    const size_t cstride = (align256(nbp * 256 * 4) + 1024) / 4;   // counts, then 256 totals
+    uint32_t *cnt = (uint32_t *)p;        p += (size_t)kMaxPasses * cstride * 4;
+    SortCtl *ctl = (SortCtl *)p;
+    hipLaunchKernelGGL(k_sort_init, dim3(1), dim3(64), 0, s, ctl);
     for (int pass = 0; pass < passes; ++pass) {
-        const int shift = pass * 8;
-        hipLaunchKernelGGL(k_digit_hist, dim3(nb), dim3(kSortThreads), 0, s, ka, n, shift, hist, nb);
-        const hipError_t se = scan_u32(hist, (int64_t)nb * 256, nullptr, scanws, s);
-        if (se != hipSuccess) return se;
-        hipLaunchKernelGGL(k_digit_scatter, dim3(nb), dim3(kSortThreads), 0, s, ka, va, kb, vb, n,
-                           shift, hist, nb);
-        u64 *tk = ka; ka = kb; kb = tk;
-        uint32_t *tv = va; va = vb; vb = tv;
+        uint32_t *c = cnt + (size_t)pass * cstride;
+        uint32_t *tot = c + align256(nbp * 256 * 4) / 4;
+        hipLaunchKernelGGL(k_sort_hist, dim3(nb), dim3(kSortThreads), 0, s, (const u64 *)keys,
+                           (const u64 *)kalt, n, pass * 8, pass, c, nb, (const SortCtl *)ctl);
+        hipLaunchKernelGGL(k_sort_scan, dim3(256), dim3(256), 0, s, c, nb, tot);
+        hipLaunchKernelGGL(k_sort_scatter, dim3(nb), dim3(kSortThreads), 0, s, keys, vals, kalt,
+                           valt, n, pass * 8, pass, (const uint32_t *)c, (const uint32_t *)tot, nb,
+                           ctl);
     }
-    if (ka != keys)     // odd pass count: copy back (a kernel, so graphs hold no copy nodes)
-        hipLaunchKernelGGL(k_copy_pairs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ka, va,
-                           keys, vals, n);
+    hipLaunchKernelGGL(k_sort_finish, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, keys, vals,
+                       (const u64 *)kalt, (const uint32_t *)valt, n, passes, (const SortCtl *)ctl);
     return hipGetLastError();
 }
 
