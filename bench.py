@@ -82,6 +82,8 @@ def parse():
                     help="time the built-in search parameters (skip the autotuner)")
     ap.add_argument("--tune-reps", type=int, default=2,
                     help="encodes per candidate in the autotuner (best of)")
+    ap.add_argument("--separate-searches", action="store_true",
+                    help="batch: one search launch per range size instead of the combined one")
     return ap.parse_args()
 
 
@@ -212,19 +214,29 @@ def run_autotune(args, fic, images, jobs):
     t0 = time.perf_counter()
     rep = fic.fic.autotune(images, jobs, reps=max(1, args.tune_reps))
     dt = time.perf_counter() - t0
+    launch = [r for r in rep if r["range_size"] == 0]
+    rep = [r for r in rep if r["range_size"] != 0]
     for r in rep:
         progress("autotune B=%d log2D=%d bucket %d (%d images): chunk 2^%d -> 2^%d, flush %d -> %d, "
                  "%.3f -> %.3f ms" % (r["range_size"], r["dlog2"], r["bucket"], r["images"],
                                       r["base_chunk_log2"], r["chunk_log2"], r["base_flush_at"],
                                       r["flush_at"], r["base_ms"], r["tuned_ms"]))
-    return {"tuned": True, "seconds": round(dt, 2),
+    out = {"tuned": True, "seconds": round(dt, 2)}
+    if launch:
+        r = launch[0]
+        out["batch_search_launches"] = {
+            "chosen": "one per range size" if r["flush_at"] else "one combined 4x4 + 8x8",
+            "combined_ms": round(r["base_ms"], 4), "chosen_ms": round(r["tuned_ms"], 4)}
+        progress("autotune batch launches: %s (combined %.3f ms, chosen %.3f ms)"
+                 % (out["batch_search_launches"]["chosen"], r["base_ms"], r["tuned_ms"]))
+    return dict(out, **{
             "classes": [{"range_size": r["range_size"], "log2_domains": r["dlog2"],
                          "pool_bucket": r["bucket"], "images": r["images"],
                          "chunk_log2": r["chunk_log2"], "flush_at": r["flush_at"],
                          "default_chunk_log2": r["base_chunk_log2"],
                          "default_flush_at": r["base_flush_at"],
                          "default_ms": round(r["base_ms"], 4), "tuned_ms": round(r["tuned_ms"], 4)}
-                        for r in rep]}
+                        for r in rep]})
 
 
 def search_kernel_name(b):
@@ -660,6 +672,8 @@ def bench_batch(args, fic, wl):
     imgs = [torch.from_numpy(np.ascontiguousarray(im)).to(dev) for (im, _, _, _) in items]
     jobs = [(b, t, tol) for (_, b, t, tol) in items]
     ctx = fic.fic.context(0)
+    if args.separate_searches:
+        ctx.set_debug(fic.fic.DEBUG_SEPARATE_SEARCHES)
     ws = torch.empty(fic.batch_workspace_bytes(imgs, jobs), dtype=torch.uint8, device=dev)
     codes = [torch.empty(((im.shape[0] // b) * (im.shape[1] // b), 16), dtype=torch.uint8,
                          device=dev) for (im, b, _, _) in items]
@@ -699,7 +713,7 @@ def bench_batch(args, fic, wl):
     stage_ms = stage_sums(recs, 1)
     searches = [ms for (name, ms) in recs if name == "search"]
     flops = {b: pairs_b[b] * 2 * b * b for b in pairs_b}
-    if 4 in pairs_b and 8 in pairs_b:
+    if 4 in pairs_b and 8 in pairs_b and len(searches) < len(pairs_b):
         # one combined launch over the 4x4 and 8x8 images (then 16x16 alone)
         launches = {"4+8": searches[0]}
         lflops = {"4+8": flops[4] + flops[8]}

@@ -392,7 +392,13 @@ fic_status fic_decode_quadtree(fic_ctx *ctx, const fic_code *codes1, const fic_g
  * it faster than the starting row, and store it in the context. BLOCKS THE
  * HOST (event synchronisation); not for stream capture. Recorded batch graphs
  * are dropped. report (host, nullable) receives up to report_cap entries, one
- * per group; *report_count (nullable) the number of groups.
+ * per group; *report_count (nullable) the number of entries.
+ * When the images include both 4x4 and 8x8 ranges and ws also holds their
+ * whole batch (>= fic_batch_workspace_bytes(n_images, descs)), the tuner
+ * also times the batch with one combined persistent search and with one
+ * search per range size (best of 3 each) and keeps the faster for later
+ * batches; its report entry has range_size 0, flush_at 1 when separate
+ * launches won, base_ms the combined time and tuned_ms the kept one.
  *   ws  (dev) >= fic_autotune_workspace_bytes(n_images, descs) (the largest
  *       single-image batch workspace).
  * fic_tune_save / fic_tune_load: the context's rows as a JSON file (host

@@ -47,6 +47,7 @@ struct fic_ctx {
     hipStream_t cap;     // capture stream, created with the first graph
     fic::BatchStreams side;   // batch preparation streams (side.ns == 0 until created)
     uint32_t dbg;        // fic_set_debug switches
+    bool batch_separate; // tuned: one search launch per range size in batches
     void *scratch_dev;   // device address of `scratch` on this device (null: host-only)
     char arch[64];       // gcnArchName of the device (tuning cache key)
     // tuned search parameters per (range size, floor(log2 D)); classes
@@ -311,6 +312,7 @@ fic_status fic_create(int32_t device, fic_ctx **out)
     c->cap = nullptr;
     c->side.ns = 0;
     c->dbg = 0;
+    c->batch_separate = false;
     c->scratch_dev = nullptr;
     snprintf(c->arch, sizeof c->arch, "%s", "none");
     if (device >= 0) {
@@ -529,7 +531,7 @@ fic_status fic_encode_pifs_batch(fic_ctx *ctx, int32_t n_images, const fic_image
     if (bp.items > (int64_t)0xffffffffll) return FIC_ERR_CAPACITY;   // one 32-bit item queue
     if (ws_bytes < bp.total) return FIC_ERR_WORKSPACE;
     for (auto &pt : bp.part) apply_ctx(ctx, pt.plan);
-    bp.dbg = ctx->dbg;
+    bp.dbg = ctx->dbg | (ctx->batch_separate ? fic::kDbgSeparate : 0u);
     fic_status st = enter(ctx);
     if (st != FIC_OK) return st;
     hipStream_t s = (hipStream_t)stream;
@@ -538,7 +540,7 @@ fic_status fic_encode_pifs_batch(fic_ctx *ctx, int32_t n_images, const fic_image
     if (!ctx->use_graph)
         return dev_status(fic::run_encode_batch(jobs.data(), bp, ws, ctx->num_cu, ctx->counters, s,
                                                 tracer_of(ctx), side));
-    std::vector<unsigned char> key = batch_key(n_images, descs, ws, ws_bytes, ctx->counters, ctx->dbg);
+    std::vector<unsigned char> key = batch_key(n_images, descs, ws, ws_bytes, ctx->counters, bp.dbg);
     size_t hit = ctx->graphs.size();
     for (size_t i = 0; i < ctx->graphs.size(); ++i)
         if (ctx->graphs[i].key == key) { hit = i; break; }
@@ -750,6 +752,7 @@ fic_status fic_tune_reset(fic_ctx *ctx)
 {
     if (!ctx) return FIC_ERR_INVALID_ARG;
     ctx->tune.clear();
+    ctx->batch_separate = false;
     if (ctx->device >= 0 && enter(ctx) == FIC_OK) drop_graphs(ctx);
     return FIC_OK;
 }
@@ -923,6 +926,45 @@ fic_status fic_autotune(fic_ctx *ctx, int32_t n_images, const fic_image_desc *de
             r.tuned_ms = sw;
         }
         ++nrep;
+    }
+    // the launch structure of a batch with both 4x4 and 8x8 images: one
+    // combined persistent search, or one per range size (best of 3 whole
+    // batches each, interleaved, with the tuned rows)
+    bool has4 = false, has8 = false;
+    for (const auto &im : ims) { has4 = has4 || im.b == 4; has8 = has8 || im.b == 8; }
+    if (e == hipSuccess && has4 && has8 && ws_bytes >= fic_batch_workspace_bytes(n_images, descs)) {
+        std::vector<fic::BatchJob> jobs;
+        batch_jobs(n_images, descs, jobs);
+        fic::BatchPlan bp;
+        fic::plan_batch(jobs.data(), n_images, bp);
+        for (auto &pt : bp.part) apply_ctx(ctx, pt.plan);
+        const fic::BatchStreams *side = side_streams(ctx);
+        float best[2] = {1e30f, 1e30f};
+        for (int r = 0; r < 3 && e == hipSuccess && side; ++r)
+            for (int sep = 0; sep < 2 && e == hipSuccess; ++sep) {
+                bp.dbg = sep ? fic::kDbgSeparate : 0u;
+                float ms = 0.0f;
+                e = hipEventRecord(e0, s);
+                if (e == hipSuccess)
+                    e = fic::run_encode_batch(jobs.data(), bp, ws, ctx->num_cu, nullptr, s, nullptr, side);
+                if (e == hipSuccess) e = hipEventRecord(e1, s);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                best[sep] = ms < best[sep] ? ms : best[sep];
+            }
+        if (e == hipSuccess && side) {
+            ctx->batch_separate = best[1] < best[0];
+            if (nrep < report_cap) {
+                fic_tune_entry &r = report[nrep];
+                memset(&r, 0, sizeof r);
+                r.range_size = 0;             // the batch's launch structure
+                r.images = n_images;
+                r.flush_at = ctx->batch_separate ? 1 : 0;
+                r.base_ms = best[0];
+                r.tuned_ms = ctx->batch_separate ? best[1] : best[0];
+            }
+            ++nrep;
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

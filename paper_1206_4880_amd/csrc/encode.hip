@@ -61,6 +61,23 @@ template <int B> constexpr float screen_slack()
     return Cfg<B>::n / 4.0f + (Cfg<B>::NCH > 1 ? 64.0f : 0.0f);
 }
 
+// The contrast is clamped: s = k/16 with k in [-16, 15]. Relaxing k to the
+// real interval [-16, 16], F(k) = 4096 Srr' - 128 k Srd' + k^2 Sdd' reaches
+// F_best (T^2 = Srr' - F_best/4096) only if |Srd'| >= T sqrt(Sdd') when the
+// vertex |64 Srd'/Sdd'| <= 16, and only if |Srd'| >= 2 T^2 + Sdd'/8 at the
+// end points otherwise; when T > sqrt(Sdd')/4 the first case is empty, so a
+// pair passes only by the second. In C''' units (sqrt(Sdd') = n u): for
+// T > n u / 4 a cell needs max |C'''| >= 2 T^2/n + n u^2/8 (minus the same
+// slack), a stricter test than T u. Returns that threshold, lowered by 2^-20
+// for the FP32 rounding (T and u are rounded down already, and the bound
+// grows with both), or 0 when the plain test T u is the exact one.
+template <int B> __device__ __forceinline__ float clamp_threshold(float t, float u)
+{
+    constexpr float n = (float)Cfg<B>::n;
+    if (!(t > (n * 0.25f) * u)) return 0.0f;
+    return fmaf(2.0f * t, t * (1.0f / n), (n * 0.125f) * u * u) * (1.0f - 0x1p-20f);
+}
+
 // Threshold of the 16x16 search, whose hot screen sums all n products in one
 // FP32 accumulator. The products are exact; every partial sum is at most
 // ||A|| ||B|| (Cauchy-Schwarz), so each of the at most n + KS roundings is off
@@ -1481,9 +1498,12 @@ __device__ __noinline__ void flush32(const SearchArgs *ta, uint32_t nq, Queue32<
         if (e < nq) {
             ls = le[r];
             const float t = qu->T[ls];
+            const float g = clamp_threshold<B>(t, uu[r]) - slack;   // the clamped contrast
 #pragma unroll
-            for (int q = 0; q < 8; ++q)
-                if (fmaf(-t, uu[r], fabsf(qu->c[q][e])) >= -slack) mask |= 1u << q;
+            for (int q = 0; q < 8; ++q) {
+                const float c = fabsf(qu->c[q][e]);
+                if (fmaf(-t, uu[r], c) >= -slack && c >= g) mask |= 1u << q;
+            }
         }
         if (!wave_any(mask != 0)) continue;
         const double base = 4096.0 * (double)qu->srr[ls];
@@ -1570,11 +1590,16 @@ __device__ __forceinline__ void screen32(const SearchArgs &a, const SearchArgs *
         __builtin_amdgcn_sched_group_barrier(0x002, 40, 0);
     }
     if (!wave_any(hit)) return;
-    // append the passing cells (at most 64 per row block half)
+    // append the passing cells (at most 64 per row block half); a row block
+    // half where some lane passes first applies the clamped-contrast test
+    // (a range whose threshold needs |s| > 1 from this column cannot pass)
 #pragma unroll
     for (int blk = 0; blk < MB; ++blk)
 #pragma unroll
         for (int hl = 0; hl < 2; ++hl) {
+            if (__ballot(pass[blk][hl]) == 0) continue;
+            const float g = clamp_threshold<B>(st.T[blk][hl], u);
+            if (pass[blk][hl] && g > 0.0f) pass[blk][hl] = max8(acc[blk], 8 * hl) >= g - slack;
             const u64 ball = __ballot(pass[blk][hl]);
             if (ball == 0) continue;
             const uint32_t cnt = (uint32_t)__popcll(ball);

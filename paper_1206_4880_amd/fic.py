@@ -422,11 +422,13 @@ def autotune(images, jobs, reps=2):
     wsb = lib().fic_autotune_workspace_bytes(n, descs)
     if wsb == 0:
         raise FicError(ERR_INVALID_ARG, "fic_autotune_workspace_bytes")
+    # room for the whole batch too, so the tuner also picks its launch structure
+    wsb = max(wsb, int(lib().fic_batch_workspace_bytes(n, descs)))
     buf = _ws.get(wsb, images[0].device)
-    rep_ = (TuneEntry * max(n, 1))()
+    rep_ = (TuneEntry * (n + 1))()
     cnt = _i32(0)
     ctx = context(images[0].device.index)
-    _check(lib().fic_autotune(ctx.handle, n, descs, buf.data_ptr(), wsb, int(reps), rep_, n,
+    _check(lib().fic_autotune(ctx.handle, n, descs, buf.data_ptr(), wsb, int(reps), rep_, n + 1,
                               ctypes.byref(cnt), _stream()), "fic_autotune")
     return [{f: getattr(rep_[i], f) for f, _ in TuneEntry._fields_} for i in range(cnt.value)]
 

@@ -90,6 +90,11 @@ def test_autotune_then_cache_round_trip(fic, tmp_path):
     try:
         rep = fic.fic.autotune(images, jobs, reps=1)
         assert rep, "no tuning classes"
+        launch = [r for r in rep if r["range_size"] == 0]
+        rep = [r for r in rep if r["range_size"] != 0]
+        if {b for b, _, _ in jobs} >= {4, 8}:
+            assert len(launch) == 1 and launch[0]["flush_at"] in (0, 1)
+            assert launch[0]["tuned_ms"] <= launch[0]["base_ms"]
         for r in rep:
             assert 11 <= r["chunk_log2"] <= 16 and r["flush_at"] in (0, 32, 64, 128)
             assert r["tuned_ms"] <= r["base_ms"]
@@ -98,6 +103,10 @@ def test_autotune_then_cache_round_trip(fic, tmp_path):
                      r["flush_at"], r["base_ms"], r["tuned_ms"]))
         for x, (b, t, tol), want in zip(images, jobs, before):
             c, _ = fic.encode(x, b, t, tol=tol)
+            assert np.array_equal(c.cpu().numpy(), want)
+        # the batch, with whatever launch structure was kept, equals them too
+        outs = fic.encode_batch(images, jobs, graph=True)
+        for c, want in zip(outs, before):
             assert np.array_equal(c.cpu().numpy(), want)
         # the exhaustive class answers with its chosen row; save, reset, load
         q = ctx.tune_query(512, 512, 8, 2)

@@ -76,3 +76,84 @@ def test_threshold_reduction_is_small():
     na = 255.0 * np.sqrt(N)           # every |A| <= 255
     e = (N + KS) * 2.0 ** -23 * np.sqrt(N) * na
     assert e / 2 <= 1.1
+
+
+# ---------------------------------------------------- clamped-contrast screen
+def _f32(x):
+    return np.float32(x)
+
+
+def clamp_threshold(t, u, n):
+    """The kernels' clamp_threshold in FP32 (fma emulated by one rounding of
+    the fp64 value)."""
+    t, u = _f32(t), _f32(u)
+    if not t > _f32(_f32(n * 0.25) * u):
+        return _f32(0.0)
+    a = _f32(t * _f32(1.0 / n))
+    b = _f32(_f32(_f32(n * 0.125) * u) * u)
+    g = _f32(np.float64(_f32(2.0) * t) * np.float64(a) + np.float64(b))
+    return _f32(g * _f32(1.0 - 2.0 ** -20))
+
+
+def kernel_screen(c, t, u, n):
+    """Both tests a queued cell goes through: max |C'''| >= T u - n/4 (one
+    rounding) and, when the contrast is clamped, >= clamp_threshold - n/4."""
+    slack = _f32(n / 4.0)
+    c = _f32(abs(c))
+    plain = _f32(np.float64(c) - np.float64(_f32(t)) * np.float64(_f32(u))) >= -slack
+    return bool(plain and c >= _f32(clamp_threshold(t, u, n) - slack))
+
+
+def best_f(srr, srd, sdd):
+    return min(4096 * srr - 128 * k * srd + k * k * sdd for k in range(-16, 16))
+
+
+def test_clamped_screen_never_rejects_a_pair_that_reaches_the_best():
+    """For every pair and every F_best the pair reaches (its exact best F over
+    k in [-16, 15] is <= F_best), the clamped-contrast screen lets it pass,
+    with the kernels' rounding of T and u; and it rejects pairs the plain
+    screen lets through (high-contrast ranges against flat domains)."""
+    rng = np.random.default_rng(11)
+    stricter = 0
+    for b in (4, 8):
+        n = b * b
+        for trial in range(3000):
+            kind = trial % 3
+            if kind == 0:
+                r = rng.integers(0, 256, n)
+                d = rng.integers(0, 1021, n)
+            elif kind == 1:                      # contrasty range, flat-ish domain
+                r = np.where(rng.random(n) < 0.5, rng.integers(0, 40, n), rng.integers(200, 256, n))
+                d = 500 + rng.integers(-30, 31, n)
+            else:                                # domain similar to the range, any scale
+                r = rng.integers(0, 256, n)
+                s = rng.choice([0.25, 0.5, 1.0, 2.0, 4.0])
+                d = np.clip(np.round(4 * (r - r.mean()) * s + 510 + rng.integers(-20, 21, n)), 0, 1020)
+            r, d = r.astype(np.int64), d.astype(np.int64)
+            rh = (int(r.sum()) + n // 2) // n            # the kernels' centring levels
+            dh = (int(d.sum()) + n // 2) // n
+            c = int(((r - rh) * (d - dh)).sum())         # C''', exact
+            srr = n * int((r * r).sum()) - int(r.sum()) ** 2
+            sdd = n * int((d * d).sum()) - int(d.sum()) ** 2
+            srd = n * int((r * d).sum()) - int(r.sum()) * int(d.sum())
+            if srr == 0 or sdd == 0:
+                continue
+            fx = best_f(srr, srd, sdd)
+            u = np.sqrt(sdd) / n * (1.0 - 2.0 ** -20)
+            for fb in (fx, fx + 1, fx + int(rng.integers(0, 4096 * 64)), 4096 * srr):
+                if fb > 4096 * srr:
+                    continue
+                theta = srr - fb / 4096.0
+                t = np.sqrt(theta) * (1.0 - 2.0 ** -20) if theta > 0 else 0.0
+                assert kernel_screen(c, t, u, n), (b, trial, fb, fx)
+            # a best key between the unclamped optimum and what the clamped
+            # contrast reaches: the plain screen passes, the clamped one need not
+            fcont = 4096 * srr - 4096.0 * srd * srd / sdd
+            fb = int((fcont + fx) / 2)
+            theta = srr - fb / 4096.0
+            if theta > 0:
+                t = np.sqrt(theta) * (1.0 - 2.0 ** -20)
+                plain = _f32(np.float64(abs(c)) - np.float64(_f32(t)) * np.float64(_f32(u))) >= -n / 4
+                if plain and not kernel_screen(c, t, u, n):
+                    stricter += 1
+    assert stricter > 0
