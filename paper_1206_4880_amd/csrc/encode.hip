@@ -78,6 +78,21 @@ template <int B> __device__ __forceinline__ float clamp_threshold(float t, float
     return fmaf(2.0f * t, t * (1.0f / n), (n * 0.125f) * u * u) * (1.0f - 0x1p-20f);
 }
 
+// The contrast is quantised: every range's key starts at most at its DC
+// code (k = 0, F = 4096 Srr', the lowest pool domain under isometry 0, the
+// smallest (domain, isometry) there is), so a pair can only replace the key
+// with some k != 0 and F(k) < 4096 Srr', i.e. k (k Sdd' - 128 Srd') < 0,
+// which needs 128 |Srd'| > Sdd'. In C''' units (|Srd'| <= n |C'''| + n^2/4,
+// Sdd' = n^2 u^2): max |C'''| > n u^2 / 128 - n/4. This holds whatever T is,
+// and decides the ranges whose best is still the DC code (T = 0, where the
+// test T u passes every pair). Returns n u^2/128 lowered by 2^-20 (u is
+// rounded down already); flat and padding columns (u = 1e30) never pass.
+template <int B> __device__ __forceinline__ float quant_threshold(float u)
+{
+    constexpr float n = (float)Cfg<B>::n;
+    return (n * (1.0f / 128.0f)) * u * u * (1.0f - 0x1p-20f);
+}
+
 // Threshold of the 16x16 search, whose hot screen sums all n products in one
 // FP32 accumulator. The products are exact; every partial sum is at most
 // ||A|| ||B|| (Cauchy-Schwarz), so each of the at most n + KS roundings is off
@@ -722,9 +737,12 @@ __device__ __noinline__ void flush16(const SearchArgs *ta, uint32_t nq, Queue16<
             ls = lqe[r] & 255u;
             isob = lqe[r] >> 8;
             const float t = qu->T[ls];
+            const float g = quant_threshold<B>(uu[r]) - slack;    // the quantised contrast
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
-                if (fmaf(-t, uu[r], fabsf((float)qu->c[v][e])) >= -slack) mask |= 1u << v;
+            for (int v = 0; v < 4; ++v) {
+                const float c = fabsf((float)qu->c[v][e]);
+                if (fmaf(-t, uu[r], c) >= -slack && c >= g) mask |= 1u << v;
+            }
         }
         if (!wave_any(mask != 0)) continue;
         const double base = 4096.0 * (double)qu->srr[ls];
@@ -1422,7 +1440,7 @@ __global__ __launch_bounds__(256, 2) void k_search_lds16(const SearchArgs *__res
 // near-optimal domains, so its cells pass the screen far more often than
 // those of larger ranges: the queue matters most there.)
 template <int B> struct Queue32 {
-    float c[8][kQueue];              // the cell's cross term under isometry q
+    float4_t c[kQueue][2];           // the cell's cross terms, isometries 0-3 and 4-7
     uint32_t p[kQueue];              // column
     uint32_t ls[kQueue];             // range within the wave's group
     u64 best[Cfg<B>::GR];            // best keys of the wave's ranges
@@ -1498,10 +1516,12 @@ __device__ __noinline__ void flush32(const SearchArgs *ta, uint32_t nq, Queue32<
         if (e < nq) {
             ls = le[r];
             const float t = qu->T[ls];
-            const float g = clamp_threshold<B>(t, uu[r]) - slack;   // the clamped contrast
+            // the clamped and the quantised contrast
+            const float g = fmaxf(clamp_threshold<B>(t, uu[r]), quant_threshold<B>(uu[r])) - slack;
+            const float4_t ca = qu->c[e][0], cb = qu->c[e][1];
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
-                const float c = fabsf(qu->c[q][e]);
+                const float c = fabsf(q < 4 ? ca[q] : cb[q - 4]);
                 if (fmaf(-t, uu[r], c) >= -slack && c >= g) mask |= 1u << q;
             }
         }
@@ -1517,7 +1537,7 @@ __device__ __noinline__ void flush32(const SearchArgs *ta, uint32_t nq, Queue32<
             if (mask) {
                 const int q = __builtin_ctz(mask);
                 mask &= mask - 1u;
-                const double rd = (double)n * (double)qu->c[q][e] - ne;   // exact integers
+                const double rd = (double)n * (double)((const float *)&qu->c[e][0])[q] - ne;   // exact
                 const double f = fit_f_d(base, rd, dd, inv);
                 if (qb < 0 || f < fb) {      // ascending q: ties keep the lower isometry
                     fb = f;
@@ -1590,16 +1610,13 @@ __device__ __forceinline__ void screen32(const SearchArgs &a, const SearchArgs *
         __builtin_amdgcn_sched_group_barrier(0x002, 40, 0);
     }
     if (!wave_any(hit)) return;
-    // append the passing cells (at most 64 per row block half); a row block
-    // half where some lane passes first applies the clamped-contrast test
-    // (a range whose threshold needs |s| > 1 from this column cannot pass)
+    // append the passing cells (at most 64 per row block half), each as one
+    // 32-byte record of its 8 cross terms (the flush applies the clamped- and
+    // quantised-contrast tests; here they did not remove enough cells to pay)
 #pragma unroll
     for (int blk = 0; blk < MB; ++blk)
 #pragma unroll
         for (int hl = 0; hl < 2; ++hl) {
-            if (__ballot(pass[blk][hl]) == 0) continue;
-            const float g = clamp_threshold<B>(st.T[blk][hl], u);
-            if (pass[blk][hl] && g > 0.0f) pass[blk][hl] = max8(acc[blk], 8 * hl) >= g - slack;
             const u64 ball = __ballot(pass[blk][hl]);
             if (ball == 0) continue;
             const uint32_t cnt = (uint32_t)__popcll(ball);
@@ -1608,8 +1625,9 @@ __device__ __forceinline__ void screen32(const SearchArgs &a, const SearchArgs *
                 const uint32_t below = __builtin_amdgcn_mbcnt_hi(
                     (uint32_t)(ball >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ball, 0u));
                 const uint32_t pos = st.qn + below;
-#pragma unroll
-                for (int q = 0; q < 8; ++q) qu->c[q][pos] = acc[blk][8 * hl + q];
+                const float16_t &av = acc[blk];
+                qu->c[pos][0] = float4_t{av[8 * hl + 0], av[8 * hl + 1], av[8 * hl + 2], av[8 * hl + 3]};
+                qu->c[pos][1] = float4_t{av[8 * hl + 4], av[8 * hl + 5], av[8 * hl + 6], av[8 * hl + 7]};
                 qu->p[pos] = p;
                 qu->ls[pos] = (uint32_t)(4 * blk + 2 * h + hl);
             }

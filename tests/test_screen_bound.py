@@ -157,3 +157,40 @@ def test_clamped_screen_never_rejects_a_pair_that_reaches_the_best():
                 if plain and not kernel_screen(c, t, u, n):
                     stricter += 1
     assert stricter > 0
+
+
+def quant_threshold(u, n):
+    return _f32(_f32(_f32(n * (1.0 / 128.0)) * _f32(u)) * _f32(u) * _f32(1.0 - 2.0 ** -20))
+
+
+def test_quantised_contrast_screen_keeps_every_pair_that_beats_the_dc_code():
+    """A pair can replace a range's key only with F < 4096 Srr' (the key
+    starts at the DC code, the smallest (domain, isometry) of the pool), and
+    then it passes max |C'''| >= n u^2/128 - n/4 with the kernels' rounding;
+    pairs whose best k is 0 are mostly rejected."""
+    rng = np.random.default_rng(12)
+    rejected = 0
+    for b in (4, 8, 16):
+        n = b * b
+        for trial in range(2000):
+            scale = rng.choice([1, 3, 20, 255])
+            r = np.clip(128 + rng.integers(-scale, scale + 1, n), 0, 255).astype(np.int64)
+            d = np.clip(510 + rng.integers(-4 * scale, 4 * scale + 1, n), 0, 1020).astype(np.int64)
+            if trial % 4 == 0:                      # correlated: a real contrast
+                d = np.clip(510 + 2 * (r - 128) + rng.integers(-8, 9, n), 0, 1020)
+            rh = (int(r.sum()) + n // 2) // n
+            dh = (int(d.sum()) + n // 2) // n
+            c = int(((r - rh) * (d - dh)).sum())
+            srr = n * int((r * r).sum()) - int(r.sum()) ** 2
+            sdd = n * int((d * d).sum()) - int(d.sum()) ** 2
+            srd = n * int((r * d).sum()) - int(r.sum()) * int(d.sum())
+            if sdd == 0:
+                continue
+            u = np.sqrt(sdd) / n * (1.0 - 2.0 ** -20)
+            passes = _f32(abs(c)) >= _f32(quant_threshold(u, n) - _f32(n / 4.0))
+            beats = best_f(srr, srd, sdd) < 4096 * srr
+            if beats:
+                assert passes, (b, trial, c, srd, sdd)
+            elif not passes:
+                rejected += 1
+    assert rejected > 100
