@@ -218,9 +218,10 @@ def run_autotune(args, fic, images, jobs):
     rep = [r for r in rep if r["range_size"] != 0]
     for r in rep:
         progress("autotune B=%d log2D=%d bucket %d (%d images): chunk 2^%d -> 2^%d, flush %d -> %d, "
-                 "%.3f -> %.3f ms" % (r["range_size"], r["dlog2"], r["bucket"], r["images"],
-                                      r["base_chunk_log2"], r["chunk_log2"], r["base_flush_at"],
-                                      r["flush_at"], r["base_ms"], r["tuned_ms"]))
+                 "xcd %d -> %d, %.3f -> %.3f ms"
+                 % (r["range_size"], r["dlog2"], r["bucket"], r["images"], r["base_chunk_log2"],
+                    r["chunk_log2"], r["base_flush_at"], r["flush_at"], r["base_xcd"], r["xcd"],
+                    r["base_ms"], r["tuned_ms"]))
     out = {"tuned": True, "seconds": round(dt, 2)}
     if launch:
         r = launch[0]
@@ -233,6 +234,7 @@ def run_autotune(args, fic, images, jobs):
             "classes": [{"range_size": r["range_size"], "log2_domains": r["dlog2"],
                          "pool_bucket": r["bucket"], "images": r["images"],
                          "chunk_log2": r["chunk_log2"], "flush_at": r["flush_at"],
+                         "xcd_queues": r["xcd"],
                          "default_chunk_log2": r["base_chunk_log2"],
                          "default_flush_at": r["base_flush_at"],
                          "default_ms": round(r["base_ms"], 4), "tuned_ms": round(r["tuned_ms"], 4)}

@@ -378,17 +378,22 @@ fic_status fic_decode_quadtree(fic_ctx *ctx, const fic_code *codes1, const fic_g
  * sum of the searched ranges' pool sizes / (R * D)):
  *   chunk_log2  columns per work item = 2^chunk_log2, 11..16;
  *   flush_at    early flush of a wave's queue of passing cells once it holds
- *               at least this many (0 = only when full), 0..256.
+ *               at least this many (0 = only when full), 0..256;
+ *   xcd         1: a single-image search takes its work items from one
+ *               queue per XCD (the column chunks c = x mod 8 on XCD x, so
+ *               each XCD's L2 streams an eighth of the domain columns;
+ *               waves take from other queues once theirs is empty); 0: one
+ *               queue in chunk order. Batches always use one queue.
  * A row serves one (range size B, floor(log2 D)) class; classes without a
  * row use the built-in defaults (exhaustive 2^14, pooled 2^12; flush 64 at
- * B = 8, else 0). Every choice gives the same codes.
+ * B = 8, else 0; xcd 0). Every choice gives the same codes.
  *
  * fic_autotune: for the images described by descs (each with its geometry
  * and tolerance, codes written to descs[i].codes), group them by (B,
  * floor(log2 D), bucket) and, per group, time whole encodes (classify, pool,
  * search, finalize of each image alone, best of `reps`) of candidate rows by
  * coordinate descent (chunk_log2 over 11..16, then flush_at over 0, 32, 64,
- * 128), keep the winner only if a final interleaved re-measurement still has
+ * 128, then xcd), keep the winner only if a final interleaved re-measurement still has
  * it faster than the starting row, and store it in the context. BLOCKS THE
  * HOST (event synchronisation); not for stream capture. Recorded batch graphs
  * are dropped. report (host, nullable) receives up to report_cap entries, one
@@ -408,15 +413,15 @@ fic_status fic_decode_quadtree(fic_ctx *ctx, const fic_code *codes1, const fic_g
  * an unreadable or malformed one. fic_create loads the file named by the
  * environment variable FIC_TUNE_CACHE when it matches.
  * fic_tune_reset: back to the defaults.
- * fic_tune_query: the (chunk_log2, flush_at) an encode of geometry g would
- * use (pool_fraction as above, ignored when pooled = 0).
+ * fic_tune_query: the (chunk_log2, flush_at, xcd) an encode of geometry g
+ * would use (pool_fraction as above, ignored when pooled = 0; xcd nullable).
  * fic_kernel_hash: static string identifying the kernel sources of this
  * build.
  * ---------------------------------------------------------------------- */
 typedef struct {
     int32_t range_size, dlog2, bucket, images;   /* the tuning class         */
-    int32_t chunk_log2, flush_at;                /* chosen                   */
-    int32_t base_chunk_log2, base_flush_at;      /* the row it started from  */
+    int32_t chunk_log2, flush_at, xcd;           /* chosen                   */
+    int32_t base_chunk_log2, base_flush_at, base_xcd;   /* the row it started from */
     float base_ms, tuned_ms;   /* summed encode times of the class's images */
 } fic_tune_entry;
 size_t fic_autotune_workspace_bytes(int32_t n_images, const fic_image_desc *descs);
@@ -428,7 +433,8 @@ fic_status fic_tune_save(fic_ctx *ctx, const char *path);
 fic_status fic_tune_load(fic_ctx *ctx, const char *path);
 fic_status fic_tune_reset(fic_ctx *ctx);
 fic_status fic_tune_query(fic_ctx *ctx, const fic_geom *g, int32_t pooled, double pool_fraction,
-                          int32_t *chunk_log2 /* host */, int32_t *flush_at /* host */);
+                          int32_t *chunk_log2 /* host */, int32_t *flush_at /* host */,
+                          int32_t *xcd /* host, nullable */);
 const char *fic_kernel_hash(void);
 
 #ifdef __cplusplus

@@ -758,7 +758,7 @@ fic_status fic_tune_reset(fic_ctx *ctx)
 }
 
 fic_status fic_tune_query(fic_ctx *ctx, const fic_geom *g, int32_t pooled, double pool_fraction,
-                          int32_t *chunk_log2, int32_t *flush_at)
+                          int32_t *chunk_log2, int32_t *flush_at, int32_t *xcd)
 {
     if (!ctx || !g || !chunk_log2 || !flush_at || !geom_ok(g)) return FIC_ERR_INVALID_ARG;
     if (pooled && !(pool_fraction >= 0.0 && pool_fraction <= 1.0)) return FIC_ERR_INVALID_ARG;
@@ -767,6 +767,7 @@ fic_status fic_tune_query(fic_ctx *ctx, const fic_geom *g, int32_t pooled, doubl
     const int k = pooled ? fic::tune_bucket_of_fraction(pool_fraction) : 0;
     *chunk_log2 = row.chunk_log2[k];
     *flush_at = row.flush_at[k];
+    if (xcd) *xcd = row.xcd[k];
     return FIC_OK;
 }
 
@@ -899,6 +900,13 @@ fic_status fic_autotune(fic_ctx *ctx, int32_t n_images, const fic_image_desc *de
             cost(cand, t);
             if (t < t_best) { t_best = t; best = cand; }
         }
+        if (e == hipSuccess) {          // one queue per XCD, or one queue
+            fic::TuneRow cand = best;
+            cand.xcd[k] = best.xcd[k] ? 0 : 1;
+            float t = 0.0f;
+            cost(cand, t);
+            if (t < t_best) { t_best = t; best = cand; }
+        }
         if (e != hipSuccess) break;
         // measure the starting row and the winner again, interleaved, and keep
         // the winner only if it is still faster
@@ -920,8 +928,10 @@ fic_status fic_autotune(fic_ctx *ctx, int32_t n_images, const fic_image_desc *de
             r.images = (int32_t)cls.size();
             r.chunk_log2 = best.chunk_log2[k];
             r.flush_at = best.flush_at[k];
+            r.xcd = best.xcd[k];
             r.base_chunk_log2 = base.chunk_log2[k];
             r.base_flush_at = base.flush_at[k];
+            r.base_xcd = base.xcd[k];
             r.base_ms = sb;
             r.tuned_ms = sw;
         }
@@ -993,6 +1003,11 @@ fic_status fic_tune_save(fic_ctx *ctx, const char *path)
         out += "], \"flush_at\": [";
         for (int k = 0; k < fic::kTuneBuckets; ++k) {
             snprintf(line, sizeof line, "%s%d", k ? ", " : "", (int)t.row.flush_at[k]);
+            out += line;
+        }
+        out += "], \"xcd\": [";
+        for (int k = 0; k < fic::kTuneBuckets; ++k) {
+            snprintf(line, sizeof line, "%s%d", k ? ", " : "", (int)t.row.xcd[k]);
             out += line;
         }
         out += "]}";
@@ -1079,10 +1094,21 @@ fic_status fic_tune_load(fic_ctx *ctx, const char *path)
     for (;;) {
         const char *q = strstr(p, "\"range_size\"");
         if (!q) break;
-        long b = 0, dl = 0, cl[fic::kTuneBuckets], fl[fic::kTuneBuckets];
+        long b = 0, dl = 0, cl[fic::kTuneBuckets], fl[fic::kTuneBuckets], xc[fic::kTuneBuckets];
         if (!json_int(q, end, "range_size", b) || !json_int(q, end, "dlog2", dl) ||
             !json_ints(q, end, "chunk_log2", cl) || !json_ints(q, end, "flush_at", fl))
             return FIC_ERR_INVALID_ARG;
+        // "xcd" is optional (0: one queue); it belongs to this row only if it
+        // comes before the next row
+        {
+            const char *nx = strstr(q, "\"range_size\"");
+            const char *xk = strstr(q, "\"xcd\"");
+            if (xk && (!nx || xk < nx)) {
+                if (!json_ints(q, end, "xcd", xc)) return FIC_ERR_INVALID_ARG;
+            } else {
+                for (int k = 0; k < fic::kTuneBuckets; ++k) xc[k] = 0;
+            }
+        }
         if ((b != 4 && b != 8 && b != 16) || dl < 0 || dl > 40) return FIC_ERR_INVALID_ARG;
         fic_ctx::TuneEntry t;
         t.b = (int32_t)b;
@@ -1090,8 +1116,10 @@ fic_status fic_tune_load(fic_ctx *ctx, const char *path)
         for (int k = 0; k < fic::kTuneBuckets; ++k) {
             if (cl[k] < fic::kChunkLog2Min || cl[k] > fic::kChunkLog2Max || fl[k] < 0 || fl[k] > 256)
                 return FIC_ERR_INVALID_ARG;
+            if (xc[k] != 0 && xc[k] != 1) return FIC_ERR_INVALID_ARG;
             t.row.chunk_log2[k] = (int8_t)cl[k];
             t.row.flush_at[k] = (int16_t)fl[k];
+            t.row.xcd[k] = (uint8_t)xc[k];
         }
         rows.push_back(t);
         p = q;

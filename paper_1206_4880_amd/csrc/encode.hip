@@ -470,6 +470,9 @@ struct SearchArgs {
     u64 *keys;
     int shift;
     int flush_at;                // early flush trigger (0: only when the queue is full)
+    int xcd;                     // items in XCD order: one queue per XCD
+    int ncx;                     // chunk slots per XCD
+    const uint32_t *xq;          // exclusive item offsets per chunk slot (XCD x: slots x*ncx..)
 };
 
 // Per group: the union [L, H) of its active ranges' intervals (rounded to
@@ -503,30 +506,45 @@ __global__ void k_group_bounds(const RangeStat *__restrict__ rs, int64_t G, int 
 
 // Columns per work item and flush trigger of an image, from its tuning row
 // and the pool-fraction bucket of its pool sizes (exact integer sum).
-struct ItemParams { uint32_t chunk; int flush_at; };
+struct ItemParams { uint32_t chunk; int flush_at; int xcd; };
 __device__ inline ItemParams item_params(const TuneRow &t, int pooled, const u64 *pool_sum,
-                                         int64_t R, int64_t D)
+                                         int64_t R, int64_t D, int allow_xcd)
 {
     const int b = tune_bucket(pooled, pooled ? *pool_sum : 0ull, R, D);
     ItemParams ip;
     ip.chunk = 1u << t.chunk_log2[b];
     ip.flush_at = t.flush_at[b];
+    ip.xcd = allow_xcd && t.xcd[b];
     return ip;
 }
 
+// Slot of column chunk c in the work list: chunk-major, or XCD-major (the
+// chunks c = x (mod 8) of XCD x together, ncx slots per XCD).
+__device__ inline int64_t chunk_slot(int64_t c, int xcd, int64_t ncx)
+{
+    return xcd ? (c % kXcds) * ncx + c / kXcds : c;
+}
+__device__ inline int64_t slot_chunk(int64_t p, int xcd, int64_t ncx)
+{
+    return xcd ? (p % ncx) * kXcds + p / ncx : p;
+}
+
 // Per column chunk c: the run of groups [gf, gl] that touch it (both ends
-// of the group intervals are monotone in the group index), and its length.
-// NC counts chunks of the narrowest item width; with wider items the chunks
-// past the lattice get no groups.
+// of the group intervals are monotone in the group index), and its length,
+// at the chunk's slot. NC counts chunk slots of the narrowest item width (a
+// multiple of 8); with wider items the chunks past the lattice get no groups.
 __global__ void k_chunk_span(const uint4 *__restrict__ grp, int64_t G, int64_t NC, TuneRow tune,
                              int pooled, const u64 *__restrict__ pool_sum, int64_t R, int64_t D,
-                             uint32_t *__restrict__ cnt, uint32_t *__restrict__ gfirst)
+                             int allow_xcd, uint32_t *__restrict__ cnt,
+                             uint32_t *__restrict__ gfirst)
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= NC) return;
-    const uint32_t chunk = item_params(tune, pooled, pool_sum, R, D).chunk;
+    const ItemParams ip = item_params(tune, pooled, pool_sum, R, D, allow_xcd);
+    const uint32_t chunk = ip.chunk;
+    const int64_t pc = chunk_slot(c, ip.xcd, NC / kXcds);
     if ((uint64_t)c * chunk >= (uint64_t)D) {   // past the lattice (also past its padding)
-        cnt[c] = 0;
+        cnt[pc] = 0;
         gfirst[c] = 0;
         return;
     }
@@ -540,34 +558,38 @@ __global__ void k_chunk_span(const uint4 *__restrict__ grp, int64_t G, int64_t N
     a = 0; b = gact;                         // first group with L >= c1
     while (a < b) { const int64_t m = (a + b) >> 1; if (grp[m].x >= c1) b = m; else a = m + 1; }
     const int64_t gend = a;
-    cnt[c] = gend > gf ? (uint32_t)(gend - gf) : 0u;
+    cnt[pc] = gend > gf ? (uint32_t)(gend - gf) : 0u;
     gfirst[c] = (uint32_t)gf;
 }
 
-// Item i: its chunk by binary search over the scanned counts, its group by
-// offset inside the chunk's run. Column-chunk-major order: the items in
-// flight at any moment share a few column chunks, which then stay resident
-// in each XCD's L2.
+// Item i: its chunk slot by binary search over the scanned counts, its group
+// by offset inside the chunk's run. Chunk-major order: the items in flight at
+// any moment share a few column chunks, which then stay resident in each
+// XCD's L2; in XCD order, the chunks of each XCD's queue together.
 // Thread 0 also publishes the image's table entry.
 __global__ void k_emit_items(const uint4 *__restrict__ grp, const uint32_t *__restrict__ chunkoff,
                              const uint32_t *__restrict__ gfirst, int64_t NC, TuneRow tune,
                              int pooled, const u64 *__restrict__ pool_sum, int64_t R, int64_t D,
-                             const uint32_t *__restrict__ total, int64_t max_items,
+                             int allow_xcd, const uint32_t *__restrict__ total, int64_t max_items,
                              WorkItem *__restrict__ items, SearchArgs args,
                              SearchArgs *__restrict__ slot)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const ItemParams ip = item_params(tune, pooled, pool_sum, R, D);
+    const ItemParams ip = item_params(tune, pooled, pool_sum, R, D, allow_xcd);
     const uint32_t chunk = ip.chunk;
+    const int64_t ncx = NC / kXcds;
     if (i == 0) {
         args.flush_at = ip.flush_at;
+        args.xcd = ip.xcd;
+        args.ncx = (int)ncx;
+        args.xq = chunkoff;
         *slot = args;
     }
     if (i >= max_items || i >= (int64_t)*total) return;
-    int64_t a = 0, b = NC;                   // last c with chunkoff[c] <= i
+    int64_t a = 0, b = NC;                   // last slot p with chunkoff[p] <= i
     while (b - a > 1) { const int64_t m = (a + b) >> 1; if (chunkoff[m] <= (uint32_t)i) a = m; else b = m; }
-    const int64_t c = a;
-    const uint32_t g = gfirst[c] + (uint32_t)(i - chunkoff[c]);
+    const int64_t c = slot_chunk(a, ip.xcd, ncx);
+    const uint32_t g = gfirst[c] + (uint32_t)(i - chunkoff[a]);
     const uint4 gb = grp[g];
     WorkItem w;
     w.grp = g;
@@ -1140,6 +1162,55 @@ __device__ __forceinline__ void scan_blocks(const SearchArgs &a, const SearchArg
     if (cb < cb_end) screen_block<B, MASK>(ta, st, qu, b0, u0, cb);
 }
 
+// Work-item claims of a persistent wave. One counter (ctr[0]) over the items
+// of all table entries; or, for one image whose work list is in XCD order,
+// one counter per XCD queue (ctr[16 + x]): a wave starts at the queue of the
+// XCD its workgroup runs on (workgroups go to the XCDs round robin) and moves
+// on to the next queue when that one is empty, until all are empty. Every
+// wave reaches the end: each queue is finite and found empty once.
+struct ItemQueue {
+    int xq;                          // XCD queues
+    int q, left;                     // current queue, queues not yet found empty
+};
+__device__ __forceinline__ ItemQueue item_queue(const SearchArgs *tab, int32_t n_img)
+{
+    ItemQueue iq;
+    iq.xq = n_img == 1 && tab[0].xcd;
+    iq.q = (int)(blockIdx.x % kXcds);
+    iq.left = kXcds;
+    return iq;
+}
+__device__ __forceinline__ bool claim_item(uint32_t *ctr, const SearchArgs *tab, uint32_t nitems,
+                                           uint32_t dbg, ItemQueue &iq, uint32_t &item)
+{
+    const int lane = threadIdx.x & 63;
+    if (!iq.xq) {
+        uint32_t i = 0;
+        if (lane == 0) i = atomicAdd(ctr, 1u);
+        i = __builtin_amdgcn_readfirstlane(i);
+        if (i >= nitems) return false;
+        item = (dbg & kDbgReverse) ? nitems - 1u - i : i;   // order-independence check
+        return true;
+    }
+    const uint32_t *xq = tab->xq;
+    const int ncx = tab->ncx;
+    while (iq.left > 0) {
+        const int q = __builtin_amdgcn_readfirstlane(iq.q);
+        const uint32_t lo = xq[q * ncx];
+        const uint32_t hi = q == kXcds - 1 ? nitems : xq[(q + 1) * ncx];
+        uint32_t j = 0;
+        if (lane == 0) j = atomicAdd(ctr + 16 + q, 1u);
+        j = __builtin_amdgcn_readfirstlane(j);
+        if (lo + j < hi) {
+            item = (dbg & kDbgReverse) ? hi - 1u - j : lo + j;
+            return true;
+        }
+        iq.q = (q + 1) % kXcds;
+        iq.left -= 1;
+    }
+    return false;
+}
+
 // The image of global item `item` among n_img table entries with item bases
 // base[] (last entry whose base <= item), wave-uniform.
 __device__ __forceinline__ int image_of_item(const uint32_t *__restrict__ base, int32_t n_img,
@@ -1248,12 +1319,10 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma(const SearchArgs *__rest
     st.screened = 0;
     st.qn = 0;
     u64 items_done = 0;
+    ItemQueue iq = item_queue(tab, n_img);
     for (;;) {
-        uint32_t item = 0;
-        if (lane == 0) item = atomicAdd(item_ctr, 1u);
-        item = __builtin_amdgcn_readfirstlane(item);
-        if (item >= nitems) break;
-        if (dbg & kDbgReverse) item = nitems - 1u - item;   // order-independence check
+        uint32_t item;
+        if (!claim_item(item_ctr, tab, nitems, dbg, iq, item)) break;
         const int ia = image_of_item(base, n_img, item);
         const SearchArgs *ta = tab + ia;
         const SearchArgs a = *ta;
@@ -1288,6 +1357,7 @@ __global__ __launch_bounds__(256, 2) void k_search_lds16(const SearchArgs *__res
     __shared__ float sU0[SB * 16], sU1[SB * 16];    // never aliases the one being read
     __shared__ Queue16<B> queues[4];
     __shared__ uint32_t sItem;
+    __shared__ int sOk;
     const int lane = threadIdx.x & 63, col = lane & 15;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     Queue16<B> *qu = &queues[w];
@@ -1297,13 +1367,21 @@ __global__ __launch_bounds__(256, 2) void k_search_lds16(const SearchArgs *__res
     st.screened = 0;
     st.qn = 0;
     u64 items_done = 0;
+    ItemQueue iq = item_queue(tab, n_img);     // used by wave 0, which claims for the workgroup
     for (;;) {
-        if (threadIdx.x == 0) sItem = atomicAdd(item_ctr, 1u);
+        if (w == 0) {
+            uint32_t it = 0;
+            const bool ok = claim_item(item_ctr, tab, nitems, dbg, iq, it);
+            if (lane == 0) {
+                sItem = it;
+                sOk = ok ? 1 : 0;
+            }
+        }
         __syncthreads();
-        uint32_t item = sItem;
+        const uint32_t item = sItem;
+        const int ok = sOk;
         __syncthreads();
-        if (item >= nitems) break;
-        if (dbg & kDbgReverse) item = nitems - 1u - item;   // order-independence check
+        if (!ok) break;
         int ia = 0, ib = n_img;              // last image whose base <= item
         while (ib - ia > 1) {
             const int m = (ia + ib) >> 1;
@@ -1794,12 +1872,10 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma32(const SearchArgs *__re
     st.screened = 0;
     st.qn = 0;
     u64 items_done = 0;
+    ItemQueue iq = item_queue(tab, n_img);
     for (;;) {
-        uint32_t item = 0;
-        if (lane == 0) item = atomicAdd(item_ctr, 1u);
-        item = __builtin_amdgcn_readfirstlane(item);
-        if (item >= nitems) break;
-        if (dbg & kDbgReverse) item = nitems - 1u - item;   // order-independence check
+        uint32_t item;
+        if (!claim_item(item_ctr, tab, nitems, dbg, iq, item)) break;
         const int ia = image_of_item(base, n_img, item);
         const SearchArgs *ta = tab + ia;
         const SearchArgs a = *ta;
@@ -2062,7 +2138,7 @@ hipError_t run_plain_b(const EncodePlan &p, const uint8_t *img, const uint32_t *
 template <int B>
 hipError_t prep_b(const EncodePlan &p, const uint8_t *img, const uint32_t *perm,
                   const uint32_t *lo, const uint32_t *hi, void *ws, u64 *counters,
-                  SearchArgs *slot, hipStream_t s, const Tracer *tr)
+                  SearchArgs *slot, hipStream_t s, const Tracer *tr, int allow_xcd)
 {
     const Geom &g = p.g;
     char *w = (char *)ws;
@@ -2113,16 +2189,18 @@ hipError_t prep_b(const EncodePlan &p, const uint8_t *img, const uint32_t *perm,
     hipLaunchKernelGGL(k_group_bounds, dim3(blocks_for(p.IG, th)), dim3(th), 0, s, rs, p.IG,
                        (int)(p.GR * p.IGW), (uint32_t)p.Dp, (uint32_t)Cfg<B>::MR, grp, pool_sum);
     hipLaunchKernelGGL(k_chunk_span, dim3(blocks_for(p.NC, th)), dim3(th), 0, s, grp, p.IG, p.NC,
-                       p.tune, p.pooled, (const u64 *)pool_sum, g.R, g.D, chunkcnt, chunkfill);
+                       p.tune, p.pooled, (const u64 *)pool_sum, g.R, g.D, allow_xcd, chunkcnt,
+                       chunkfill);
     // exclusive scan of the per-chunk counts; the total is the item count
     const hipError_t se = scan_u32(chunkcnt, p.NC, ctr + 1, w + p.off_scan, s);
     if (se != hipSuccess) return se;
     SearchArgs a;
     a.A = A; a.Bm = Bm; a.u = u; a.eps = eps; a.sdd = sdd; a.dom = dom; a.rs = rs; a.grp = grp;
     a.items = items; a.n_items = ctr + 1; a.keys = keys; a.shift = p.shift; a.flush_at = 0;
+    a.xcd = 0; a.ncx = 0; a.xq = nullptr;
     hipLaunchKernelGGL(k_emit_items, dim3(blocks_for(p.max_items, th)), dim3(th), 0, s, grp,
                        chunkcnt, chunkfill, p.NC, p.tune, p.pooled, (const u64 *)pool_sum, g.R,
-                       g.D, ctr + 1, p.max_items, items, a, slot);
+                       g.D, allow_xcd, ctr + 1, p.max_items, items, a, slot);
     trace(tr, FIC_STAGE_WORKLIST, 0, s);
     return hipGetLastError();
 }
@@ -2189,7 +2267,7 @@ hipError_t run_encode_b(const EncodePlan &p, const uint8_t *img, const uint32_t 
     char *w = (char *)ws;
     uint32_t *ctr = (uint32_t *)(w + p.off_ctr);   // [0] item counter, [1] items, [2..3] bases
     SearchArgs *slot = (SearchArgs *)(w + p.off_args);
-    hipError_t e = prep_b<B>(p, img, perm, lo, hi, ws, counters, slot, s, tr);
+    hipError_t e = prep_b<B>(p, img, perm, lo, hi, ws, counters, slot, s, tr, 1);
     if (e == hipSuccess) e = search_b<B>(slot, 1, ctr + 2, ctr, num_cu, counters, p.dbg, s, tr);
     if (e == hipSuccess) e = finalize_b<B>(p, img, ws, codes, s, tr);
     return e;
@@ -2200,7 +2278,8 @@ hipError_t batch_phase(int phase, const EncodePlan &p, const uint8_t *img, const
                        const uint32_t *lo, const uint32_t *hi, void *ws, u64 *counters,
                        SearchArgs *slot, fic_code *codes, hipStream_t s, const Tracer *tr)
 {
-    return phase == 0 ? prep_b<B>(p, img, perm, lo, hi, ws, counters, slot, s, tr)
+    // batches share one queue over all images: chunk-major work lists
+    return phase == 0 ? prep_b<B>(p, img, perm, lo, hi, ws, counters, slot, s, tr, 0)
                       : finalize_b<B>(p, img, ws, codes, s, tr);
 }
 
@@ -2234,6 +2313,7 @@ void plan_encode(const Geom &g, int pooled, EncodePlan &p)
     p.IG = p.G / p.IGW;
     p.Dp = (g.D + mr - 1) / mr * mr;
     p.NC = (p.Dp + ((int64_t)1 << kChunkLog2Min) - 1) >> kChunkLog2Min;
+    p.NC = (p.NC + kXcds - 1) / kXcds * kXcds;
     p.max_items = p.IG * p.NC;
     int dbits = 1;
     while (((int64_t)1 << dbits) < g.D) ++dbits;

@@ -105,13 +105,19 @@ struct WorkItem { uint32_t grp, c0, c1, pad; };
 // clamped to [1, kTuneBuckets - 1]. Per bucket: the columns of a work item
 // (2^chunk_log2, kChunkLog2Min..kChunkLog2Max) and the early flush trigger of
 // the search queue (flush once at least flush_at half cells (4x4: cells) are
-// queued; 0 = only when the queue is full). A row serves one (range size,
-// log2 D) class; the autotuner fills rows, defaults are below.
+// queued; 0 = only when the queue is full), and whether a single-image
+// search takes its work items from one queue per XCD (xcd = 1: queue x holds
+// the column chunks c = x (mod 8), so each XCD's L2 streams an eighth of the
+// domain columns; waves steal from the other queues when theirs is empty).
+// A row serves one (range size, log2 D) class; the autotuner fills rows,
+// defaults are below.
 constexpr int kTuneBuckets = 6;
 constexpr int kChunkLog2Min = 11, kChunkLog2Max = 16;
+constexpr int kXcds = 8;             // MI355X: 8 XCDs, workgroups assigned round robin
 struct TuneRow {
     int8_t chunk_log2[kTuneBuckets];
     int16_t flush_at[kTuneBuckets];
+    uint8_t xcd[kTuneBuckets];
 };
 // Exhaustive jobs 16384-column items, pooled 4096 (narrow pools need the
 // finer balance); the early flush at 64 queued half cells only at 8x8.
@@ -121,6 +127,7 @@ inline TuneRow default_tune_row(int b)
     for (int k = 0; k < kTuneBuckets; ++k) {
         r.chunk_log2[k] = (int8_t)(k == 0 ? 14 : 12);
         r.flush_at[k] = (int16_t)(b == 8 ? 64 : 0);
+        r.xcd[k] = 0;
     }
     return r;
 }
@@ -297,7 +304,8 @@ struct EncodePlan {
     int pooled;
     int64_t Rp, Dp, G, GR, NC;   // padded ranges/columns, groups, ranges per group, chunks
     int64_t IGW, IG;              // groups per work item (one per wave of a workgroup), item groups
-    int32_t shift;                // NC: chunks at the narrowest item (2^kChunkLog2Min columns)
+    int32_t shift;                // NC: chunk slots at the narrowest item (2^kChunkLog2Min
+                                  // columns), a multiple of kXcds
     int64_t max_items;
     size_t off_A, off_rs, off_order, off_B, off_u, off_eps, off_sdd, off_dom, off_keys,
         off_items, off_ctr, off_args, off_chunkcnt, off_chunkfill, off_grp, off_bmin, off_S,

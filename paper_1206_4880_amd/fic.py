@@ -43,7 +43,8 @@ class TuneEntry(ctypes.Structure):
     _fields_ = [("range_size", ctypes.c_int32), ("dlog2", ctypes.c_int32),
                 ("bucket", ctypes.c_int32), ("images", ctypes.c_int32),
                 ("chunk_log2", ctypes.c_int32), ("flush_at", ctypes.c_int32),
-                ("base_chunk_log2", ctypes.c_int32), ("base_flush_at", ctypes.c_int32),
+                ("xcd", ctypes.c_int32), ("base_chunk_log2", ctypes.c_int32),
+                ("base_flush_at", ctypes.c_int32), ("base_xcd", ctypes.c_int32),
                 ("base_ms", ctypes.c_float), ("tuned_ms", ctypes.c_float)]
 
 
@@ -109,7 +110,7 @@ def lib():
         "fic_tune_load": (_st, [_vp, ctypes.c_char_p]),
         "fic_tune_reset": (_st, [_vp]),
         "fic_tune_query": (_st, [_vp, ctypes.POINTER(Geom), _i32, ctypes.c_double,
-                                 ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+                                 ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
         "fic_kernel_hash": (ctypes.c_char_p, []),
         "fic_noalloc_scratch_bytes": (ctypes.c_size_t, []),
         "fic_encode_pifs_noalloc": (_st, [_vp, _vp, ctypes.POINTER(Geom), _vp, _vp, _vp, _i32, _vp,
@@ -209,13 +210,17 @@ class Context:
     def tune_reset(self):
         _check(lib().fic_tune_reset(self.handle), "fic_tune_reset")
 
-    def tune_query(self, height, width, range_size, domain_step, pooled=False, pool_fraction=1.0):
-        """(chunk_log2, flush_at) an encode of this geometry would use."""
+    def tune_query(self, height, width, range_size, domain_step, pooled=False, pool_fraction=1.0,
+                   with_xcd=False):
+        """(chunk_log2, flush_at) an encode of this geometry would use, and
+        the XCD-queue flag with with_xcd=True."""
         g = make_geom(height, width, range_size, domain_step)
-        cl, fl = _i32(0), _i32(0)
+        cl, fl, xc = _i32(0), _i32(0), _i32(0)
         _check(lib().fic_tune_query(self.handle, ctypes.byref(g), 1 if pooled else 0,
-                                    float(pool_fraction), ctypes.byref(cl), ctypes.byref(fl)),
-               "fic_tune_query")
+                                    float(pool_fraction), ctypes.byref(cl), ctypes.byref(fl),
+                                    ctypes.byref(xc)), "fic_tune_query")
+        if with_xcd:
+            return int(cl.value), int(fl.value), int(xc.value)
         return int(cl.value), int(fl.value)
 
 

@@ -282,10 +282,11 @@ def test_debug_switch_validation(L, hctx):
     assert L.fic_set_debug(hctx.handle, 0) == fic.OK
 
 
-def _tune_file(path, arch, khash, rows):
+def _tune_file(path, arch, khash, rows, xcd=None):
     import json
     doc = {"format": "fic-tune-1", "arch": arch, "kernel_hash": khash,
-           "rows": [{"range_size": b, "dlog2": dl, "chunk_log2": cl, "flush_at": fl}
+           "rows": [dict({"range_size": b, "dlog2": dl, "chunk_log2": cl, "flush_at": fl},
+                         **({"xcd": xcd} if xcd is not None else {}))
                     for b, dl, cl, fl in rows]}
     with open(path, "w") as f:
         json.dump(doc, f)
@@ -316,6 +317,14 @@ def test_tune_defaults_and_bucket_rule(L, tmp_path):
         assert q(0.0624) == (16, 256) and q(0.0) == (16, 256)
         # another lattice class keeps the defaults
         assert c.tune_query(512, 512, 8, 1) == (14, 64)
+        assert c.tune_query(1024, 1024, 8, 1, with_xcd=True) == (11, 0, 0)   # no "xcd": 0
+        _tune_file(p, "none", fic.kernel_hash(),
+                   [(8, dl, [11, 12, 13, 14, 15, 16], [0, 32, 64, 128, 192, 256])],
+                   xcd=[1, 0, 1, 0, 1, 0])
+        assert c.tune_load(p) == fic.OK
+        assert c.tune_query(1024, 1024, 8, 1, with_xcd=True) == (11, 0, 1)
+        assert c.tune_query(1024, 1024, 8, 1, pooled=True, pool_fraction=0.3,
+                            with_xcd=True) == (13, 64, 1)
         # save -> reset -> load round trip
         p2 = str(tmp_path / "t2.json")
         c.tune_save(p2)
@@ -340,6 +349,8 @@ def test_tune_cache_rejections(L, tmp_path):
         assert c.tune_load(p) == fic.ERR_INVALID_ARG              # item width out of range
         _tune_file(p, "none", fic.kernel_hash(), [(6, 20, [12] * 6, [64] * 6)])
         assert c.tune_load(p) == fic.ERR_INVALID_ARG              # range size
+        _tune_file(p, "none", fic.kernel_hash(), [(8, 20, [12] * 6, [64] * 6)], xcd=[2] * 6)
+        assert c.tune_load(p) == fic.ERR_INVALID_ARG              # xcd is 0 or 1
         with open(p, "w") as f:
             f.write("not json")
         assert c.tune_load(p) == fic.ERR_INVALID_ARG

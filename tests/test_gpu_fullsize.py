@@ -163,6 +163,35 @@ def test_reverse_item_order(fic, orc, golden, job):
         check_digests(orc, rec, img, rev, jid_of(*job) + " reversed")
 
 
+@pytest.mark.parametrize("chunk_log2", [13, 16])
+def test_xcd_queues_every_range(fic, orc, golden, tmp_path, chunk_log2):
+    """Single-image searches taking their items from one queue per XCD (with
+    stealing), at two item widths, on the 1024^2 jobs and the 2048^2 8x8
+    job: every range equals the oracle digests."""
+    from synth import workload_images
+    ctx = fic.fic.context()
+    arch = torch.cuda.get_device_properties(0).gcnArchName
+    path = str(tmp_path / "xcd.json")
+    rows = [{"range_size": b, "dlog2": dl, "chunk_log2": [chunk_log2] * 6, "flush_at": [64] * 6,
+             "xcd": [1] * 6} for b in (4, 8, 16) for dl in range(0, 31)]
+    with open(path, "w") as f:
+        json.dump({"format": "fic-tune-1", "arch": arch, "kernel_hash": fic.fic.kernel_hash(),
+                   "rows": rows}, f)
+    assert ctx.tune_load(path) == fic.fic.OK
+    try:
+        for job in [("fbm1024_b8t1", 8, 1, None), ("fbm1024_b8t1", 8, 1, 0.02),
+                    ("fbm1024_b8t1", 8, 1, 0.1), ("fbm2048_twolevel", 8, 2, 0.05),
+                    ("fbm2048_twolevel", 16, 4, 0.05)]:
+            rec = golden["jobs"].get(jid_of(*job))
+            if not rec or not rec["blocks"]:
+                continue
+            img = workload_images(job[0])
+            got = gpu_codes(fic, img, *job[1:])
+            check_digests(orc, rec, img, got, jid_of(*job) + " xcd queues")
+    finally:
+        ctx.tune_reset()
+
+
 def test_batch64_every_range(fic, orc, golden):
     """The 64-image mixed batch in one call (graph): every image's codes
     against its oracle digests; then the same batch with the work items

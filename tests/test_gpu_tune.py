@@ -46,11 +46,12 @@ def _codes(fic, cases):
     return out
 
 
-def _write_rows(path, chunk_log2, flush_at):
+def _write_rows(path, chunk_log2, flush_at, xcd=0):
     arch = torch.cuda.get_device_properties(0).gcnArchName
     import paper_1206_4880_amd as p
     rows = [{"range_size": b, "dlog2": dl, "chunk_log2": [chunk_log2] * 6,
-             "flush_at": [flush_at] * 6} for b in (4, 8, 16) for dl in range(0, 31)]
+             "flush_at": [flush_at] * 6, "xcd": [xcd] * 6}
+            for b in (4, 8, 16) for dl in range(0, 31)]
     with open(path, "w") as f:
         json.dump({"format": "fic-tune-1", "arch": arch, "kernel_hash": p.fic.kernel_hash(),
                    "rows": rows}, f)
@@ -65,12 +66,14 @@ def test_codes_identical_under_every_candidate(fic, tmp_path):
     try:
         for cl in range(11, 17):
             for fl in (0, 32, 128):
-                _write_rows(path, cl, fl)
-                assert ctx.tune_load(path) == fic.fic.OK
-                assert ctx.tune_query(512, 512, 8, 2) == (cl, fl)
-                got = _codes(fic, cases)
-                for (name, *_), a, b in zip(cases, ref, got):
-                    assert np.array_equal(a, b), "%s, chunk 2^%d, flush %d" % (name, cl, fl)
+                for xc in (0, 1):
+                    _write_rows(path, cl, fl, xc)
+                    assert ctx.tune_load(path) == fic.fic.OK
+                    assert ctx.tune_query(512, 512, 8, 2, with_xcd=True) == (cl, fl, xc)
+                    got = _codes(fic, cases)
+                    for (name, *_), a, b in zip(cases, ref, got):
+                        assert np.array_equal(a, b), "%s, chunk 2^%d, flush %d, xcd %d" % (
+                            name, cl, fl, xc)
     finally:
         ctx.tune_reset()
 
@@ -97,6 +100,7 @@ def test_autotune_then_cache_round_trip(fic, tmp_path):
             assert launch[0]["tuned_ms"] <= launch[0]["base_ms"]
         for r in rep:
             assert 11 <= r["chunk_log2"] <= 16 and r["flush_at"] in (0, 32, 64, 128)
+            assert r["xcd"] in (0, 1)
             assert r["tuned_ms"] <= r["base_ms"]
             print("B=%d log2 D=%d bucket %d (%d images): chunk 2^%d flush %d, %.3f -> %.3f ms"
                   % (r["range_size"], r["dlog2"], r["bucket"], r["images"], r["chunk_log2"],
