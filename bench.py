@@ -82,6 +82,8 @@ def parse():
                     help="time the built-in search parameters (skip the autotuner)")
     ap.add_argument("--tune-reps", type=int, default=2,
                     help="encodes per candidate in the autotuner (best of)")
+    ap.add_argument("--tune-file", default=None,
+                    help="load these search parameters (fic_tune_load) instead of autotuning")
     ap.add_argument("--separate-searches", action="store_true",
                     help="batch: one search launch per range size instead of the combined one")
     return ap.parse_args()
@@ -209,6 +211,11 @@ def pool_margin(fr_t, fd_t, tol):
 def run_autotune(args, fic, images, jobs):
     """The library's autotuner on the workload's own images (untimed); the
     timed steps then run with its choices. Returns the report."""
+    if args.tune_file:
+        st = fic.fic.context(images[0].device.index).tune_load(args.tune_file)
+        if st != fic.fic.OK:
+            raise SystemExit("tune file %s not loaded (status %d)" % (args.tune_file, st))
+        return {"tuned": "file", "file": os.path.basename(args.tune_file)}
     if args.no_tune:
         return {"tuned": False}
     t0 = time.perf_counter()
