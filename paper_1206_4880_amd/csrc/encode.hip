@@ -801,15 +801,25 @@ __device__ __noinline__ void flush16(const SearchArgs *ta, uint32_t nq, Queue16<
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
 
+// Fit and empty the queue. The thresholds the wave screens with are reloaded
+// separately (refresh16): a block's pass tests are all taken before its
+// cells are queued, so a flush in the middle of queueing them changes
+// nothing for that block, and keeping the thresholds fixed until the block
+// is queued keeps them out of the queueing branches' register copies.
 template <int B>
-__device__ __forceinline__ void flush_and_refresh16(const SearchArgs *ta, WaveState<B> &st,
-                                                    Queue16<B> *qu)
+__device__ __forceinline__ void flush_queue16(const SearchArgs *ta, WaveState<B> &st,
+                                              Queue16<B> *qu)
+{
+    flush16<B>(ta, st.qn, qu, st.grp);
+    st.survivors += 4ull * st.qn;    // wave-uniform
+    st.qn = 0;
+}
+
+template <int B>
+__device__ __forceinline__ void refresh16(WaveState<B> &st, const Queue16<B> *qu)
 {
     constexpr int MW = Cfg<B>::MB;
     const int lane = threadIdx.x & 63;
-    flush16<B>(ta, st.qn, qu, st.grp);
-    st.survivors += lane == 0 ? 4ull * st.qn : 0ull;
-    st.qn = 0;
 #pragma unroll
     for (int b = 0; b < MW; ++b)
         if (st.T[b] != __builtin_inff())        // searched ranges only
@@ -840,14 +850,18 @@ __device__ __forceinline__ void mma_block(const WaveState<B> &st,
 template <int B>
 __device__ __forceinline__ void queue_rowblock(const SearchArgs *ta, WaveState<B> &st,
                                                Queue16<B> *qu, int b, bool pass,
-                                               const float4_t (&accb)[Cfg<B>::NCH], uint32_t p)
+                                               const float4_t (&accb)[Cfg<B>::NCH], uint32_t p,
+                                               bool &flushed)
 {
     constexpr int NCH = Cfg<B>::NCH;
     const int lane = threadIdx.x & 63;
     const u64 ball = __ballot(pass);
     if (ball == 0) return;
     const uint32_t cnt = (uint32_t)__popcll(ball);
-    if (st.qn + cnt > (uint32_t)queue16_cap<B>()) flush_and_refresh16<B>(ta, st, qu);
+    if (st.qn + cnt > (uint32_t)queue16_cap<B>()) {
+        flush_queue16<B>(ta, st, qu);
+        flushed = true;
+    }
     if (pass) {
         const uint32_t below = __builtin_amdgcn_mbcnt_hi(
             (uint32_t)(ball >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ball, 0u));
@@ -930,9 +944,14 @@ __device__ __forceinline__ void screen_acc(const SearchArgs *ta, WaveState<B> &s
     }
     if (!MASK) hit = dmax >= -slack;
     if (!wave_any(hit)) return;
+    bool flushed = false;
 #pragma unroll
-    for (int b = 0; b < MW; ++b) queue_rowblock<B>(ta, st, qu, b, pass[b], acc[b], p);
-    if (st.flush_at && st.qn >= st.flush_at) flush_and_refresh16<B>(ta, st, qu);
+    for (int b = 0; b < MW; ++b) queue_rowblock<B>(ta, st, qu, b, pass[b], acc[b], p, flushed);
+    if (st.flush_at && st.qn >= st.flush_at) {
+        flush_queue16<B>(ta, st, qu);
+        flushed = true;
+    }
+    if (flushed) refresh16<B>(st, qu);
 }
 
 template <int B, bool MASK>
@@ -1062,8 +1081,12 @@ __device__ __forceinline__ void screen_block_lds(const SearchArgs *ta, WaveState
     if (!MASK) hit = dmax >= -slack;
     if (!wave_any(hit)) return;
     // exact chunk sums, exact screen and queue, one row block at a time
+    // (after a flush in the middle, the later row blocks still screen with
+    // the thresholds the block started with: looser, never wrong, and the
+    // flush re-screens every queued cell against the current ones)
     constexpr int NCH = C::NCH, KPC = KS / NCH;
     const float slx = screen_slack<B>();
+    bool flushed = false;
 #pragma unroll
     for (int b = 0; b < MW; ++b) {
         float4_t ax[NCH];
@@ -1080,9 +1103,13 @@ __device__ __forceinline__ void screen_block_lds(const SearchArgs *ta, WaveState
         const float m = fmaxf(fmaxf(fabsf(sv[0]), fabsf(sv[1])), fmaxf(fabsf(sv[2]), fabsf(sv[3])));
         bool h = fmaf(-st.T[b], u, m) >= -slx;
         if (MASK) h = h && p >= st.lo[b] && p < st.hi[b];
-        queue_rowblock<B>(ta, st, qu, b, h, ax, p);
+        queue_rowblock<B>(ta, st, qu, b, h, ax, p, flushed);
     }
-    if (st.flush_at && st.qn >= st.flush_at) flush_and_refresh16<B>(ta, st, qu);
+    if (st.flush_at && st.qn >= st.flush_at) {
+        flush_queue16<B>(ta, st, qu);
+        flushed = true;
+    }
+    if (flushed) refresh16<B>(st, qu);
 }
 
 // Column blocks [cb_begin, cb_end) against the wave's A rows. The B
@@ -1275,7 +1302,7 @@ __device__ __forceinline__ void item16(const SearchArgs *ta, const SearchArgs &a
     scan_blocks<B, true>(a, ta, st, qu, cb0, ib0);
     scan_blocks<B, false>(a, ta, st, qu, ib0, ib1);
     scan_blocks<B, true>(a, ta, st, qu, ib1, cb1);
-    if (st.qn) flush_and_refresh16<B>(ta, st, qu);
+    if (st.qn) flush_queue16<B>(ta, st, qu);
     if (lane < GR) {
         const u64 bk = qu->best[lane];
         if (bk != kNoKey) atomicMin(&a.keys[(int64_t)st.grp * GR + lane], bk);
@@ -1288,13 +1315,9 @@ __device__ __forceinline__ void add_counters(u64 *counters, u64 screened, u64 su
                                              u64 items_done)
 {
     if (!counters) return;
-    const int lane = threadIdx.x & 63;
-    u64 sv = survivors;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) sv += __shfl_xor(sv, off);
-    if (lane == 0) {
+    if ((threadIdx.x & 63) == 0) {      // all three counts are wave-uniform
         atomicAdd(&counters[0], screened);
-        atomicAdd(&counters[1], sv);
+        atomicAdd(&counters[1], survivors);
         atomicAdd(&counters[2], items_done);
     }
 }
@@ -1489,7 +1512,7 @@ __global__ __launch_bounds__(256, 2) void k_search_lds16(const SearchArgs *__res
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
         }
-        if (st.qn) flush_and_refresh16<B>(ta, st, qu);
+        if (st.qn) flush_queue16<B>(ta, st, qu);
         if (lane < GR) {
             const u64 bk = qu->best[lane];
             if (bk != kNoKey) atomicMin(&a.keys[(int64_t)st.grp * GR + lane], bk);
@@ -1497,15 +1520,10 @@ __global__ __launch_bounds__(256, 2) void k_search_lds16(const SearchArgs *__res
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         items_done += 1;
     }
-    if (counters) {
-        u64 sv = st.survivors;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) sv += __shfl_xor(sv, off);
-        if (lane == 0) {
-            atomicAdd(&counters[0], st.screened);
-            atomicAdd(&counters[1], sv);
-            if (w == 0) atomicAdd(&counters[2], items_done);
-        }
+    if (counters && lane == 0) {       // wave-uniform counts
+        atomicAdd(&counters[0], st.screened);
+        atomicAdd(&counters[1], st.survivors);
+        if (w == 0) atomicAdd(&counters[2], items_done);
     }
 }
 
@@ -1637,15 +1655,22 @@ __device__ __noinline__ void flush32(const SearchArgs *ta, uint32_t nq, Queue32<
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
 
+// Fit and empty the queue; the thresholds in registers are reloaded by
+// refresh32 once the current block's cells are queued (as flush_queue16).
 template <int B>
-__device__ __forceinline__ void flush_and_refresh(const SearchArgs *ta, Wave32<B> &st,
-                                                  Queue32<B> *qu)
+__device__ __forceinline__ void flush_queue32(const SearchArgs *ta, Wave32<B> &st,
+                                              Queue32<B> *qu)
+{
+    flush32<B>(ta, st.qn, qu, st.grp);
+    st.survivors += 8ull * st.qn;    // wave-uniform
+    st.qn = 0;
+}
+
+template <int B>
+__device__ __forceinline__ void refresh32(Wave32<B> &st, const Queue32<B> *qu)
 {
     constexpr int MB = Cfg<B>::MB;
     const int h = (threadIdx.x >> 5) & 1;
-    flush32<B>(ta, st.qn, qu, st.grp);
-    st.survivors += (threadIdx.x & 63) == 0 ? 8ull * st.qn : 0ull;
-    st.qn = 0;
 #pragma unroll
     for (int blk = 0; blk < MB; ++blk)
 #pragma unroll
@@ -1691,6 +1716,7 @@ __device__ __forceinline__ void screen32(const SearchArgs &a, const SearchArgs *
     // append the passing cells (at most 64 per row block half), each as one
     // 32-byte record of its 8 cross terms (the flush applies the clamped- and
     // quantised-contrast tests; here they did not remove enough cells to pay)
+    bool flushed = false;
 #pragma unroll
     for (int blk = 0; blk < MB; ++blk)
 #pragma unroll
@@ -1698,7 +1724,10 @@ __device__ __forceinline__ void screen32(const SearchArgs &a, const SearchArgs *
             const u64 ball = __ballot(pass[blk][hl]);
             if (ball == 0) continue;
             const uint32_t cnt = (uint32_t)__popcll(ball);
-            if (st.qn + cnt > (uint32_t)kQueue) flush_and_refresh<B>(ta, st, qu);
+            if (st.qn + cnt > (uint32_t)kQueue) {
+                flush_queue32<B>(ta, st, qu);
+                flushed = true;
+            }
             if (pass[blk][hl]) {
                 const uint32_t below = __builtin_amdgcn_mbcnt_hi(
                     (uint32_t)(ball >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ball, 0u));
@@ -1711,7 +1740,11 @@ __device__ __forceinline__ void screen32(const SearchArgs &a, const SearchArgs *
             }
             st.qn += cnt;
         }
-    if (st.flush_at && st.qn >= st.flush_at) flush_and_refresh<B>(ta, st, qu);
+    if (st.flush_at && st.qn >= st.flush_at) {
+        flush_queue32<B>(ta, st, qu);
+        flushed = true;
+    }
+    if (flushed) refresh32<B>(st, qu);
 }
 
 // Column blocks [cb_begin, cb_end): the B fragments and u of the block PD
@@ -1849,7 +1882,7 @@ __device__ __forceinline__ void item32(const SearchArgs *ta, const SearchArgs &a
     scan32<B, true>(a, ta, st, qu, cb0, ib0);
     scan32<B, false>(a, ta, st, qu, ib0, ib1);
     scan32<B, true>(a, ta, st, qu, ib1, cb1);
-    if (st.qn) flush_and_refresh<B>(ta, st, qu);
+    if (st.qn) flush_queue32<B>(ta, st, qu);
     if (lane < GR) {
         const u64 bk = qu->best[lane];
         if (bk != kNoKey) atomicMin(&a.keys[(int64_t)st.grp * GR + lane], bk);
