@@ -118,6 +118,8 @@ const char *fic_status_string(fic_status s);
    caller) is set, the search kernels add
      [0] pair evaluations screened, [1] pairs passed to the exact fit,
      [2] work items processed,      [3] exact seeds evaluated,
+     [7] columns the 4x4 search queued and replayed (recomputed on the
+         matrix cores and screened cell by cell),
    and with FIC_DEBUG_VERIFY16 (fic_set_debug) the 16x16 search adds
      [4] FP32 sums whose rounding error exceeded the bound its screen
          threshold is lowered by (must stay 0),

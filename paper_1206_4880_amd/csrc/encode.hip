@@ -1532,13 +1532,25 @@ __global__ __launch_bounds__(256, 2) void k_search_lds16(const SearchArgs *__res
 // 4*blk+3 under the 8 isometries. Lane l's 16 outputs of a tile are column
 // l%32 against range 4*blk + 2*(l/32) (v < 8) and that + 1 (v >= 8), under
 // isometry v%8: whole cells. Per block: MB*KS MFMAs, then per lane and range
-// half one 8-value maximum, one fma and one compare. (A 4x4 range meets many
-// near-optimal domains, so its cells pass the screen far more often than
-// those of larger ranges: the queue matters most there.)
+// half one 8-value maximum, one fma and one compare.
+// A 4x4 range meets many near-optimal domains: on smooth images nearly every
+// block has a passing cell. So the scan only queues the COLUMNS in which some
+// cell passes (one ballot and one LDS store per block); once kColReplay
+// columns are queued (tested after every group of blocks), replay32 gathers
+// their B fragments, redoes the MFMAs, screens each cell against its range's
+// current threshold and pool window, and queues the passing cells, with
+// their cross terms, for the exact fit (flush32).
+constexpr int kColReplay = 64;
+constexpr int kColQ = kColReplay + 4 * 32;   // + one group of 4 blocks: no overflow check per block
+
 template <int B> struct Queue32 {
     float4_t c[kQueue][2];           // the cell's cross terms, isometries 0-3 and 4-7
     uint32_t p[kQueue];              // column
     uint32_t ls[kQueue];             // range within the wave's group
+    uint32_t colp[kColQ];            // queued columns
+    float colu[kColQ];               // their u
+    uint32_t lo[Cfg<B>::GR];         // pool windows of the wave's ranges (empty if idle)
+    uint32_t hi[Cfg<B>::GR];
     u64 best[Cfg<B>::GR];            // best keys of the wave's ranges
     float T[Cfg<B>::GR];             // their thresholds
     int64_t srr[Cfg<B>::GR];         // their Srr'
@@ -1552,8 +1564,9 @@ template <int B> struct Wave32 {
     uint32_t lo[MB][2], hi[MB][2];
     uint32_t grp;
     uint32_t qn;                     // queued cells (wave-uniform)
+    uint32_t cq;                     // queued columns (wave-uniform)
     uint32_t flush_at;               // early flush trigger (0: off)
-    u64 survivors, screened;
+    u64 survivors, screened, replayed;
 };
 
 __device__ __forceinline__ float max8(const float16_t &a, int base)
@@ -1655,8 +1668,7 @@ __device__ __noinline__ void flush32(const SearchArgs *ta, uint32_t nq, Queue32<
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
 
-// Fit and empty the queue; the thresholds in registers are reloaded by
-// refresh32 once the current block's cells are queued (as flush_queue16).
+// Fit and empty the cell queue.
 template <int B>
 __device__ __forceinline__ void flush_queue32(const SearchArgs *ta, Wave32<B> &st,
                                               Queue32<B> *qu)
@@ -1679,16 +1691,112 @@ __device__ __forceinline__ void refresh32(Wave32<B> &st, const Queue32<B> *qu)
                 st.T[blk][hl] = qu->T[4 * blk + 2 * h + hl];
 }
 
+// Queue the passing cells of one 32-column tile (pass: the lane's two cells
+// of each row block), each as one 32-byte record of its 8 cross terms,
+// fitting and emptying the queue first whenever it would overflow. Returns
+// the queue's new length; fitted gains the cells fitted on the way.
+template <int B>
+__device__ __forceinline__ uint32_t queue_cells32(const SearchArgs *ta, uint32_t qn,
+                                                  Queue32<B> *qu, uint32_t grp,
+                                                  const float16_t (&acc)[Cfg<B>::MB],
+                                                  const bool (&pass)[Cfg<B>::MB][2], uint32_t p,
+                                                  uint32_t &fitted)
+{
+    constexpr int MB = Cfg<B>::MB;
+    const int h = (threadIdx.x >> 5) & 1;
+#pragma unroll
+    for (int blk = 0; blk < MB; ++blk)
+#pragma unroll
+        for (int hl = 0; hl < 2; ++hl) {
+            const u64 ball = __ballot(pass[blk][hl]);
+            if (ball == 0) continue;
+            const uint32_t cnt = (uint32_t)__popcll(ball);
+            if (qn + cnt > (uint32_t)kQueue) {
+                flush32<B>(ta, qn, qu, grp);
+                fitted += qn;
+                qn = 0;
+            }
+            if (pass[blk][hl]) {
+                const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+                    (uint32_t)(ball >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ball, 0u));
+                const uint32_t pos = qn + below;
+                const float16_t &av = acc[blk];
+                qu->c[pos][0] = float4_t{av[8 * hl + 0], av[8 * hl + 1], av[8 * hl + 2], av[8 * hl + 3]};
+                qu->c[pos][1] = float4_t{av[8 * hl + 4], av[8 * hl + 5], av[8 * hl + 6], av[8 * hl + 7]};
+                qu->p[pos] = p;
+                qu->ls[pos] = (uint32_t)(4 * blk + 2 * h + hl);
+            }
+            qn += cnt;
+        }
+    return qn;
+}
+
+// Replay and empty the column queue, 32 columns per tile: gather their B
+// fragments, redo the MFMAs against the wave's A fragments (the same exact
+// cross terms as in the scan) and screen every cell again, against its
+// range's current threshold (never looser than when the column was queued)
+// and pool window. The passing cells go to the cell queue, which is fitted
+// whenever it would overflow and, at the end, once it holds flush_at cells;
+// the thresholds in registers are reloaded.
+template <int B>
+__device__ __forceinline__ void replay_queue32(const SearchArgs *ta, Wave32<B> &st,
+                                               Queue32<B> *qu)
+{
+    constexpr int MB = Cfg<B>::MB;
+    static_assert(Cfg<B>::KS == 1, "one K step per 32 x 32 tile");
+    const float slack = screen_slack<B>();
+    const int lane = threadIdx.x & 63, h = lane >> 5, col = lane & 31;
+    const half8_t *gb = (const half8_t *)uniform_ptr(ta->Bm);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    const uint32_t ncol = st.cq, grp = st.grp;
+    uint32_t qn = st.qn, fitted = 0;
+    for (uint32_t c0 = 0; c0 < ncol; c0 += 32) {
+        const bool valid = c0 + (uint32_t)col < ncol;
+        const uint32_t e = valid ? c0 + (uint32_t)col : c0;
+        const uint32_t p = qu->colp[e];
+        const float u = qu->colu[e];
+        // lane l holds K half l/32 of its column, as in the scan's fragments
+        const half8_t bf = gb[(int64_t)(p >> 5) * 64 + h * 32 + (p & 31)];
+        float16_t acc[MB];
+#pragma unroll
+        for (int blk = 0; blk < MB; ++blk) {
+            float16_t z;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) z[i] = 0.0f;
+            acc[blk] = mma32(st.af[blk][0], bf, z);
+        }
+        bool pass[MB][2];
+#pragma unroll
+        for (int blk = 0; blk < MB; ++blk)
+#pragma unroll
+            for (int hl = 0; hl < 2; ++hl) {
+                const int r = 4 * blk + 2 * h + hl;
+                const float d = fmaf(-qu->T[r], u, max8(acc[blk], 8 * hl));
+                pass[blk][hl] = valid && d >= -slack && p >= qu->lo[r] && p < qu->hi[r];
+            }
+        qn = queue_cells32<B>(ta, qn, qu, grp, acc, pass, p, fitted);
+    }
+    if (st.flush_at && qn >= st.flush_at) {
+        flush32<B>(ta, qn, qu, grp);
+        fitted += qn;
+        qn = 0;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    st.qn = qn;
+    st.survivors += 8ull * fitted;   // wave-uniform
+    st.replayed += ncol;
+    st.cq = 0;
+    refresh32<B>(st, qu);
+}
+
 template <int B, bool MASK>
-__device__ __forceinline__ void screen32(const SearchArgs &a, const SearchArgs *ta,
-                                         Wave32<B> &st, Queue32<B> *qu,
+__device__ __forceinline__ void screen32(const SearchArgs *ta, Wave32<B> &st, Queue32<B> *qu,
                                          const float16_t (&acc)[Cfg<B>::MB], float u, int cb)
 {
     constexpr int MB = Cfg<B>::MB;
     const float slack = screen_slack<B>();
-    const int lane = threadIdx.x & 63, h = lane >> 5;
+    const int lane = threadIdx.x & 63;
     const uint32_t p = (uint32_t)cb * 32 + (lane & 31);
-    bool pass[MB][2];
     bool hit = false;
     float dmax = -__builtin_inff();
 #pragma unroll
@@ -1697,10 +1805,7 @@ __device__ __forceinline__ void screen32(const SearchArgs &a, const SearchArgs *
         for (int hl = 0; hl < 2; ++hl) {
             // max |C'''| - T u in one rounding (see the 16x16 screen)
             const float d = fmaf(-st.T[blk][hl], u, max8(acc[blk], 8 * hl));
-            bool ok = d >= -slack;
-            if (MASK) ok = ok && p >= st.lo[blk][hl] && p < st.hi[blk][hl];
-            pass[blk][hl] = ok;
-            if (MASK) hit = hit || ok;
+            if (MASK) hit = hit || (d >= -slack && p >= st.lo[blk][hl] && p < st.hi[blk][hl]);
             else dmax = fmaxf(dmax, d);
         }
     if (!MASK) hit = dmax >= -slack;
@@ -1712,39 +1817,18 @@ __device__ __forceinline__ void screen32(const SearchArgs &a, const SearchArgs *
         __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
         __builtin_amdgcn_sched_group_barrier(0x002, 40, 0);
     }
-    if (!wave_any(hit)) return;
-    // append the passing cells (at most 64 per row block half), each as one
-    // 32-byte record of its 8 cross terms (the flush applies the clamped- and
-    // quantised-contrast tests; here they did not remove enough cells to pay)
-    bool flushed = false;
-#pragma unroll
-    for (int blk = 0; blk < MB; ++blk)
-#pragma unroll
-        for (int hl = 0; hl < 2; ++hl) {
-            const u64 ball = __ballot(pass[blk][hl]);
-            if (ball == 0) continue;
-            const uint32_t cnt = (uint32_t)__popcll(ball);
-            if (st.qn + cnt > (uint32_t)kQueue) {
-                flush_queue32<B>(ta, st, qu);
-                flushed = true;
-            }
-            if (pass[blk][hl]) {
-                const uint32_t below = __builtin_amdgcn_mbcnt_hi(
-                    (uint32_t)(ball >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ball, 0u));
-                const uint32_t pos = st.qn + below;
-                const float16_t &av = acc[blk];
-                qu->c[pos][0] = float4_t{av[8 * hl + 0], av[8 * hl + 1], av[8 * hl + 2], av[8 * hl + 3]};
-                qu->c[pos][1] = float4_t{av[8 * hl + 4], av[8 * hl + 5], av[8 * hl + 6], av[8 * hl + 7]};
-                qu->p[pos] = p;
-                qu->ls[pos] = (uint32_t)(4 * blk + 2 * h + hl);
-            }
-            st.qn += cnt;
-        }
-    if (st.flush_at && st.qn >= st.flush_at) {
-        flush_queue32<B>(ta, st, qu);
-        flushed = true;
+    const u64 ball = __ballot(hit);
+    if (ball == 0) return;
+    // queue the column once (lanes l and l + 32 hold the same column); the
+    // scan replays the queue before it can hold more than kColQ - 32
+    const uint32_t cols = (uint32_t)ball | (uint32_t)(ball >> 32);
+    const uint32_t cnt = (uint32_t)__popc(cols);
+    if (lane < 32 && ((cols >> (lane & 31)) & 1u)) {
+        const uint32_t pos = st.cq + __builtin_amdgcn_mbcnt_lo(cols, 0u);
+        qu->colp[pos] = p;
+        qu->colu[pos] = u;
     }
-    if (flushed) refresh32<B>(st, qu);
+    st.cq += cnt;
 }
 
 // Column blocks [cb_begin, cb_end): the B fragments and u of the block PD
@@ -1811,13 +1895,14 @@ __device__ __forceinline__ void scan32(const SearchArgs &a, const SearchArgs *ta
         mmab(bq, acc);
         const float uc = uq;
         load(bq, uq, min(cb + i + PD, last));
-        screen32<B, MASK>(a, ta, st, qu, acc, uc, cb + i);
+        screen32<B, MASK>(ta, st, qu, acc, uc, cb + i);
     };
     auto tail = [&](const half8_t (&bq)[KS], float uq, int i) {
         float16_t acc[MB];
         mmab(bq, acc);
-        screen32<B, MASK>(a, ta, st, qu, acc, uq, cb + i);
+        screen32<B, MASK>(ta, st, qu, acc, uq, cb + i);
     };
+    static_assert(kColQ >= kColReplay + PD * 32, "a group of blocks fits the column queue");
     for (; cb + PD <= cb_end; cb += PD) {
         step(b0, u0, 0);
         step(b1, u1, 1);
@@ -1825,12 +1910,14 @@ __device__ __forceinline__ void scan32(const SearchArgs &a, const SearchArgs *ta
             step(b2, u2, 2);
             step(b3, u3, 3);
         }
+        if (st.cq >= (uint32_t)kColReplay) replay_queue32<B>(ta, st, qu);
     }
     if (cb + 0 < cb_end) tail(b0, u0, 0);
     if constexpr (PD == 4) {
         if (cb + 1 < cb_end) tail(b1, u1, 1);
         if (cb + 2 < cb_end) tail(b2, u2, 2);
     }
+    if (st.cq >= (uint32_t)kColReplay) replay_queue32<B>(ta, st, qu);
 }
 
 // One work item of the 32x32-tile search (4x4 ranges), as item16.
@@ -1848,14 +1935,17 @@ __device__ __forceinline__ void item32(const SearchArgs *ta, const SearchArgs &a
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) st.af[blk][ks] = ap[(blk * KS + ks) * 64];
     if (lane < GR) {
-        // the flush re-screens queued cells against these thresholds
+        // the replay and the flush screen against these thresholds and windows
         const int64_t slot = (int64_t)st.grp * GR + lane;
         const u64 bk = a.keys[slot];
-        const int64_t srr = a.rs[slot].srr;
+        const RangeStat rsx = a.rs[slot];
+        const bool act = !(rsx.flags & kIdle);
         qu->best[lane] = bk;
-        qu->srr[lane] = srr;
-        qu->delta[lane] = a.rs[slot].delta;
-        qu->T[lane] = bk == kNoKey ? 0.0f : screen_t(srr, (int64_t)(bk >> a.shift));
+        qu->srr[lane] = rsx.srr;
+        qu->delta[lane] = rsx.delta;
+        qu->T[lane] = bk == kNoKey ? 0.0f : screen_t(rsx.srr, (int64_t)(bk >> a.shift));
+        qu->lo[lane] = act ? rsx.lo : 0u;
+        qu->hi[lane] = act ? rsx.hi : 0u;
     }
 #pragma unroll
     for (int blk = 0; blk < MB; ++blk)
@@ -1882,6 +1972,7 @@ __device__ __forceinline__ void item32(const SearchArgs *ta, const SearchArgs &a
     scan32<B, true>(a, ta, st, qu, cb0, ib0);
     scan32<B, false>(a, ta, st, qu, ib0, ib1);
     scan32<B, true>(a, ta, st, qu, ib1, cb1);
+    if (st.cq) replay_queue32<B>(ta, st, qu);
     if (st.qn) flush_queue32<B>(ta, st, qu);
     if (lane < GR) {
         const u64 bk = qu->best[lane];
@@ -1903,7 +1994,9 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma32(const SearchArgs *__re
     Wave32<B> st;
     st.survivors = 0;
     st.screened = 0;
+    st.replayed = 0;
     st.qn = 0;
+    st.cq = 0;
     u64 items_done = 0;
     ItemQueue iq = item_queue(tab, n_img);
     for (;;) {
@@ -1916,6 +2009,7 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma32(const SearchArgs *__re
         items_done += 1;
     }
     add_counters(counters, st.screened, st.survivors, items_done);
+    if (counters && lane == 0) atomicAdd(&counters[7], st.replayed);
 }
 
 // 4x4 and 8x8 images of a batch in ONE persistent launch: the items of the
@@ -1965,10 +2059,13 @@ __global__ __launch_bounds__(256, 2) void k_search_mixed(const SearchArgs *__res
             const SearchArgs a = *ta;
             Wave32<4> s4;
             s4.qn = 0;
+            s4.cq = 0;
             s4.screened = 0;
             s4.survivors = 0;
+            s4.replayed = 0;
             item32<4>(ta, a, a.items[i4 - base4[ia]], s4, &qm[w].q4);
             add_counters(counters, s4.screened, s4.survivors, 1);
+            if (counters && lane == 0) atomicAdd(&counters[7], s4.replayed);
         }
     }
 }
