@@ -84,6 +84,8 @@ def parse():
                     help="encodes per candidate in the autotuner (best of)")
     ap.add_argument("--tune-file", default=None,
                     help="load these search parameters (fic_tune_load) instead of autotuning")
+    ap.add_argument("--tune-save", default=None,
+                    help="after autotuning, save the parameters (fic_tune_save) to this file")
     ap.add_argument("--separate-searches", action="store_true",
                     help="batch: one search launch per range size instead of the combined one")
     return ap.parse_args()
@@ -221,6 +223,8 @@ def run_autotune(args, fic, images, jobs):
     t0 = time.perf_counter()
     rep = fic.fic.autotune(images, jobs, reps=max(1, args.tune_reps))
     dt = time.perf_counter() - t0
+    if args.tune_save:
+        fic.fic.context(images[0].device.index).tune_save(args.tune_save)
     launch = [r for r in rep if r["range_size"] == 0]
     rep = [r for r in rep if r["range_size"] != 0]
     for r in rep:

@@ -408,8 +408,9 @@ fic_status fic_decode_quadtree(fic_ctx *ctx, const fic_code *codes1, const fic_g
  * launches won, base_ms the combined time and tuned_ms the kept one.
  *   ws  (dev) >= fic_autotune_workspace_bytes(n_images, descs) (the largest
  *       single-image batch workspace).
- * fic_tune_save / fic_tune_load: the context's rows as a JSON file (host
- * path) tagged with the device's gcnArchName and fic_kernel_hash(); load
+ * fic_tune_save / fic_tune_load: the context's rows and batch launch choice
+ * ("batch_separate": 0 or 1; optional on load, 0 when absent) as a JSON file
+ * (host path) tagged with the device's gcnArchName and fic_kernel_hash(); load
  * replaces the rows, answers FIC_ERR_UNSUPPORTED (rows unchanged) for a file
  * written for another architecture or other kernels, FIC_ERR_INVALID_ARG for
  * an unreadable or malformed one. fic_create loads the file named by the

@@ -988,8 +988,10 @@ fic_status fic_tune_save(fic_ctx *ctx, const char *path)
     if (!ctx || !path) return FIC_ERR_INVALID_ARG;
     std::string out = "{\n \"format\": \"fic-tune-1\",\n";
     char line[512];
-    snprintf(line, sizeof line, " \"arch\": \"%s\",\n \"kernel_hash\": \"%s\",\n \"rows\": [",
-             ctx->arch, FIC_KERNEL_HASH);
+    snprintf(line, sizeof line,
+             " \"arch\": \"%s\",\n \"kernel_hash\": \"%s\",\n \"batch_separate\": %d,\n"
+             " \"rows\": [",
+             ctx->arch, FIC_KERNEL_HASH, ctx->batch_separate ? 1 : 0);
     out += line;
     for (size_t i = 0; i < ctx->tune.size(); ++i) {
         const auto &t = ctx->tune[i];
@@ -1091,6 +1093,17 @@ fic_status fic_tune_load(fic_ctx *ctx, const char *path)
     const char *p = strstr(text.c_str(), "\"rows\"");
     const char *end = text.c_str() + text.size();
     if (!p) return FIC_ERR_INVALID_ARG;
+    // the batch launch structure: optional (0: one combined search); a
+    // top-level key (no row has one), so it may come anywhere
+    long sep = 0;
+    {
+        const char *sk = strstr(text.c_str(), "\"batch_separate\"");
+        if (sk) {
+            const char *q = sk;
+            if (!json_int(q, end, "batch_separate", sep) || (sep != 0 && sep != 1))
+                return FIC_ERR_INVALID_ARG;
+        }
+    }
     for (;;) {
         const char *q = strstr(p, "\"range_size\"");
         if (!q) break;
@@ -1126,6 +1139,7 @@ fic_status fic_tune_load(fic_ctx *ctx, const char *path)
     }
     ctx->tune.clear();
     for (const auto &t : rows) set_tune_row(ctx, t.b, t.dlog, t.row);
+    ctx->batch_separate = sep != 0;
     if (ctx->device >= 0 && enter(ctx) == FIC_OK) drop_graphs(ctx);
     return FIC_OK;
 }

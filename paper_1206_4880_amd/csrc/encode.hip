@@ -2551,18 +2551,41 @@ hipError_t run_encode_batch(const BatchJob *jobs, const BatchPlan &bp, void *ws,
     uint32_t *ctr = (uint32_t *)(w + bp.off_ctr);
     hipLaunchKernelGGL(k_fill_u32, dim3(3), dim3(64), 0, s, ctr, (int64_t)(3 * 64), 0u);
     hipError_t e = hipGetLastError();
-    // The images' preparations are independent small launches: spread them
-    // over the side streams, round robin in the table order.
+    // The images' preparations (and, after the search, their finalizations)
+    // are independent chains of small launches: spread them over the side
+    // streams, each image (largest first, by ranges + domains) onto the
+    // least loaded one, so that the streams end together.
     const int ns = bs ? bs->ns : 0;
-    if (ns > 0 && e == hipSuccess) {
-        e = hipEventRecord(bs->fork, s);
-        for (int q = 0; q < ns && e == hipSuccess; ++q) e = hipStreamWaitEvent(bs->side[q], bs->fork, 0);
+    std::vector<int> lane_of(bp.n, 0);
+    if (ns > 1) {
+        std::vector<int32_t> by(bp.n);
+        for (int32_t k = 0; k < bp.n; ++k) by[k] = k;
+        auto cost = [&](int32_t k) { return jobs[bp.order[k]].g.R + jobs[bp.order[k]].g.D; };
+        std::stable_sort(by.begin(), by.end(), [&](int32_t x, int32_t y) { return cost(x) > cost(y); });
+        std::vector<int64_t> load(ns, 0);
+        for (const int32_t k : by) {
+            const int q = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            lane_of[k] = q;
+            load[q] += cost(k);
+        }
     }
+    auto fork = [&]() {
+        hipError_t r = hipEventRecord(bs->fork, s);
+        for (int q = 0; q < ns && r == hipSuccess; ++q) r = hipStreamWaitEvent(bs->side[q], bs->fork, 0);
+        return r;
+    };
+    auto join = [&]() {
+        hipError_t r = hipSuccess;
+        for (int q = 0; q < ns && r == hipSuccess; ++q) r = hipEventRecord(bs->join[q], bs->side[q]);
+        for (int q = 0; q < ns && r == hipSuccess; ++q) r = hipStreamWaitEvent(s, bs->join[q], 0);
+        return r;
+    };
+    if (ns > 0 && e == hipSuccess) e = fork();
     // classify, pool and search preparation, image by image
     for (int32_t k = 0; k < bp.n && e == hipSuccess; ++k) {
         const int32_t i = bp.order[k];
         const BatchJob &j = jobs[i];
-        const hipStream_t ps = ns > 0 ? bs->side[k % ns] : s;
+        const hipStream_t ps = ns > 0 ? bs->side[lane_of[k]] : s;
         const BatchPart &pt = bp.part[i];
         const Geom &g = j.g;
         double *fdr = (double *)(w + pt.off_fdr);
@@ -2589,10 +2612,7 @@ hipError_t run_encode_batch(const BatchJob *jobs, const BatchPlan &bp, void *ws,
         default: e = batch_phase<16>(0, pt.plan, j.img, pp, pl, ph, ew, counters, tab + k, nullptr, ps, tr); break;
         }
     }
-    if (ns > 0) {
-        for (int q = 0; q < ns && e == hipSuccess; ++q) e = hipEventRecord(bs->join[q], bs->side[q]);
-        for (int q = 0; q < ns && e == hipSuccess; ++q) e = hipStreamWaitEvent(s, bs->join[q], 0);
-    }
+    if (ns > 0 && e == hipSuccess) e = join();
     // 4x4 and 8x8 images together: one persistent search over all their items
     const bool mixed = bp.group_count[0] > 0 && bp.group_count[1] > 0 && !(bp.dbg & kDbgSeparate);
     if (mixed && e == hipSuccess) {
@@ -2620,17 +2640,21 @@ hipError_t run_encode_batch(const BatchJob *jobs, const BatchPlan &bp, void *ws,
         default: e = search_b<16>(t, bp.group_count[gi], gb, gc, num_cu, counters, bp.dbg, s, tr); break;
         }
     }
+    // finalize, image by image, over the side streams again
+    if (ns > 0 && e == hipSuccess) e = fork();
     for (int32_t k = 0; k < bp.n && e == hipSuccess; ++k) {
         const int32_t i = bp.order[k];
         const BatchJob &j = jobs[i];
         const BatchPart &pt = bp.part[i];
+        const hipStream_t ps = ns > 0 ? bs->side[lane_of[k]] : s;
         void *ew = w + pt.off_enc;
         switch (j.g.b) {
-        case 4: e = batch_phase<4>(1, pt.plan, j.img, nullptr, nullptr, nullptr, ew, counters, nullptr, j.codes, s, tr); break;
-        case 8: e = batch_phase<8>(1, pt.plan, j.img, nullptr, nullptr, nullptr, ew, counters, nullptr, j.codes, s, tr); break;
-        default: e = batch_phase<16>(1, pt.plan, j.img, nullptr, nullptr, nullptr, ew, counters, nullptr, j.codes, s, tr); break;
+        case 4: e = batch_phase<4>(1, pt.plan, j.img, nullptr, nullptr, nullptr, ew, counters, nullptr, j.codes, ps, tr); break;
+        case 8: e = batch_phase<8>(1, pt.plan, j.img, nullptr, nullptr, nullptr, ew, counters, nullptr, j.codes, ps, tr); break;
+        default: e = batch_phase<16>(1, pt.plan, j.img, nullptr, nullptr, nullptr, ew, counters, nullptr, j.codes, ps, tr); break;
         }
     }
+    if (ns > 0 && e == hipSuccess) e = join();
     return e;
 }
 

@@ -282,12 +282,14 @@ def test_debug_switch_validation(L, hctx):
     assert L.fic_set_debug(hctx.handle, 0) == fic.OK
 
 
-def _tune_file(path, arch, khash, rows, xcd=None):
+def _tune_file(path, arch, khash, rows, xcd=None, batch_separate=None):
     import json
     doc = {"format": "fic-tune-1", "arch": arch, "kernel_hash": khash,
            "rows": [dict({"range_size": b, "dlog2": dl, "chunk_log2": cl, "flush_at": fl},
                          **({"xcd": xcd} if xcd is not None else {}))
                     for b, dl, cl, fl in rows]}
+    if batch_separate is not None:
+        doc["batch_separate"] = batch_separate
     with open(path, "w") as f:
         json.dump(doc, f)
 
@@ -351,11 +353,42 @@ def test_tune_cache_rejections(L, tmp_path):
         assert c.tune_load(p) == fic.ERR_INVALID_ARG              # range size
         _tune_file(p, "none", fic.kernel_hash(), [(8, 20, [12] * 6, [64] * 6)], xcd=[2] * 6)
         assert c.tune_load(p) == fic.ERR_INVALID_ARG              # xcd is 0 or 1
+        _tune_file(p, "none", fic.kernel_hash(), row, batch_separate=2)
+        assert c.tune_load(p) == fic.ERR_INVALID_ARG              # batch_separate is 0 or 1
         with open(p, "w") as f:
             f.write("not json")
         assert c.tune_load(p) == fic.ERR_INVALID_ARG
         assert c.tune_load(str(tmp_path / "missing.json")) == fic.ERR_INVALID_ARG
         assert c.tune_query(1024, 1024, 8, 1) == (14, 64)          # unchanged
+    finally:
+        c.close()
+
+
+def test_tune_cache_keeps_the_batch_launch_choice(L, tmp_path):
+    """The batch launch structure (one combined search or one per range
+    size) is saved with the rows and restored by a load; absent means
+    combined."""
+    import json
+    c = fic.Context(-1)
+    try:
+        p, q = str(tmp_path / "in.json"), str(tmp_path / "out.json")
+        row = [(8, 20, [12] * 6, [64] * 6)]
+        c.tune_save(q)
+        assert json.load(open(q))["batch_separate"] == 0          # default
+        _tune_file(p, "none", fic.kernel_hash(), row, batch_separate=1)
+        assert c.tune_load(p) == fic.OK
+        c.tune_save(q)
+        doc = json.load(open(q))
+        assert doc["batch_separate"] == 1 and doc["rows"][0]["chunk_log2"] == [12] * 6
+        _tune_file(p, "none", fic.kernel_hash(), row)               # absent: combined
+        assert c.tune_load(p) == fic.OK
+        c.tune_save(q)
+        assert json.load(open(q))["batch_separate"] == 0
+        _tune_file(p, "none", fic.kernel_hash(), row, batch_separate=1)
+        assert c.tune_load(p) == fic.OK
+        c.tune_reset()
+        c.tune_save(q)
+        assert json.load(open(q))["batch_separate"] == 0
     finally:
         c.close()
 
