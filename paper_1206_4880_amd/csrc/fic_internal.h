@@ -290,7 +290,7 @@ hipError_t launch_fd_classify(const uint8_t *img, int32_t h, int32_t w, int32_t 
 // radix sort + pool (pool.hip)
 size_t sort_ws_bytes(int64_t n);
 hipError_t radix_sort_pairs(u64 *keys, uint32_t *vals, int64_t n, int key_bits, void *ws,
-                            hipStream_t s);
+                            hipStream_t s, double *fd_out = nullptr);
 size_t scan_ws_bytes(int64_t m);
 hipError_t scan_u32(uint32_t *a, int64_t m, uint32_t *total, void *ws, hipStream_t s);
 size_t pool_ws_bytes(int64_t nr, int64_t nd);

@@ -110,20 +110,32 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_add(uint32_t *__restrict_
         if (base + i < m) a[base + i] += off;
 }
 
+// Order-preserving integer image of an fp64 value, and its inverse.
+__device__ inline u64 fd_bits(double x)
+{
+    u64 b = (u64)__double_as_longlong(x);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+__device__ inline double fd_of_bits(u64 k)
+{
+    const u64 b = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
+    return __longlong_as_double((long long)b);
+}
+
 // Control words of one multi-block sort (in its workspace): cur[p] is where
 // the data is before pass p (0: the caller's arrays, 1: the alternate
-// ones); cur[0] = 0, and each pass's scatter writes the next entry.
+// ones). Pass 0 starts in the caller's arrays without reading cur[0]; each
+// pass's scatter writes the next entry before a later kernel reads it.
 constexpr int kMaxPasses = 8;
 struct SortCtl {
     uint32_t cur[kMaxPasses + 1];
 };
 
-__global__ void k_sort_init(SortCtl *ctl)
-{
-    uint32_t *w = (uint32_t *)ctl;
-    const int i = threadIdx.x;
-    if (i < (int)(sizeof(SortCtl) / 4)) w[i] = 0u;
-}
+// Up to this many tiles, each scatter workgroup sums its digit offsets from
+// the tile counts itself (at most 64 x 256 counts per workgroup), so a pass
+// takes two launches instead of three.
+constexpr int kFusedScanTiles = 64;
 
 // Exclusive scan over the 1024 threads of a block (16 waves); *total gets
 // the sum. All threads must call it.
@@ -160,7 +172,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const u64 *__restric
 {
     __shared__ uint32_t h[256];
     const int tid = threadIdx.x;
-    const u64 *keys = ctl->cur[pass] ? kb : ka;     // written by the previous pass's scatter
+    const u64 *keys = (pass && ctl->cur[pass]) ? kb : ka;   // written by the previous pass's scatter
     if (tid < 256) h[tid] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
@@ -197,13 +209,14 @@ __global__ __launch_bounds__(256) void k_sort_scan(uint32_t *__restrict__ cnt, i
 // Step 3: stable scatter of each tile by the digit: equal digits are ranked
 // by position with wave ballots, waves in order, rounds in order. A tile's
 // start position of digit d is (keys of smaller digits) + (keys of digit d in
-// earlier tiles). A pass in which one digit holds all n keys would not change
-// the order and is skipped; block 0 records where the data is for the next
-// pass.
+// earlier tiles): from the scan (offs, tot) or, with fused (nb <=
+// kFusedScanTiles), summed here from the raw tile counts. A pass in which
+// one digit holds all n keys would not change the order and is skipped;
+// block 0 records where the data is for the next pass.
 __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
     u64 *__restrict__ ka, uint32_t *__restrict__ va, u64 *__restrict__ kb,
     uint32_t *__restrict__ vb, int64_t n, int shift, int pass, const uint32_t *__restrict__ offs,
-    const uint32_t *__restrict__ tot, int nb, SortCtl *ctl)
+    const uint32_t *__restrict__ tot, int nb, int fused, SortCtl *ctl)
 {
     __shared__ uint32_t run[256];
     __shared__ uint32_t wc[kSortWaves][256];
@@ -213,11 +226,24 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
     if (tid == 0) skip = 0;
     for (int i = tid; i < kSortWaves * 256; i += kSortThreads) (&wc[0][0])[i] = 0u;
     __syncthreads();
-    const uint32_t t = tid < 256 ? tot[tid] : 0u;
+    uint32_t t = 0, before = 0;
+    if (tid < 256) {
+        const uint32_t *row = offs + (int64_t)tid * padded_tiles(nb);
+        if (fused) {
+            for (int b = 0; b < nb; ++b) {
+                const uint32_t c = row[b];
+                before += b < (int)blockIdx.x ? c : 0u;
+                t += c;
+            }
+        } else {
+            t = tot[tid];
+            before = row[blockIdx.x];
+        }
+    }
     if (tid < 256 && (int64_t)t == n) skip = 1;
     uint32_t all;
     const uint32_t dbase = block_scan_1024(t, wsum, all);     // digits >= 256 add 0
-    const uint32_t cur = ctl->cur[pass];
+    const uint32_t cur = pass ? ctl->cur[pass] : 0u;
     const bool skipped = skip != 0;
     if (blockIdx.x == 0 && tid == 0) ctl->cur[pass + 1] = skipped ? cur : (cur ^ 1u);
     if (skipped) return;                            // block-uniform
@@ -225,7 +251,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
     const uint32_t *vin = cur ? vb : va;
     u64 *kout = cur ? ka : kb;
     uint32_t *vout = cur ? va : vb;
-    if (tid < 256) run[tid] = dbase + offs[(int64_t)tid * padded_tiles(nb) + blockIdx.x];
+    if (tid < 256) run[tid] = dbase + before;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
     const u64 lt = (1ull << lane) - 1ull;
@@ -264,16 +290,22 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
 }
 
 // The sorted data back into the caller's arrays when it ended in the
-// alternate ones.
+// alternate ones; with fd_out (nullable), the sorted keys read as fd_bits
+// images are decoded into it (the sorted fp64 values).
 __global__ void k_sort_finish(u64 *__restrict__ ka, uint32_t *__restrict__ va,
                               const u64 *__restrict__ kb, const uint32_t *__restrict__ vb,
-                              int64_t n, int passes, const SortCtl *ctl)
+                              int64_t n, int passes, const SortCtl *ctl, double *__restrict__ fd_out)
 {
-    if (ctl->cur[passes] == 0u) return;
+    const bool moved = ctl->cur[passes] != 0u;
+    if (!moved && !fd_out) return;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    ka[i] = kb[i];
-    va[i] = vb[i];
+    const u64 k = moved ? kb[i] : ka[i];
+    if (moved) {
+        ka[i] = k;
+        va[i] = vb[i];
+    }
+    if (fd_out) fd_out[i] = fd_of_bits(k);
 }
 
 // Up to kSmallSort pairs: the whole sort in one workgroup, in LDS. Per pass
@@ -285,7 +317,7 @@ constexpr int kSmallSort = 4096;
 
 __global__ __launch_bounds__(kSmallThreads) void k_sort_small(u64 *__restrict__ keys,
                                                               uint32_t *__restrict__ vals, int n,
-                                                              int passes)
+                                                              int passes, double *__restrict__ fd_out)
 {
     __shared__ u64 sk[2][kSmallSort];
     __shared__ uint32_t sv[2][kSmallSort];
@@ -364,14 +396,8 @@ __global__ __launch_bounds__(kSmallThreads) void k_sort_small(u64 *__restrict__ 
     for (int i = tid; i < n; i += kSmallThreads) {
         keys[i] = sk[cur][i];
         vals[i] = sv[cur][i];
+        if (fd_out) fd_out[i] = fd_of_bits(sk[cur][i]);
     }
-}
-
-// Order-preserving integer image of an fp64 value.
-__device__ inline u64 fd_bits(double x)
-{
-    u64 b = (u64)__double_as_longlong(x);
-    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
 }
 
 __global__ void k_fd_keys(const double *__restrict__ fd, int64_t n, u64 *__restrict__ keys,
@@ -384,47 +410,18 @@ __global__ void k_fd_keys(const double *__restrict__ fd, int64_t n, u64 *__restr
     }
 }
 
-// Window half-width: tol, or (max - min)/3 over the domain dimensions.
-__global__ __launch_bounds__(1024) void k_resolve_tol(const double *__restrict__ fd, int64_t n,
-                                                       double tol, double *__restrict__ out)
-{
-    __shared__ double smax[1024], smin[1024];
-    double mx = -INFINITY, mn = INFINITY;
-    if (tol < 0.0)
-        for (int64_t i = threadIdx.x; i < n; i += 1024) {
-            mx = fmax(mx, fd[i]);
-            mn = fmin(mn, fd[i]);
-        }
-    smax[threadIdx.x] = mx;
-    smin[threadIdx.x] = mn;
-    __syncthreads();
-    for (int off = 512; off > 0; off >>= 1) {
-        if (threadIdx.x < off) {
-            smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + off]);
-            smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + off]);
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[0] = tol < 0.0 ? (smax[0] - smin[0]) / 3.0 : tol;
-}
-
-__global__ void k_sorted_fd(const double *__restrict__ fd, const uint32_t *__restrict__ perm,
-                            int64_t n, double *__restrict__ out)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = fd[perm[i]];
-}
-
 // Per range: [lo, hi) = positions p with -T <= fd_sorted[p] - fd_r <= T,
 // T = tol + 1e-9, both bounds by binary search on the monotone difference.
+// A negative tol asks for (max - min)/3 over the domain dimensions: the ends
+// of the sorted array.
 __global__ void k_bounds(const double *__restrict__ fdr, int32_t nr,
-                         const double *__restrict__ fds, int32_t nd,
-                         const double *__restrict__ tol_eff, uint32_t *__restrict__ lo,
-                         uint32_t *__restrict__ hi)
+                         const double *__restrict__ fds, int32_t nd, double tol,
+                         uint32_t *__restrict__ lo, uint32_t *__restrict__ hi)
 {
     int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nr) return;
-    const double T = tol_eff[0] + 1e-9;
+    const double te = tol >= 0.0 ? tol : (nd > 0 ? (fds[nd - 1] - fds[0]) / 3.0 : 0.0);
+    const double T = te + 1e-9;
     const double x = fdr[r];
     int a = 0, b = nd;                       // first p with fds[p] - x >= -T
     while (a < b) {
@@ -474,21 +471,22 @@ hipError_t scan_u32(uint32_t *a, int64_t m, uint32_t *total, void *ws, hipStream
 
 // Stable sort of n (key, value) pairs by the low key_bits bits of the keys
 // (LSD, 8-bit digits). Up to kSmallSort pairs: one launch (k_sort_small).
-// Otherwise three launches per digit (tile histograms, per-digit scans of
-// the tile counts, stable scatter), one to clear the control words and one
-// to copy the
-// result back when it ended in the alternate arrays; passes in which every
-// key has the same digit are skipped on the device. No workgroup waits on
-// another: every hand-over is a kernel boundary.
+// Otherwise per digit the tile histograms and the stable scatter, with a
+// scan of the tile counts between them above kFusedScanTiles tiles, and a
+// last launch that copies the result back when it ended in the alternate
+// arrays; passes in which every key has the same digit are skipped on the
+// device. No workgroup waits on another: every hand-over is a kernel
+// boundary. With fd_out (nullable) the keys are fd_bits images and their
+// sorted fp64 values are also written there.
 hipError_t radix_sort_pairs(u64 *keys, uint32_t *vals, int64_t n, int key_bits, void *ws,
-                            hipStream_t s)
+                            hipStream_t s, double *fd_out)
 {
-    if (n <= 1) return hipSuccess;
+    if (n <= 0 || (n == 1 && !fd_out)) return hipSuccess;
     const int passes = (key_bits + 7) / 8;
     if (passes > kMaxPasses) return hipErrorInvalidValue;
     if (n <= kSmallSort) {
         hipLaunchKernelGGL(k_sort_small, dim3(1), dim3(kSmallThreads), 0, s, keys, vals, (int)n,
-                           passes);
+                           passes, fd_out);
         return hipGetLastError();
     }
     const int nb = (int)((n + kSortTile - 1) / kSortTile);
@@ -499,28 +497,29 @@ hipError_t radix_sort_pairs(u64 *keys, uint32_t *vals, int64_t n, int key_bits, 
     const size_t cstride = (align256(nbp * 256 * 4) + 1024) / 4;   // counts, then 256 totals
     uint32_t *cnt = (uint32_t *)p;        p += (size_t)kMaxPasses * cstride * 4;
     SortCtl *ctl = (SortCtl *)p;
-    hipLaunchKernelGGL(k_sort_init, dim3(1), dim3(64), 0, s, ctl);
+    const int fused = nb <= kFusedScanTiles ? 1 : 0;
     for (int pass = 0; pass < passes; ++pass) {
         uint32_t *c = cnt + (size_t)pass * cstride;
         uint32_t *tot = c + align256(nbp * 256 * 4) / 4;
         hipLaunchKernelGGL(k_sort_hist, dim3(nb), dim3(kSortThreads), 0, s, (const u64 *)keys,
                            (const u64 *)kalt, n, pass * 8, pass, c, nb, (const SortCtl *)ctl);
-        hipLaunchKernelGGL(k_sort_scan, dim3(256), dim3(256), 0, s, c, nb, tot);
+        if (!fused) hipLaunchKernelGGL(k_sort_scan, dim3(256), dim3(256), 0, s, c, nb, tot);
         hipLaunchKernelGGL(k_sort_scatter, dim3(nb), dim3(kSortThreads), 0, s, keys, vals, kalt,
                            valt, n, pass * 8, pass, (const uint32_t *)c, (const uint32_t *)tot, nb,
-                           ctl);
+                           fused, ctl);
     }
     hipLaunchKernelGGL(k_sort_finish, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, keys, vals,
-                       (const u64 *)kalt, (const uint32_t *)valt, n, passes, (const SortCtl *)ctl);
+                       (const u64 *)kalt, (const uint32_t *)valt, n, passes, (const SortCtl *)ctl,
+                       fd_out);
     return hipGetLastError();
 }
 
-// Pool workspace: sort keys (n_domain u64), sorted fd (n_domain f64),
-// tol (f64), sort scratch.
+// Pool workspace: sort keys (n_domain u64), sorted fd (n_domain f64), sort
+// scratch.
 size_t pool_ws_bytes(int64_t nr, int64_t nd)
 {
     (void)nr;
-    return align256((size_t)nd * 8) * 2 + 256 + sort_ws_bytes(nd);
+    return align256((size_t)nd * 8) * 2 + sort_ws_bytes(nd);
 }
 
 hipError_t launch_pool(const double *fd_range, int32_t nr, const double *fd_dom, int32_t nd,
@@ -531,18 +530,15 @@ hipError_t launch_pool(const double *fd_range, int32_t nr, const double *fd_dom,
     char *p = (char *)ws;
     u64 *keys = (u64 *)p;          p += align256((size_t)nd * 8);
     double *fds = (double *)p;     p += align256((size_t)nd * 8);
-    double *tol_eff = (double *)p; p += 256;
     void *sortws = p;
     const int th = 256;
     hipLaunchKernelGGL(k_fd_keys, dim3((nd + th - 1) / th), dim3(th), 0, s, fd_dom, (int64_t)nd,
                        keys, perm);
-    hipError_t e = radix_sort_pairs(keys, perm, nd, 64, sortws, s);
+    // the sort also writes the sorted fd values (decoded from its keys)
+    hipError_t e = radix_sort_pairs(keys, perm, nd, 64, sortws, s, fds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_resolve_tol, dim3(1), dim3(1024), 0, s, fd_dom, (int64_t)nd, tol, tol_eff);
-    hipLaunchKernelGGL(k_sorted_fd, dim3((nd + th - 1) / th), dim3(th), 0, s, fd_dom, perm,
-                       (int64_t)nd, fds);
     hipLaunchKernelGGL(k_bounds, dim3((nr + th - 1) / th), dim3(th), 0, s, fd_range, nr, fds, nd,
-                       tol_eff, lo, hi);
+                       tol, lo, hi);
     trace(tr, FIC_STAGE_POOL, 0, s);
     return hipGetLastError();
 }
