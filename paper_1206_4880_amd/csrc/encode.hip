@@ -713,6 +713,15 @@ template <int B> struct WaveState {
 // into the LDS best keys, write the thresholds to LDS. The column loads of
 // all rounds are issued before the first fit, so their latency is paid once
 // per flush; the range constants come from LDS.
+// The current global key of range `lane` of group grp: an atomic load at
+// device scope (never an older copy from this XCD's L2). Any value it
+// returns is a key some wave reached, so taking it is always valid.
+__device__ __forceinline__ u64 group_key(u64 *keys, uint32_t grp, int gr, int lane)
+{
+    return __hip_atomic_load(&keys[(int64_t)grp * gr + lane], __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <int B>
 __device__ __noinline__ void flush16(const SearchArgs *ta, uint32_t nq, Queue16<B> *qu,
                                      uint32_t grp)
@@ -747,6 +756,9 @@ __device__ __noinline__ void flush16(const SearchArgs *ta, uint32_t nq, Queue16<
             dm[r] = gdom[pe[r]];
             uu[r] = gu[pe[r]];
         }
+    // what other waves on the same ranges (other column chunks) have found,
+    // read with the column loads (one memory round trip per flush)
+    const u64 gk = lane < GR ? group_key(a.keys, grp, GR, lane) : kNoKey;
 #pragma unroll
     for (int r = 0; r < RQ; ++r) {
         const uint32_t e = (uint32_t)(r * 64 + lane);
@@ -790,11 +802,11 @@ __device__ __noinline__ void flush16(const SearchArgs *ta, uint32_t nq, Queue16<
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     if (lane < GR) {
-        // publish the wave's best keys and take what other waves on the same
-        // ranges (other column chunks) have found
+        // take the other waves' keys read above and publish the wave's best
+        // (no wait for the atomic's reply)
         u64 bk = qu->best[lane];
-        const u64 g = atomicMin(&a.keys[(int64_t)grp * GR + lane], bk);
-        bk = g < bk ? g : bk;
+        bk = gk < bk ? gk : bk;
+        atomicMin(&a.keys[(int64_t)grp * GR + lane], bk);
         qu->best[lane] = bk;
         qu->T[lane] = bk == kNoKey ? 0.0f : screen_t_b<B>(qu->srr[lane], (int64_t)(bk >> a.shift));
     }
@@ -1238,6 +1250,27 @@ __device__ __forceinline__ bool claim_item(uint32_t *ctr, const SearchArgs *tab,
     return false;
 }
 
+// Claiming ahead: claim_issue sends the plain queue's atomic for the next
+// item (lane 0's reply, not yet read), claim_take reads it when that item
+// is due, so the atomic's round trip overlaps the current item. With the
+// per-XCD queues claim_take claims then (claim_item).
+__device__ __forceinline__ uint32_t claim_issue(uint32_t *ctr, const ItemQueue &iq)
+{
+    uint32_t r = 0;
+    if (!iq.xq && (threadIdx.x & 63) == 0) r = atomicAdd(ctr, 1u);
+    return r;
+}
+__device__ __forceinline__ bool claim_take(uint32_t raw, uint32_t *ctr, const SearchArgs *tab,
+                                           uint32_t nitems, uint32_t dbg, ItemQueue &iq,
+                                           uint32_t &item)
+{
+    if (iq.xq) return claim_item(ctr, tab, nitems, dbg, iq, item);
+    const uint32_t i = __builtin_amdgcn_readfirstlane(raw);
+    if (i >= nitems) return false;
+    item = (dbg & kDbgReverse) ? nitems - 1u - i : i;   // order-independence check
+    return true;
+}
+
 // The image of global item `item` among n_img table entries with item bases
 // base[] (last entry whose base <= item), wave-uniform.
 __device__ __forceinline__ int image_of_item(const uint32_t *__restrict__ base, int32_t n_img,
@@ -1343,9 +1376,11 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma(const SearchArgs *__rest
     st.qn = 0;
     u64 items_done = 0;
     ItemQueue iq = item_queue(tab, n_img);
+    uint32_t raw = claim_issue(item_ctr, iq);
     for (;;) {
         uint32_t item;
-        if (!claim_item(item_ctr, tab, nitems, dbg, iq, item)) break;
+        if (!claim_take(raw, item_ctr, tab, nitems, dbg, iq, item)) break;
+        raw = claim_issue(item_ctr, iq);            // the next item, in flight meanwhile
         const int ia = image_of_item(base, n_img, item);
         const SearchArgs *ta = tab + ia;
         const SearchArgs a = *ta;
@@ -1549,6 +1584,7 @@ template <int B> struct Queue32 {
     uint32_t ls[kQueue];             // range within the wave's group
     uint32_t colp[kColQ];            // queued columns
     float colu[kColQ];               // their u
+    half8_t colb[kColQ][2];          // their B fragments (K halves 0, 1), gathered by the replay
     uint32_t lo[Cfg<B>::GR];         // pool windows of the wave's ranges (empty if idle)
     uint32_t hi[Cfg<B>::GR];
     u64 best[Cfg<B>::GR];            // best keys of the wave's ranges
@@ -1612,6 +1648,8 @@ __device__ __noinline__ void flush32(const SearchArgs *ta, uint32_t nq, Queue32<
             dm[r] = gdom[pe[r]];
             uu[r] = gu[pe[r]];
         }
+    // other waves' keys for the group, read with the column loads (as flush16)
+    const u64 gk = lane < GR ? group_key(a.keys, grp, GR, lane) : kNoKey;
 #pragma unroll
     for (int r = 0; r < RQ; ++r) {
         const uint32_t e = (uint32_t)(r * 64 + lane);
@@ -1658,10 +1696,10 @@ __device__ __noinline__ void flush32(const SearchArgs *ta, uint32_t nq, Queue32<
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     if (lane < GR) {
-        // publish the wave's best keys and take what other waves found
+        // take the other waves' keys read above, publish the wave's best
         u64 bk = qu->best[lane];
-        const u64 g = atomicMin(&a.keys[(int64_t)grp * GR + lane], bk);
-        bk = g < bk ? g : bk;
+        bk = gk < bk ? gk : bk;
+        atomicMin(&a.keys[(int64_t)grp * GR + lane], bk);
         qu->best[lane] = bk;
         qu->T[lane] = bk == kNoKey ? 0.0f : screen_t(qu->srr[lane], (int64_t)(bk >> a.shift));
     }
@@ -1732,7 +1770,9 @@ __device__ __forceinline__ uint32_t queue_cells32(const SearchArgs *ta, uint32_t
 }
 
 // Replay and empty the column queue, 32 columns per tile: gather their B
-// fragments, redo the MFMAs against the wave's A fragments (the same exact
+// fragments (all tiles' loads in flight at once, staged through LDS, so
+// their latency is paid once per replay), redo the MFMAs against the
+// wave's A fragments (the same exact
 // cross terms as in the scan) and screen every cell again, against its
 // range's current threshold (never looser than when the column was queued)
 // and pool window. The passing cells go to the cell queue, which is fitted
@@ -1749,14 +1789,29 @@ __device__ __forceinline__ void replay_queue32(const SearchArgs *ta, Wave32<B> &
     const half8_t *gb = (const half8_t *)uniform_ptr(ta->Bm);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     const uint32_t ncol = st.cq, grp = st.grp;
+    constexpr int kTiles = kColQ / 32;
+    {
+        // lane l fetches K half l/32 of its column, as in the scan's fragments
+        half8_t g[kTiles];
+#pragma unroll
+        for (int t = 0; t < kTiles; ++t)
+            if ((uint32_t)(32 * t) < ncol) {
+                const uint32_t e = min((uint32_t)(32 * t + col), ncol - 1u);
+                const uint32_t p = qu->colp[e];
+                g[t] = gb[(int64_t)(p >> 5) * 64 + h * 32 + (p & 31)];
+            }
+#pragma unroll
+        for (int t = 0; t < kTiles; ++t)
+            if ((uint32_t)(32 * t) < ncol) qu->colb[min((uint32_t)(32 * t + col), ncol - 1u)][h] = g[t];
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
     uint32_t qn = st.qn, fitted = 0;
     for (uint32_t c0 = 0; c0 < ncol; c0 += 32) {
         const bool valid = c0 + (uint32_t)col < ncol;
         const uint32_t e = valid ? c0 + (uint32_t)col : c0;
         const uint32_t p = qu->colp[e];
         const float u = qu->colu[e];
-        // lane l holds K half l/32 of its column, as in the scan's fragments
-        const half8_t bf = gb[(int64_t)(p >> 5) * 64 + h * 32 + (p & 31)];
+        const half8_t bf = qu->colb[e][h];
         float16_t acc[MB];
 #pragma unroll
         for (int blk = 0; blk < MB; ++blk) {
@@ -1765,14 +1820,26 @@ __device__ __forceinline__ void replay_queue32(const SearchArgs *ta, Wave32<B> &
             for (int i = 0; i < 16; ++i) z[i] = 0.0f;
             acc[blk] = mma32(st.af[blk][0], bf, z);
         }
-        bool pass[MB][2];
+        // every cell's threshold and window read up front and the tests
+        // combined without short-circuits (no LDS round trip per branch)
+        float tr[MB][2];
+        uint32_t lr[MB][2], hr[MB][2];
 #pragma unroll
         for (int blk = 0; blk < MB; ++blk)
 #pragma unroll
             for (int hl = 0; hl < 2; ++hl) {
                 const int r = 4 * blk + 2 * h + hl;
-                const float d = fmaf(-qu->T[r], u, max8(acc[blk], 8 * hl));
-                pass[blk][hl] = valid && d >= -slack && p >= qu->lo[r] && p < qu->hi[r];
+                tr[blk][hl] = qu->T[r];
+                lr[blk][hl] = qu->lo[r];
+                hr[blk][hl] = qu->hi[r];
+            }
+        bool pass[MB][2];
+#pragma unroll
+        for (int blk = 0; blk < MB; ++blk)
+#pragma unroll
+            for (int hl = 0; hl < 2; ++hl) {
+                const float d = fmaf(-tr[blk][hl], u, max8(acc[blk], 8 * hl));
+                pass[blk][hl] = valid & (d >= -slack) & (p >= lr[blk][hl]) & (p < hr[blk][hl]);
             }
         qn = queue_cells32<B>(ta, qn, qu, grp, acc, pass, p, fitted);
     }
@@ -1999,9 +2066,11 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma32(const SearchArgs *__re
     st.cq = 0;
     u64 items_done = 0;
     ItemQueue iq = item_queue(tab, n_img);
+    uint32_t raw = claim_issue(item_ctr, iq);
     for (;;) {
         uint32_t item;
-        if (!claim_item(item_ctr, tab, nitems, dbg, iq, item)) break;
+        if (!claim_take(raw, item_ctr, tab, nitems, dbg, iq, item)) break;
+        raw = claim_issue(item_ctr, iq);            // the next item, in flight meanwhile
         const int ia = image_of_item(base, n_img, item);
         const SearchArgs *ta = tab + ia;
         const SearchArgs a = *ta;
@@ -2034,11 +2103,12 @@ __global__ __launch_bounds__(256, 2) void k_search_mixed(const SearchArgs *__res
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint32_t ni8 = base8[n8];
     const uint32_t nitems = ni8 + base4[n4];
+    // the next item is claimed while this one runs (see claim_issue)
+    uint32_t raw = lane == 0 ? atomicAdd(item_ctr, 1u) : 0u;
     for (;;) {
-        uint32_t item = 0;
-        if (lane == 0) item = atomicAdd(item_ctr, 1u);
-        item = __builtin_amdgcn_readfirstlane(item);
+        uint32_t item = __builtin_amdgcn_readfirstlane(raw);
         if (item >= nitems) break;
+        raw = lane == 0 ? atomicAdd(item_ctr, 1u) : 0u;
         if (dbg & kDbgReverse) item = nitems - 1u - item;   // order-independence check
         // per item: the queue is empty between items, and the counters are
         // added per item (nothing but the loop is carried across items)
