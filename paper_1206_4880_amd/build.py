@@ -24,8 +24,11 @@ FLAGS = [
 
 
 # The search screen never sees a NaN (padding columns carry a finite u and
-# are masked), so its |x| maxima need no NaN canonicalisation.
-PER_FILE = {"encode.hip": ["-fno-honor-nans"]}
+# are masked), so its |x| maxima need no NaN canonicalisation. Without the
+# atomic optimizer, a work-queue claim made by lane 0 stays one atomic whose
+# reply is read only when the next item starts (the optimizer would rewrite
+# it into a wave-wide atomic that waits for its reply at once).
+PER_FILE = {"encode.hip": ["-fno-honor-nans", "-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]}
 
 
 def _hipcc():
@@ -40,10 +43,12 @@ def sources():
 
 
 def kernel_hash():
-    """First 16 hex digits of SHA-256 over the library's sources (every
-    csrc/*.hip and *.h, then include/fic.h): the tag of autotuning caches."""
+    """First 16 hex digits of SHA-256 over the build flags and the library's
+    sources (every csrc/*.hip and *.h, then include/fic.h): the tag of
+    autotuning caches."""
     import hashlib
     h = hashlib.sha256()
+    h.update(repr((FLAGS, sorted(PER_FILE.items()))).encode())   # the build flags too
     files = sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".h")))
     for f in files + ["../../include/fic.h"]:
         with open(os.path.join(CSRC, f), "rb") as fh:

@@ -1252,13 +1252,16 @@ __device__ __forceinline__ bool claim_item(uint32_t *ctr, const SearchArgs *tab,
 
 // Claiming ahead: claim_issue sends the plain queue's atomic for the next
 // item (lane 0's reply, not yet read), claim_take reads it when that item
-// is due, so the atomic's round trip overlaps the current item. With the
-// per-XCD queues claim_take claims then (claim_item).
-__device__ __forceinline__ uint32_t claim_issue(uint32_t *ctr, const ItemQueue &iq)
+// is due, so the atomic's round trip overlaps the current item's end (its
+// last flush and key publication). With the per-XCD queues claim_take
+// claims then (claim_item). (The file is built without the compiler's
+// atomic optimizer, which would turn the lane-0 atomic into a wave-wide one
+// that reads its reply at once.)
+__device__ __forceinline__ void claim_issue(uint32_t *ctr, const ItemQueue &iq, uint32_t &raw)
 {
-    uint32_t r = 0;
-    if (!iq.xq && (threadIdx.x & 63) == 0) r = atomicAdd(ctr, 1u);
-    return r;
+    // only lane 0's value is read; the other lanes keep theirs, so the reply
+    // needs no merge (a merge would wait for it right here)
+    if (!iq.xq && (threadIdx.x & 63) == 0) raw = atomicAdd(ctr, 1u);
 }
 __device__ __forceinline__ bool claim_take(uint32_t raw, uint32_t *ctr, const SearchArgs *tab,
                                            uint32_t nitems, uint32_t dbg, ItemQueue &iq,
@@ -1273,24 +1276,41 @@ __device__ __forceinline__ bool claim_take(uint32_t raw, uint32_t *ctr, const Se
 
 // The image of global item `item` among n_img table entries with item bases
 // base[] (last entry whose base <= item), wave-uniform.
+// The bases are read through the constant address space: wave-uniform
+// scalar loads that hit the scalar cache (every wave reads the same few
+// words), not one vector-memory round trip per bisection step.
+typedef __attribute__((address_space(4))) const uint32_t cu32;
 __device__ __forceinline__ int image_of_item(const uint32_t *__restrict__ base, int32_t n_img,
                                              uint32_t item)
 {
+    cu32 *cb = (cu32 *)base;
     int ia = 0, ib = n_img;
     while (ib - ia > 1) {
-        const int m = (ia + ib) >> 1;
-        if (base[m] <= item) ia = m; else ib = m;
+        const int m = __builtin_amdgcn_readfirstlane((ia + ib) >> 1);
+        if (cb[m] <= item) ia = m; else ib = m;
     }
     return __builtin_amdgcn_readfirstlane(ia);
+}
+
+// Item index `item` of image ia relative to its base (a scalar load, as above).
+__device__ __forceinline__ uint32_t item_in_image(const uint32_t *__restrict__ base, int ia,
+                                                  uint32_t item)
+{
+    return item - ((cu32 *)base)[ia];
 }
 
 // One work item (a group of 2*MB ranges against a run of column blocks) of
 // the 16x16-tile search: load the group's A rows and thresholds, scan the
 // blocks (masked where some range's pool ends inside them), flush, publish
 // the keys.
-template <int B>
+struct NoHook {
+    __device__ void operator()() const {}
+};
+
+template <int B, class Hook = NoHook>
 __device__ __forceinline__ void item16(const SearchArgs *ta, const SearchArgs &a,
-                                       const WorkItem &wi, WaveState<B> &st, Queue16<B> *qu)
+                                       const WorkItem &wi, WaveState<B> &st, Queue16<B> *qu,
+                                       const Hook &before_end = Hook())
 {
     using C = Cfg<B>;
     constexpr int MW = C::MB, KS = C::KS, GR = C::GR;
@@ -1335,6 +1355,7 @@ __device__ __forceinline__ void item16(const SearchArgs *ta, const SearchArgs &a
     scan_blocks<B, true>(a, ta, st, qu, cb0, ib0);
     scan_blocks<B, false>(a, ta, st, qu, ib0, ib1);
     scan_blocks<B, true>(a, ta, st, qu, ib1, cb1);
+    before_end();
     if (st.qn) flush_queue16<B>(ta, st, qu);
     if (lane < GR) {
         const u64 bk = qu->best[lane];
@@ -1376,15 +1397,17 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma(const SearchArgs *__rest
     st.qn = 0;
     u64 items_done = 0;
     ItemQueue iq = item_queue(tab, n_img);
-    uint32_t raw = claim_issue(item_ctr, iq);
+    uint32_t raw = 0;
+    claim_issue(item_ctr, iq, raw);
     for (;;) {
         uint32_t item;
         if (!claim_take(raw, item_ctr, tab, nitems, dbg, iq, item)) break;
-        raw = claim_issue(item_ctr, iq);            // the next item, in flight meanwhile
         const int ia = image_of_item(base, n_img, item);
         const SearchArgs *ta = tab + ia;
         const SearchArgs a = *ta;
-        item16<B>(ta, a, a.items[item - base[ia]], st, qu);
+        // the next item is claimed before this one's end work
+        item16<B>(ta, a, a.items[item_in_image(base, ia, item)], st, qu,
+                  [&]() { claim_issue(item_ctr, iq, raw); });
         items_done += 1;
     }
     add_counters(counters, st.screened, st.survivors, items_done);
@@ -1440,15 +1463,10 @@ __global__ __launch_bounds__(256, 2) void k_search_lds16(const SearchArgs *__res
         const int ok = sOk;
         __syncthreads();
         if (!ok) break;
-        int ia = 0, ib = n_img;              // last image whose base <= item
-        while (ib - ia > 1) {
-            const int m = (ia + ib) >> 1;
-            if (base[m] <= item) ia = m; else ib = m;
-        }
-        ia = __builtin_amdgcn_readfirstlane(ia);
+        const int ia = image_of_item(base, n_img, item);
         const SearchArgs *ta = tab + ia;
         const SearchArgs a = *ta;
-        const WorkItem wi = a.items[item - base[ia]];
+        const WorkItem wi = a.items[item_in_image(base, ia, item)];
         st.flush_at = (uint32_t)a.flush_at;
         st.grp = __builtin_amdgcn_readfirstlane(wi.grp) * 4 + (uint32_t)w;
         const frag_t *ap = (const frag_t *)a.A + (int64_t)st.grp * MW * KS * 64 + lane;
@@ -1988,9 +2006,10 @@ __device__ __forceinline__ void scan32(const SearchArgs &a, const SearchArgs *ta
 }
 
 // One work item of the 32x32-tile search (4x4 ranges), as item16.
-template <int B>
+template <int B, class Hook = NoHook>
 __device__ __forceinline__ void item32(const SearchArgs *ta, const SearchArgs &a,
-                                       const WorkItem &wi, Wave32<B> &st, Queue32<B> *qu)
+                                       const WorkItem &wi, Wave32<B> &st, Queue32<B> *qu,
+                                       const Hook &before_end = Hook())
 {
     constexpr int MB = Cfg<B>::MB, KS = Cfg<B>::KS, GR = Cfg<B>::GR;
     const int lane = threadIdx.x & 63, h = lane >> 5;
@@ -2039,6 +2058,7 @@ __device__ __forceinline__ void item32(const SearchArgs *ta, const SearchArgs &a
     scan32<B, true>(a, ta, st, qu, cb0, ib0);
     scan32<B, false>(a, ta, st, qu, ib0, ib1);
     scan32<B, true>(a, ta, st, qu, ib1, cb1);
+    before_end();
     if (st.cq) replay_queue32<B>(ta, st, qu);
     if (st.qn) flush_queue32<B>(ta, st, qu);
     if (lane < GR) {
@@ -2066,15 +2086,16 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma32(const SearchArgs *__re
     st.cq = 0;
     u64 items_done = 0;
     ItemQueue iq = item_queue(tab, n_img);
-    uint32_t raw = claim_issue(item_ctr, iq);
+    uint32_t raw = 0;
+    claim_issue(item_ctr, iq, raw);
     for (;;) {
         uint32_t item;
         if (!claim_take(raw, item_ctr, tab, nitems, dbg, iq, item)) break;
-        raw = claim_issue(item_ctr, iq);            // the next item, in flight meanwhile
         const int ia = image_of_item(base, n_img, item);
         const SearchArgs *ta = tab + ia;
         const SearchArgs a = *ta;
-        item32<B>(ta, a, a.items[item - base[ia]], st, qu);
+        claim_issue(item_ctr, iq, raw);             // the next item
+        item32<B>(ta, a, a.items[item_in_image(base, ia, item)], st, qu);
         items_done += 1;
     }
     add_counters(counters, st.screened, st.survivors, items_done);
@@ -2104,11 +2125,12 @@ __global__ __launch_bounds__(256, 2) void k_search_mixed(const SearchArgs *__res
     const uint32_t ni8 = base8[n8];
     const uint32_t nitems = ni8 + base4[n4];
     // the next item is claimed while this one runs (see claim_issue)
-    uint32_t raw = lane == 0 ? atomicAdd(item_ctr, 1u) : 0u;
+    uint32_t raw = 0;
+    if (lane == 0) raw = atomicAdd(item_ctr, 1u);
     for (;;) {
         uint32_t item = __builtin_amdgcn_readfirstlane(raw);
         if (item >= nitems) break;
-        raw = lane == 0 ? atomicAdd(item_ctr, 1u) : 0u;
+        if (lane == 0) raw = atomicAdd(item_ctr, 1u);
         if (dbg & kDbgReverse) item = nitems - 1u - item;   // order-independence check
         // per item: the queue is empty between items, and the counters are
         // added per item (nothing but the loop is carried across items)
@@ -2120,7 +2142,7 @@ __global__ __launch_bounds__(256, 2) void k_search_mixed(const SearchArgs *__res
             s8.qn = 0;
             s8.screened = 0;
             s8.survivors = 0;
-            item16<8>(ta, a, a.items[item - base8[ia]], s8, &qm[w].q8);
+            item16<8>(ta, a, a.items[item_in_image(base8, ia, item)], s8, &qm[w].q8);
             add_counters(counters, s8.screened, s8.survivors, 1);
         } else {
             const uint32_t i4 = item - ni8;
@@ -2133,7 +2155,7 @@ __global__ __launch_bounds__(256, 2) void k_search_mixed(const SearchArgs *__res
             s4.screened = 0;
             s4.survivors = 0;
             s4.replayed = 0;
-            item32<4>(ta, a, a.items[i4 - base4[ia]], s4, &qm[w].q4);
+            item32<4>(ta, a, a.items[item_in_image(base4, ia, i4)], s4, &qm[w].q4);
             add_counters(counters, s4.screened, s4.survivors, 1);
             if (counters && lane == 0) atomicAdd(&counters[7], s4.replayed);
         }
