@@ -252,6 +252,19 @@ def run_autotune(args, fic, images, jobs):
                         for r in rep]})
 
 
+def searched_sizes(img_np, b, sizes):
+    """Pool sizes with those of flat ranges set to 0. A range whose pixels
+    are all equal (Srr' = 0) is coded without a search: every domain fits it
+    exactly at k = 0, so the lowest pool domain under isometry 0 wins, and
+    the search kernels skip it. Its pairs are not evaluated and are not
+    counted. Ranges in raster order, as the pools."""
+    import numpy as np
+    h, w = img_np.shape
+    blk = np.asarray(img_np)[:h // b * b, :w // b * b].reshape(h // b, b, w // b, b)
+    flat = (blk.max(axis=(1, 3)) == blk.min(axis=(1, 3))).ravel()
+    return np.where(flat, 0, np.asarray(sizes))
+
+
 def search_kernel_name(b):
     """Name of the matrix-core search kernel the library runs for B x B ranges."""
     return {4: "k_search_mfma32<4>", 16: "k_search_lds16<16>"}.get(b, "k_search_mfma<%d>" % b)
@@ -321,7 +334,7 @@ def bench_image(args, fic, wl, img_np):
         else:
             _, lo, hi = pools[(b, t, tol)]
             sizes.append((hi.long() - lo.long()).cpu().numpy())
-        pairs.append(int(sizes[-1].sum()) * 8)
+        pairs.append(int(searched_sizes(img_np, b, sizes[-1]).sum()) * 8)
     pairs_step = sum(pairs)
     progress("%s: %d jobs, %d pair evaluations per step" % (wl.name, len(jobs), pairs_step))
 
@@ -505,7 +518,9 @@ def bench_quadtree(args, fic, wl, img_np):
         sizes.append((hi.long() - lo.long()).cpu().numpy())
     coded = (fic.unpack_codes(c2)["flags"] & 4) == 0
     split = int(((fic.unpack_codes(c1)["flags"] & 2) != 0).sum())
-    pairs = [int(sizes[0].sum()) * 8, int(sizes[1][coded].sum()) * 8]
+    s1 = searched_sizes(img_np, b1, sizes[0])
+    s2 = searched_sizes(img_np, b2, sizes[1])
+    pairs = [int(s1.sum()) * 8, int(s2[coded].sum()) * 8]
     pairs_step = sum(pairs)
     progress("%s: %d of %d ranges split, %d pair evaluations per step"
              % (wl.name, split, sizes[0].size, pairs_step))
@@ -570,7 +585,8 @@ def bench_color(args, fic, wl, rgb_np):
     fr, _ = fic.fd_classify(lx, b, b, want_fp32=False)
     fd, _ = fic.fd_classify(lx, 2 * b, t, want_fp32=False)
     _, lo, hi = fic.build_domain_pool(fr, fd, tol)
-    pairs_step = 3 * int((hi.long() - lo.long()).sum().item()) * 8
+    sz = (hi.long() - lo.long()).cpu().numpy()
+    pairs_step = sum(int(searched_sizes(rgb_np[:, :, c], b, sz).sum()) * 8 for c in range(3))
     progress("%s: %d pair evaluations per step" % (wl.name, pairs_step))
     for _ in range(args.warmup):
         fic.encode_color(rgb, b, t, tol=tol)
@@ -649,7 +665,7 @@ def bench_adaptive(args, fic):
         fd, _ = fic.fd_classify(x, 2 * b, t, want_fp32=False)
         fdn = fd.cpu().numpy()
         pe, pd = psnr(oe.cpu().numpy(), im), psnr(od.cpu().numpy(), im)
-        pairs = int(sizes.sum()) * 8
+        pairs = int(searched_sizes(im, b, sizes).sum()) * 8
         tot_pairs += pairs
         tot_ms += ms_d
         rows.append({"workload": name, "image": "%dx%d" % (H, W), "range_size": b,
@@ -699,7 +715,7 @@ def bench_batch(args, fic, wl):
         _, lo, hi = fic.build_domain_pool(fr, fd, tol)
         sz = (hi.long() - lo.long()).cpu().numpy()
         sizes.append(sz)
-        pairs_b[b] = pairs_b.get(b, 0) + int(sz.sum()) * 8
+        pairs_b[b] = pairs_b.get(b, 0) + int(searched_sizes(x.cpu().numpy(), b, sz).sum()) * 8
         margin = min(margin, pool_margin(fr, fd, tol))
     pairs_step = sum(pairs_b.values())
     progress("%s: %d images, %d pair evaluations per step" % (wl.name, len(items), pairs_step))
