@@ -21,7 +21,9 @@
 //                F (16x16 ranges screen one FP32 sum against a threshold
 //                lowered by its rounding bound and recompute the exact chunks
 //                only for blocks that pass); passing cells queue in LDS and
-//                get the exact fit a wave's worth at a time; packed
+//                get the exact fit a wave's worth at a time (4x4 ranges queue
+//                the passing columns and replay them, cells screened one by
+//                one, before their cells are queued); packed
 //                (F, domain, isometry) keys meet in LDS, and each flush
 //                exchanges them with the global keys, so waves on other
 //                column chunks of the same ranges tighten each other's
@@ -32,10 +34,13 @@
 //   finalize     recompute the winner exactly from the image, write fic_code.
 // Plain path (FIC_KERNEL_PLAIN): one thread per (range, domain, isometry),
 // integer cross term from the 2x2-sum image, exact fit, the same keys.
-// On top of these: batches (one persistent search per range size over many
-// images, recorded as a HIP graph), the two-level partition (level-2 search
-// of the quadrants of split ranges) and colour (three channel searches over
-// the pools of one gray image).
+// The work split (columns per item, early flush trigger, per-XCD queues)
+// comes from a tuning row per (range size, log2 D) and pool-fraction bucket,
+// read on the device. On top of these: batches (persistent searches over the
+// items of many images, one per range size or 4x4 and 8x8 in one launch,
+// recorded as a HIP graph), the two-level partition (level-2 search of the
+// quadrants of split ranges) and colour (three channel searches over the
+// pools of one gray image).
 #include "fic_internal.h"
 
 #include <algorithm>
@@ -46,10 +51,6 @@ namespace fic {
 
 namespace {
 
-// Columns per work item: 2^chunk_log2 from the image's tuning row and pool-
-// fraction bucket, chosen on the device (TuneRow). Each item reloads its
-// group's A rows, so wide items cut that traffic, while narrow items balance
-// the uneven work of pooled searches.
 constexpr int kBminBlock = 1024; // perm entries per block-minimum
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -2721,6 +2722,7 @@ hipError_t run_encode_batch(const BatchJob *jobs, const BatchPlan &bp, void *ws,
         e = hipGetLastError();
     }
     // otherwise one persistent search per range size over all its images
+    // (the tuned launch choice, or a single range size)
     for (int gi = 0; gi < 3 && e == hipSuccess; ++gi) {
         if (bp.group_count[gi] == 0 || (mixed && gi < 2)) continue;
         const SearchArgs *t = tab + bp.group_first[gi];

@@ -104,8 +104,9 @@ struct WorkItem { uint32_t grp, c0, c1, pad; };
 // f = (sum of pool sizes) / (R * D) falls in bucket 1 + floor(-log2 f),
 // clamped to [1, kTuneBuckets - 1]. Per bucket: the columns of a work item
 // (2^chunk_log2, kChunkLog2Min..kChunkLog2Max) and the early flush trigger of
-// the search queue (flush once at least flush_at half cells (4x4: cells) are
-// queued; 0 = only when the queue is full), and whether a single-image
+// the search queue (flush once at least flush_at half cells are queued; 4x4:
+// cells, tested after each replay of queued columns; 0 = only when the queue
+// is full), and whether a single-image
 // search takes its work items from one queue per XCD (xcd = 1: queue x holds
 // the column chunks c = x (mod 8), so each XCD's L2 streams an eighth of the
 // domain columns; waves steal from the other queues when theirs is empty).
