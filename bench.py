@@ -504,6 +504,9 @@ def bench_quadtree(args, fic, wl, img_np):
     H, W = img_np.shape
     (b1, t1, tol1), (b2, t2, tol2) = wl.jobs
     ctx = fic.fic.context(0)
+    # the autotuner on the two levels' jobs over the whole image: its rows are
+    # per (range size, domain count), so the two-level encode uses them
+    tune = run_autotune(args, fic, [img, img], list(wl.jobs))
     c1, c2 = fic.encode_quadtree(img, b1, t1, tol1, b2, t2, tol2, wl.rms)
 
     def step():
@@ -561,6 +564,7 @@ def bench_quadtree(args, fic, wl, img_np):
         "search_pairs_per_s_per_level": [round(p / (m / 1e3), 1) for p, m in zip(pairs, lv_ms)],
         "stage_ms_per_step": {k: round(v, 4) for k, v in stage_ms.items()},
         "roofline": roofline,
+        "autotune": tune,
     }
     if not args.no_cpu:
         out["cpu_baseline"] = oracle_rate(img_np, b1, t1, tol1, sizes[0], None, args.cpu_seconds,
