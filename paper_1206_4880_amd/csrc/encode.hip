@@ -696,6 +696,8 @@ template <int B> struct Queue16 {
     float T[Cfg<B>::GR];             // their thresholds
     int64_t srr[Cfg<B>::GR];         // their Srr'
     int32_t delta[Cfg<B>::GR];       // their delta = sum r - n*rhat
+    uint32_t lo[Cfg<B>::GR];         // their pool windows (empty if idle)
+    uint32_t hi[Cfg<B>::GR];
 };
 
 template <int B> struct WaveState {
@@ -1325,27 +1327,29 @@ __device__ __forceinline__ void item16(const SearchArgs *ta, const SearchArgs &a
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) st.af[b][ks] = ap[(b * KS + ks) * 64];
     if (lane < GR) {
-        // the flush re-screens queued cells against these thresholds
+        // the group's range constants and thresholds, once per range: the
+        // flush re-screens queued cells against these, and every lane takes
+        // its row blocks' values from here (an active range's pool is never
+        // empty, so an empty window marks an idle range)
         const int64_t slot = (int64_t)st.grp * GR + lane;
         const u64 bk = a.keys[slot];
-        const int64_t srr = a.rs[slot].srr;
-        qu->best[lane] = bk;
-        qu->srr[lane] = srr;
-        qu->delta[lane] = a.rs[slot].delta;
-        qu->T[lane] = bk == kNoKey ? 0.0f : screen_t_b<B>(srr, (int64_t)(bk >> a.shift));
-    }
-#pragma unroll
-    for (int b = 0; b < MW; ++b) {
-        const int64_t slot = (int64_t)st.grp * GR + tile_range<B>(b, lane);
         const RangeStat rsx = a.rs[slot];
-        const u64 bk = a.keys[slot];
-        st.lo[b] = rsx.lo;
-        st.hi[b] = rsx.hi;
         const bool act = !(rsx.flags & kIdle);
-        st.T[b] = !act ? __builtin_inff()
-                       : (bk == kNoKey ? 0.0f : screen_t_b<B>(rsx.srr, (int64_t)(bk >> a.shift)));
+        qu->best[lane] = bk;
+        qu->srr[lane] = rsx.srr;
+        qu->delta[lane] = rsx.delta;
+        qu->T[lane] = bk == kNoKey ? 0.0f : screen_t_b<B>(rsx.srr, (int64_t)(bk >> a.shift));
+        qu->lo[lane] = act ? rsx.lo : 0u;
+        qu->hi[lane] = act ? rsx.hi : 0u;
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+    for (int b = 0; b < MW; ++b) {
+        const int r = tile_range<B>(b, lane);
+        st.lo[b] = qu->lo[r];
+        st.hi[b] = qu->hi[r];
+        st.T[b] = st.hi[b] > st.lo[b] ? qu->T[r] : __builtin_inff();
+    }
     const uint4 gb = a.grp[st.grp];
     const int cb0 = (int)(wi.c0 >> 4), cb1 = (int)(wi.c1 >> 4);
     // column blocks fully inside every active range's pool need no mask
@@ -2034,21 +2038,17 @@ __device__ __forceinline__ void item32(const SearchArgs *ta, const SearchArgs &a
         qu->lo[lane] = act ? rsx.lo : 0u;
         qu->hi[lane] = act ? rsx.hi : 0u;
     }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    // every lane's cells from the values above (an empty window: idle)
 #pragma unroll
     for (int blk = 0; blk < MB; ++blk)
 #pragma unroll
         for (int hl = 0; hl < 2; ++hl) {
-            const int64_t slot = (int64_t)st.grp * GR + 4 * blk + 2 * h + hl;
-            const RangeStat rsx = a.rs[slot];
-            const u64 bk = a.keys[slot];
-            st.lo[blk][hl] = rsx.lo;
-            st.hi[blk][hl] = rsx.hi;
-            const bool act = !(rsx.flags & kIdle);
-            st.T[blk][hl] = !act ? __builtin_inff()
-                                 : (bk == kNoKey ? 0.0f
-                                                 : screen_t(rsx.srr, (int64_t)(bk >> a.shift)));
+            const int r = 4 * blk + 2 * h + hl;
+            st.lo[blk][hl] = qu->lo[r];
+            st.hi[blk][hl] = qu->hi[r];
+            st.T[blk][hl] = st.hi[blk][hl] > st.lo[blk][hl] ? qu->T[r] : __builtin_inff();
         }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     const uint4 gb = a.grp[st.grp];
     const int cb0 = (int)(wi.c0 >> 5), cb1 = (int)(wi.c1 >> 5);
     // column blocks fully inside every active range's pool need no mask
