@@ -1480,30 +1480,33 @@ __global__ __launch_bounds__(256, 2) void k_search_lds16(const SearchArgs *__res
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) st.af[b][ks] = ap[(b * KS + ks) * 64];
         if (lane < GR) {
-            // the flush re-screens queued cells against these thresholds
+            // the range constants and thresholds once per range (as item16):
+            // the flush re-screens queued cells against them and every lane
+            // takes its row blocks' values from here
             const int64_t slot = (int64_t)st.grp * GR + lane;
             const u64 bk = a.keys[slot];
-            const int64_t srr = a.rs[slot].srr;
+            const RangeStat rsx = a.rs[slot];
+            const bool act = !(rsx.flags & kIdle);
             qu->best[lane] = bk;
-            qu->srr[lane] = srr;
-            qu->delta[lane] = a.rs[slot].delta;
-            qu->T[lane] = bk == kNoKey ? 0.0f : screen_t_b<B>(srr, (int64_t)(bk >> a.shift));
+            qu->srr[lane] = rsx.srr;
+            qu->delta[lane] = rsx.delta;
+            qu->T[lane] = bk == kNoKey ? 0.0f : screen_t_b<B>(rsx.srr, (int64_t)(bk >> a.shift));
+            qu->lo[lane] = act ? rsx.lo : 0u;
+            qu->hi[lane] = act ? rsx.hi : 0u;
         }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         // the wave's own pools: union [wlo, whi) and intersection [ilo, ihi)
         uint32_t wlo = 0xffffffffu, whi = 0u, ilo = 0u, ihi = 0xffffffffu;
 #pragma unroll
         for (int b = 0; b < MW; ++b) {
-            const int64_t slot = (int64_t)st.grp * GR + tile_range<B>(b, lane);
-            const RangeStat rsx = a.rs[slot];
-            const u64 bk = a.keys[slot];
-            st.lo[b] = rsx.lo;
-            st.hi[b] = rsx.hi;
-            const bool act = !(rsx.flags & kIdle);
-            st.T[b] = !act ? __builtin_inff()
-                           : (bk == kNoKey ? 0.0f : screen_t_b<B>(rsx.srr, (int64_t)(bk >> a.shift)));
+            const int r = tile_range<B>(b, lane);
+            st.lo[b] = qu->lo[r];
+            st.hi[b] = qu->hi[r];
+            const bool act = st.hi[b] > st.lo[b];     // an empty window: idle
+            st.T[b] = act ? qu->T[r] : __builtin_inff();
             if (act) {
-                wlo = min(wlo, rsx.lo); whi = max(whi, rsx.hi);
-                ilo = max(ilo, rsx.lo); ihi = min(ihi, rsx.hi);
+                wlo = min(wlo, st.lo[b]); whi = max(whi, st.hi[b]);
+                ilo = max(ilo, st.lo[b]); ihi = min(ihi, st.hi[b]);
             }
         }
         wlo = min(wlo, (uint32_t)__shfl_xor((int)wlo, 32));
