@@ -308,59 +308,95 @@ __global__ void k_sort_finish(u64 *__restrict__ ka, uint32_t *__restrict__ va,
     if (fd_out) fd_out[i] = fd_of_bits(k);
 }
 
-// Up to kSmallSort pairs: the whole sort in one workgroup, in LDS, as a
-// bitonic sort of (the key's low key_bits bits, the pair's original
-// position): the positions make equal keys keep their order, so the result
-// is the stable sort's. The count is padded to a power of two with entries
-// above every real one (all key bits set, position 0xffff). With fd_out
-// (nullable) the sorted keys are also decoded as fd_bits images.
+// Up to kSmallSort pairs: the whole sort in one workgroup, in LDS. Per pass
+// a digit histogram, its scan (a pass where one digit holds every key is
+// skipped) and a stable scatter of the keys in index order, 1024 at a time:
+// ballot ranks inside a wave, per-wave digit counts across the 16 waves.
 constexpr int kSmallThreads = 1024;
 constexpr int kSmallSort = 4096;
 
 __global__ __launch_bounds__(kSmallThreads) void k_sort_small(u64 *__restrict__ keys,
                                                               uint32_t *__restrict__ vals, int n,
-                                                              int key_bits, double *__restrict__ fd_out)
+                                                              int passes, double *__restrict__ fd_out)
 {
-    __shared__ u64 sk[kSmallSort];
-    __shared__ uint32_t sv[kSmallSort];
-    __shared__ uint16_t sp[kSmallSort];
-    const int tid = threadIdx.x;
-    const u64 mask = key_bits >= 64 ? ~0ull : ((1ull << key_bits) - 1ull);
-    int np = 2;
-    while (np < n) np <<= 1;
-    for (int i = tid; i < np; i += kSmallThreads) {
-        const bool real = i < n;
-        sk[i] = real ? keys[i] : ~0ull;
-        sv[i] = real ? vals[i] : 0u;
-        sp[i] = real ? (uint16_t)i : (uint16_t)0xffffu;
+    __shared__ u64 sk[2][kSmallSort];
+    __shared__ uint32_t sv[2][kSmallSort];
+    __shared__ uint32_t hist[256], run[256], wsum[4];
+    __shared__ uint32_t wc[kSmallThreads / kWave][256];
+    __shared__ int skip;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    for (int i = tid; i < n; i += kSmallThreads) {
+        sk[0][i] = keys[i];
+        sv[0][i] = vals[i];
     }
-    __syncthreads();
-    for (int k = 2; k <= np; k <<= 1)
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            // pair p: i = its lower element, l = i + j; ascending where i & k == 0
-            for (int p = tid; p < np / 2; p += kSmallThreads) {
-                const int i = ((p & ~(j - 1)) << 1) | (p & (j - 1));
-                const int l = i + j;
-                const u64 a = sk[i] & mask, b = sk[l] & mask;
-                const bool gt = a > b || (a == b && sp[i] > sp[l]);
-                if (gt == ((i & k) == 0)) {
-                    const u64 tk = sk[i];
-                    sk[i] = sk[l];
-                    sk[l] = tk;
-                    const uint32_t tv = sv[i];
-                    sv[i] = sv[l];
-                    sv[l] = tv;
-                    const uint16_t tp = sp[i];
-                    sp[i] = sp[l];
-                    sp[l] = tp;
+    for (int i = tid; i < (kSmallThreads / kWave) * 256; i += kSmallThreads) (&wc[0][0])[i] = 0u;
+    int cur = 0;
+    const u64 lt = (1ull << lane) - 1ull;
+    for (int pass = 0; pass < passes; ++pass) {
+        const int shift = 8 * pass;
+        if (tid < 256) hist[tid] = 0u;
+        if (tid == 0) skip = 0;
+        __syncthreads();
+        for (int i = tid; i < n; i += kSmallThreads) atomicAdd(&hist[(sk[cur][i] >> shift) & 255u], 1u);
+        __syncthreads();
+        // exclusive scan of the 256 counts by waves 0..3
+        const uint32_t v = tid < 256 ? hist[tid] : 0u;
+        uint32_t x = v;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(x, off);
+            if (lane >= off) x += y;
+        }
+        if (tid < 256 && lane == 63) wsum[wave] = x;
+        if (tid < 256 && (int)v == n) skip = 1;
+        __syncthreads();
+        if (tid < 256) {
+            uint32_t b = 0;
+            for (int w = 0; w < wave; ++w) b += wsum[w];
+            run[tid] = b + x - v;
+        }
+        __syncthreads();
+        const int skipped = skip;
+        __syncthreads();                             // read by all before the next pass clears it
+        if (skipped) continue;                       // block-uniform
+        for (int base = 0; base < n; base += kSmallThreads) {
+            const int i = base + tid;
+            const bool valid = i < n;
+            const u64 key = valid ? sk[cur][i] : 0ull;
+            const uint32_t val = valid ? sv[cur][i] : 0u;
+            const uint32_t d = (uint32_t)(key >> shift) & 255u;
+            u64 peers = __ballot(valid);
+#pragma unroll
+            for (int bit = 0; bit < 8; ++bit) {
+                const u64 bb = __ballot((d >> bit) & 1u);
+                peers &= ((d >> bit) & 1u) ? bb : ~bb;
+            }
+            const uint32_t rank = __popcll(peers & lt);
+            if (valid && rank == 0) wc[wave][d] = __popcll(peers);
+            __syncthreads();
+            if (valid) {
+                uint32_t pos = run[d] + rank;
+                for (int w = 0; w < wave; ++w) pos += wc[w][d];
+                sk[cur ^ 1][pos] = key;
+                sv[cur ^ 1][pos] = val;
+            }
+            __syncthreads();
+            if (tid < 256) {
+                uint32_t add = 0;
+                for (int w = 0; w < kSmallThreads / kWave; ++w) {
+                    add += wc[w][tid];
+                    wc[w][tid] = 0u;
                 }
+                run[tid] += add;
             }
             __syncthreads();
         }
+        cur ^= 1;
+    }
     for (int i = tid; i < n; i += kSmallThreads) {
-        keys[i] = sk[i];
-        vals[i] = sv[i];
-        if (fd_out) fd_out[i] = fd_of_bits(sk[i]);
+        keys[i] = sk[cur][i];
+        vals[i] = sv[cur][i];
+        if (fd_out) fd_out[i] = fd_of_bits(sk[cur][i]);
     }
 }
 
@@ -434,8 +470,7 @@ hipError_t scan_u32(uint32_t *a, int64_t m, uint32_t *total, void *ws, hipStream
 }
 
 // Stable sort of n (key, value) pairs by the low key_bits bits of the keys
-// (LSD, 8-bit digits). Up to kSmallSort pairs: one launch (k_sort_small, a bitonic
-// sort in LDS with the same result).
+// (LSD, 8-bit digits). Up to kSmallSort pairs: one launch (k_sort_small).
 // Otherwise per digit the tile histograms and the stable scatter, with a
 // scan of the tile counts between them above kFusedScanTiles tiles, and a
 // last launch that copies the result back when it ended in the alternate
@@ -451,7 +486,7 @@ hipError_t radix_sort_pairs(u64 *keys, uint32_t *vals, int64_t n, int key_bits, 
     if (passes > kMaxPasses) return hipErrorInvalidValue;
     if (n <= kSmallSort) {
         hipLaunchKernelGGL(k_sort_small, dim3(1), dim3(kSmallThreads), 0, s, keys, vals, (int)n,
-                           key_bits, fd_out);
+                           passes, fd_out);
         return hipGetLastError();
     }
     const int nb = (int)((n + kSortTile - 1) / kSortTile);
