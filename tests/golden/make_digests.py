@@ -1,7 +1,7 @@
 """Write tests/golden/config_digests.json: SHA-256 digests of the oracle's
 codes for EVERY range of the full-size workloads, in blocks of 1024 ranges
 (ranges in raster order), so that the GPU tests can check whole jobs code for
-code without running the oracle on the GPU machine.
+code without running the oracle themselves (it takes hours at these sizes).
 
 Calls only ``oracle`` (the CPU oracle) and ``synth`` (the seeded images); it
 never loads the GPU library. Per job it also records the image's SHA-256, the
