@@ -236,8 +236,9 @@ fic_status fic_encode_pifs(fic_ctx *ctx, const uint8_t *img, const fic_geom *g,
  * routine and records no stage events.
  *   Arguments as fic_encode_pifs, without ws / ws_bytes.
  *   FIC_ERR_WORKSPACE when fic_encode_workspace_bytes(g, pooled) exceeds
- *   fic_noalloc_scratch_bytes() (64 MiB: e.g. any 512 x 512 job, 1024 x 1024
- *   at domain step 2).
+ *   fic_noalloc_scratch_bytes() (64 MiB: e.g. 512 x 512 jobs with 4 x 4 or
+ *   8 x 8 ranges, 1024 x 1024 with 8 x 8 ranges at domain step 2; 16 x 16
+ *   ranges at domain step 1 need more from 512 x 512 up).
  * The array exists once per GPU (held until the process ends) and is shared
  * by every call on that GPU: calls that overlap on one GPU (other streams,
  * other host threads or contexts) race and must be serialised by the caller.
