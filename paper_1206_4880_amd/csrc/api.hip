@@ -1021,6 +1021,9 @@ fic_status fic_tune_save(fic_ctx *ctx, const char *path)
     return (fclose(f) == 0 && ok) ? FIC_OK : FIC_ERR_INVALID_ARG;
 }
 
+}  // extern "C"
+
+// JSON helpers of the tuning cache (C++ types: outside the C block)
 namespace {
 // The string value of "key" in text (after the key's colon), or "".
 std::string json_str(const char *text, const char *key)
@@ -1071,6 +1074,8 @@ bool json_ints(const char *&p, const char *end, const char *key, long *v)
     return true;
 }
 }  // namespace
+
+extern "C" {
 
 fic_status fic_tune_load(fic_ctx *ctx, const char *path)
 {

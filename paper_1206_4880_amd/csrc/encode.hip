@@ -1393,7 +1393,6 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma(const SearchArgs *__rest
                                                         u64 *counters, uint32_t dbg)
 {
     __shared__ Queue16<B> queues[4];
-    const int lane = threadIdx.x & 63;
     Queue16<B> *qu = &queues[threadIdx.x >> 6];
     const uint32_t nitems = base[n_img];
     WaveState<B> st;
