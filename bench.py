@@ -651,6 +651,21 @@ def bench_adaptive(args, fic):
         torch.cuda.synchronize()
         return codes, pool, (time.perf_counter() - t0) * 1e3 / max(1, args.steps)
 
+    def timed_graph(x, b, t, tol, ref):
+        """The same encode as a one-image batch call replayed as a HIP graph
+        (recorded by the first call): ms per call, and whether its codes
+        equal the single-image call's."""
+        job = [(b, t, tol)]
+        ws = torch.empty(fic.batch_workspace_bytes([x], job), dtype=torch.uint8, device=dev)
+        out = fic.encode_batch([x], job, ws=ws, graph=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(max(1, args.steps)):
+            fic.encode_batch([x], job, codes=out, ws=ws, graph=True)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / max(1, args.steps)
+        return ms, bool(torch.equal(out[0], ref))
+
     rows, tot_pairs, tot_ms = [], 0, 0.0
     for (name, im, b, t) in cases:
         x = torch.from_numpy(np.ascontiguousarray(im)).to(dev)
@@ -660,6 +675,14 @@ def bench_adaptive(args, fic):
             fic.encode(x, b, t, tol=-1.0)
         ce, _, ms_e = timed_encode(x, b, t, None)
         cd, pool, ms_d = timed_encode(x, b, t, -1.0)
+        graph = {}
+        if H * W <= 256 * 256:
+            # small images: is the time host launch overhead or the GPU's kernel chain?
+            ge, eq_e = timed_graph(x, b, t, None, ce)
+            gd, eq_d = timed_graph(x, b, t, -1.0, cd)
+            graph = {"encode_ms_exhaustive_graph": round(ge, 3),
+                     "encode_ms_adaptive_graph": round(gd, 3),
+                     "graph_codes_equal": eq_e and eq_d}
         _, lo, hi = pool
         sizes = (hi.long() - lo.long()).cpu().numpy()
         frac = float(sizes.mean()) / D
@@ -677,7 +700,8 @@ def bench_adaptive(args, fic):
                      "pool_fraction": round(frac, 4),
                      "empty_pool_ranges": int((sizes == 0).sum()),
                      "psnr_exhaustive_db": round(pe, 3), "psnr_adaptive_db": round(pd, 3),
-                     "encode_ms_exhaustive": round(ms_e, 3), "encode_ms_adaptive": round(ms_d, 3)})
+                     "encode_ms_exhaustive": round(ms_e, 3), "encode_ms_adaptive": round(ms_d, 3),
+                     **graph})
         progress("%s B=%d t=%d: pool %.3f, PSNR %.2f / %.2f dB, %.2f / %.2f ms"
                  % (name, b, t, frac, pe, pd, ms_e, ms_d))
     return {

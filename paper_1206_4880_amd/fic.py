@@ -369,6 +369,17 @@ def encode(img, range_size, domain_step, tol=None, kernel="mfma"):
     return encode_pifs(img, range_size, domain_step, pool=pool, kernel=kernel), pool
 
 
+def batch_workspace_bytes(images, jobs):
+    """fic_batch_workspace_bytes for these images and jobs [(B, t, tol)]."""
+    n = len(images)
+    descs = (ImageDesc * n)()
+    for i, (img, (b, t, tol)) in enumerate(zip(images, jobs)):
+        _need_cuda_u8(img)
+        descs[i].geom = _geom_of(img, b, t)
+        descs[i].tol = float("inf") if tol is None else float(tol)
+    return int(lib().fic_batch_workspace_bytes(n, descs))
+
+
 def encode_batch(images, jobs, codes=None, ws=None, graph=True):
     """Batch encode: images (list of uint8 CUDA tensors), jobs [(B, t, tol)].
     Returns the list of codes tensors. `codes` and `ws` (uint8 CUDA tensors)
