@@ -310,10 +310,28 @@ __global__ void k_sort_finish(u64 *__restrict__ ka, uint32_t *__restrict__ va,
 
 // Up to kSmallSort pairs: the whole sort in one workgroup, in LDS. Per pass
 // a digit histogram, its scan (a pass where one digit holds every key is
-// skipped) and a stable scatter of the keys in index order, 1024 at a time:
-// ballot ranks inside a wave, per-wave digit counts across the 16 waves.
+// skipped) and a stable scatter of the keys in index order, 1024 at a time.
+// Keys of equal digit inside a wave find each other by ballots over the
+// digit's bits: the histogram takes one LDS atomic per (wave, digit) instead
+// of one per key (the digits of nearby fractal dimensions crowd a few bins),
+// and a key's position is its digit's offset for its wave (run of the digit
+// plus the counts of the waves before it, tabulated once per 1024 keys by
+// one thread per digit) plus its rank among its wave's equal digits.
 constexpr int kSmallThreads = 1024;
 constexpr int kSmallSort = 4096;
+constexpr int kSmallWaves = kSmallThreads / kWave;
+
+// Lanes of the wave whose 8-bit digit equals this lane's (valid lanes only).
+__device__ __forceinline__ u64 digit_peers(uint32_t d, bool valid)
+{
+    u64 peers = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+        const u64 bb = __ballot((d >> bit) & 1u);
+        peers &= ((d >> bit) & 1u) ? bb : ~bb;
+    }
+    return peers;
+}
 
 __global__ __launch_bounds__(kSmallThreads) void k_sort_small(u64 *__restrict__ keys,
                                                               uint32_t *__restrict__ vals, int n,
@@ -322,14 +340,15 @@ __global__ __launch_bounds__(kSmallThreads) void k_sort_small(u64 *__restrict__ 
     __shared__ u64 sk[2][kSmallSort];
     __shared__ uint32_t sv[2][kSmallSort];
     __shared__ uint32_t hist[256], run[256], wsum[4];
-    __shared__ uint32_t wc[kSmallThreads / kWave][256];
+    __shared__ uint32_t wc[kSmallWaves][256];    // per-wave digit counts (zero between uses)
+    __shared__ uint32_t wo[kSmallWaves][256];    // per-wave digit offsets
     __shared__ int skip;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     for (int i = tid; i < n; i += kSmallThreads) {
         sk[0][i] = keys[i];
         sv[0][i] = vals[i];
     }
-    for (int i = tid; i < (kSmallThreads / kWave) * 256; i += kSmallThreads) (&wc[0][0])[i] = 0u;
+    for (int i = tid; i < kSmallWaves * 256; i += kSmallThreads) (&wc[0][0])[i] = 0u;
     int cur = 0;
     const u64 lt = (1ull << lane) - 1ull;
     for (int pass = 0; pass < passes; ++pass) {
@@ -337,7 +356,13 @@ __global__ __launch_bounds__(kSmallThreads) void k_sort_small(u64 *__restrict__ 
         if (tid < 256) hist[tid] = 0u;
         if (tid == 0) skip = 0;
         __syncthreads();
-        for (int i = tid; i < n; i += kSmallThreads) atomicAdd(&hist[(sk[cur][i] >> shift) & 255u], 1u);
+        for (int base = 0; base < n; base += kSmallThreads) {
+            const int i = base + tid;
+            const bool valid = i < n;
+            const uint32_t d = valid ? (uint32_t)(sk[cur][i] >> shift) & 255u : 0u;
+            const u64 peers = digit_peers(d, valid);
+            if (valid && (peers & lt) == 0ull) atomicAdd(&hist[d], (uint32_t)__popcll(peers));
+        }
         __syncthreads();
         // exclusive scan of the 256 counts by waves 0..3
         const uint32_t v = tid < 256 ? hist[tid] : 0u;
@@ -365,33 +390,31 @@ __global__ __launch_bounds__(kSmallThreads) void k_sort_small(u64 *__restrict__ 
             const u64 key = valid ? sk[cur][i] : 0ull;
             const uint32_t val = valid ? sv[cur][i] : 0u;
             const uint32_t d = (uint32_t)(key >> shift) & 255u;
-            u64 peers = __ballot(valid);
-#pragma unroll
-            for (int bit = 0; bit < 8; ++bit) {
-                const u64 bb = __ballot((d >> bit) & 1u);
-                peers &= ((d >> bit) & 1u) ? bb : ~bb;
-            }
+            const u64 peers = digit_peers(d, valid);
             const uint32_t rank = __popcll(peers & lt);
             if (valid && rank == 0) wc[wave][d] = __popcll(peers);
             __syncthreads();
+            if (tid < 256) {
+                // digit tid: offsets of the waves in order, the counts cleared
+                uint32_t acc = run[tid];
+#pragma unroll
+                for (int w = 0; w < kSmallWaves; ++w) {
+                    const uint32_t c = wc[w][tid];
+                    wo[w][tid] = acc;
+                    wc[w][tid] = 0u;
+                    acc += c;
+                }
+                run[tid] = acc;
+            }
+            __syncthreads();
             if (valid) {
-                uint32_t pos = run[d] + rank;
-                for (int w = 0; w < wave; ++w) pos += wc[w][d];
+                const uint32_t pos = wo[wave][d] + rank;
                 sk[cur ^ 1][pos] = key;
                 sv[cur ^ 1][pos] = val;
             }
-            __syncthreads();
-            if (tid < 256) {
-                uint32_t add = 0;
-                for (int w = 0; w < kSmallThreads / kWave; ++w) {
-                    add += wc[w][tid];
-                    wc[w][tid] = 0u;
-                }
-                run[tid] += add;
-            }
-            __syncthreads();
         }
         cur ^= 1;
+        __syncthreads();
     }
     for (int i = tid; i < n; i += kSmallThreads) {
         keys[i] = sk[cur][i];
