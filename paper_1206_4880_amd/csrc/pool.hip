@@ -161,9 +161,23 @@ __device__ inline uint32_t block_scan_1024(uint32_t v, uint32_t *wsum, uint32_t 
     return base + x - v;
 }
 
+// Lanes of the wave whose 8-bit digit equals this lane's (valid lanes only).
+__device__ __forceinline__ u64 digit_peers(uint32_t d, bool valid)
+{
+    u64 peers = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+        const u64 bb = __ballot((d >> bit) & 1u);
+        peers &= ((d >> bit) & 1u) ? bb : ~bb;
+    }
+    return peers;
+}
+
 // Pass `pass` (digit at bit `shift`) of the multi-block sort, step 1: per
 // tile digit counts into cnt (digit-major: cnt[d * nbp + tile], nbp = nb
 // padded to 16).
+// Keys of equal digit in a wave are counted together: one LDS atomic per
+// (wave, digit), not one per key (nearby dimensions crowd a few digits).
 __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const u64 *__restrict__ ka,
                                                             const u64 *__restrict__ kb, int64_t n,
                                                             int shift, int pass,
@@ -176,10 +190,14 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const u64 *__restric
     if (tid < 256) h[tid] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    const u64 lt = (1ull << (tid & 63)) - 1ull;
 #pragma unroll
     for (int r = 0; r < kSortPerThread; ++r) {
         const int64_t i = base + r * kSortThreads + tid;
-        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+        const bool valid = i < n;
+        const uint32_t d = valid ? (uint32_t)(keys[i] >> shift) & 255u : 0u;
+        const u64 peers = digit_peers(d, valid);
+        if (valid && (peers & lt) == 0ull) atomicAdd(&h[d], (uint32_t)__popcll(peers));
     }
     __syncthreads();
     if (tid < 256) cnt[(int64_t)tid * padded_tiles(nb) + blockIdx.x] = h[tid];
@@ -207,7 +225,8 @@ __global__ __launch_bounds__(256) void k_sort_scan(uint32_t *__restrict__ cnt, i
 }
 
 // Step 3: stable scatter of each tile by the digit: equal digits are ranked
-// by position with wave ballots, waves in order, rounds in order. A tile's
+// by position with wave ballots, waves in order (one thread per digit
+// tabulates each wave's offset once per round), rounds in order. A tile's
 // start position of digit d is (keys of smaller digits) + (keys of digit d in
 // earlier tiles): from the scan (offs, tot) or, with fused (nb <=
 // kFusedScanTiles), summed here from the raw tile counts. A pass in which
@@ -219,7 +238,8 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
     const uint32_t *__restrict__ tot, int nb, int fused, SortCtl *ctl)
 {
     __shared__ uint32_t run[256];
-    __shared__ uint32_t wc[kSortWaves][256];
+    __shared__ uint32_t wc[kSortWaves][256];     // per-wave digit counts (zero between uses)
+    __shared__ uint32_t wo[kSortWaves][256];     // per-wave digit offsets
     __shared__ uint32_t wsum[kSortWaves];
     __shared__ int skip;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -261,31 +281,28 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
         const u64 key = valid ? kin[i] : 0ull;
         const uint32_t val = valid ? vin[i] : 0u;
         const uint32_t d = (uint32_t)(key >> shift) & 255u;
-        u64 peers = __ballot(valid);
-#pragma unroll
-        for (int bit = 0; bit < 8; ++bit) {
-            const u64 bb = __ballot((d >> bit) & 1u);
-            peers &= ((d >> bit) & 1u) ? bb : ~bb;
-        }
+        const u64 peers = digit_peers(d, valid);
         const uint32_t rank = __popcll(peers & lt);
         if (valid && rank == 0) wc[wave][d] = __popcll(peers);
         __syncthreads();
+        if (tid < 256) {
+            // digit tid: offsets of the waves in order, the counts cleared
+            uint32_t acc = run[tid];
+#pragma unroll
+            for (int w = 0; w < kSortWaves; ++w) {
+                const uint32_t c = wc[w][tid];
+                wo[w][tid] = acc;
+                wc[w][tid] = 0u;
+                acc += c;
+            }
+            run[tid] = acc;
+        }
+        __syncthreads();
         if (valid) {
-            uint32_t pos = run[d] + rank;
-            for (int w = 0; w < wave; ++w) pos += wc[w][d];
+            const uint32_t pos = wo[wave][d] + rank;
             kout[pos] = key;
             vout[pos] = val;
         }
-        __syncthreads();
-        if (tid < 256) {
-            uint32_t add = 0;
-            for (int w = 0; w < kSortWaves; ++w) {
-                add += wc[w][tid];
-                wc[w][tid] = 0u;
-            }
-            run[tid] += add;
-        }
-        __syncthreads();
     }
 }
 
@@ -320,18 +337,6 @@ __global__ void k_sort_finish(u64 *__restrict__ ka, uint32_t *__restrict__ va,
 constexpr int kSmallThreads = 1024;
 constexpr int kSmallSort = 4096;
 constexpr int kSmallWaves = kSmallThreads / kWave;
-
-// Lanes of the wave whose 8-bit digit equals this lane's (valid lanes only).
-__device__ __forceinline__ u64 digit_peers(uint32_t d, bool valid)
-{
-    u64 peers = __ballot(valid);
-#pragma unroll
-    for (int bit = 0; bit < 8; ++bit) {
-        const u64 bb = __ballot((d >> bit) & 1u);
-        peers &= ((d >> bit) & 1u) ? bb : ~bb;
-    }
-    return peers;
-}
 
 __global__ __launch_bounds__(kSmallThreads) void k_sort_small(u64 *__restrict__ keys,
                                                               uint32_t *__restrict__ vals, int n,
