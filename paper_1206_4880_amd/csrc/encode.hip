@@ -482,27 +482,41 @@ struct SearchArgs {
 // active range get L = H = Dp.
 // Also adds the group's pool sizes to *pool_sum (zeroed before), from which
 // the work list picks its parameters.
+// One wave per group, a lane per range, wave reductions: the range records
+// are loaded side by side, not one after another.
 __global__ void k_group_bounds(const RangeStat *__restrict__ rs, int64_t G, int GR, uint32_t Dp,
                                uint32_t bw, uint4 *__restrict__ grp, u64 *pool_sum)
 {
-    const int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gi >= G) return;
+    const int64_t gi = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (gi >= G) return;                     // wave-uniform
     uint32_t L = 0xffffffffu, H = 0, ilo = 0, ihi = 0xffffffffu;
     u64 psum = 0;
-    bool any = false;
-    for (int r = 0; r < GR; ++r) {
+    bool act = false;
+    for (int r = lane; r < GR; r += 64) {
         const RangeStat st = rs[gi * GR + r];
         if (st.flags & kIdle) continue;
-        any = true;
+        act = true;
         L = min(L, st.lo);
         H = max(H, st.hi);
         ilo = max(ilo, st.lo);
         ihi = min(ihi, st.hi);
         psum += st.hi - st.lo;
     }
-    grp[gi] = any ? make_uint4(L & ~(bw - 1u), (H + bw - 1u) & ~(bw - 1u), ilo, ihi)
-                  : make_uint4(Dp, Dp, 0, 0);
-    if (psum) atomicAdd(pool_sum, psum);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        L = min(L, (uint32_t)__shfl_xor((int)L, off));
+        H = max(H, (uint32_t)__shfl_xor((int)H, off));
+        ilo = max(ilo, (uint32_t)__shfl_xor((int)ilo, off));
+        ihi = min(ihi, (uint32_t)__shfl_xor((int)ihi, off));
+        psum += (u64)__shfl_xor((unsigned long long)psum, off);
+    }
+    const bool any = __ballot(act) != 0ull;
+    if (lane == 0) {
+        grp[gi] = any ? make_uint4(L & ~(bw - 1u), (H + bw - 1u) & ~(bw - 1u), ilo, ihi)
+                      : make_uint4(Dp, Dp, 0, 0);
+        if (psum) atomicAdd(pool_sum, psum);
+    }
 }
 
 // Columns per work item and flush trigger of an image, from its tuning row
@@ -2411,7 +2425,7 @@ hipError_t prep_b(const EncodePlan &p, const uint8_t *img, const uint32_t *perm,
     hipLaunchKernelGGL(k_seed<B>, dim3(blocks_for(p.Rp * 64, th)), dim3(th), 0, s, A, Bm, rs, eps,
                        sdd, dom, p.Rp, perm, bmin, p.shift, keys, counters);
     u64 *pool_sum = (u64 *)(ctr + 8);     // zeroed with the counters above
-    hipLaunchKernelGGL(k_group_bounds, dim3(blocks_for(p.IG, th)), dim3(th), 0, s, rs, p.IG,
+    hipLaunchKernelGGL(k_group_bounds, dim3(blocks_for(p.IG * 64, th)), dim3(th), 0, s, rs, p.IG,
                        (int)(p.GR * p.IGW), (uint32_t)p.Dp, (uint32_t)Cfg<B>::MR, grp, pool_sum);
     hipLaunchKernelGGL(k_chunk_span, dim3(blocks_for(p.NC, th)), dim3(th), 0, s, grp, p.IG, p.NC,
                        p.tune, p.pooled, (const u64 *)pool_sum, g.R, g.D, allow_xcd, chunkcnt,
