@@ -248,7 +248,8 @@ def run_autotune(args, fic, images, jobs):
                          "xcd_queues": r["xcd"],
                          "default_chunk_log2": r["base_chunk_log2"],
                          "default_flush_at": r["base_flush_at"],
-                         "default_ms": round(r["base_ms"], 4), "tuned_ms": round(r["tuned_ms"], 4)}
+                         "default_search_ms": round(r["base_ms"], 4),
+                         "tuned_search_ms": round(r["tuned_ms"], 4)}
                         for r in rep]})
 
 

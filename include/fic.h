@@ -393,8 +393,9 @@ fic_status fic_decode_quadtree(fic_ctx *ctx, const fic_code *codes1, const fic_g
  *
  * fic_autotune: for the images described by descs (each with its geometry
  * and tolerance, codes written to descs[i].codes), group them by (B,
- * floor(log2 D), bucket) and, per group, time whole encodes (classify, pool,
- * search, finalize of each image alone, best of `reps`) of candidate rows by
+ * floor(log2 D), bucket) and, per group, time encodes of each image alone
+ * (classify, pool, search, finalize; the time taken is the search launch's,
+ * from events around it, best of `reps`) of candidate rows by
  * coordinate descent (chunk_log2 over 11..16, then flush_at over 0, 32, 64,
  * 128, then xcd), keep the winner only if a final interleaved re-measurement still has
  * it faster than the starting row, and store it in the context. BLOCKS THE
@@ -426,7 +427,7 @@ typedef struct {
     int32_t range_size, dlog2, bucket, images;   /* the tuning class         */
     int32_t chunk_log2, flush_at, xcd;           /* chosen                   */
     int32_t base_chunk_log2, base_flush_at, base_xcd;   /* the row it started from */
-    float base_ms, tuned_ms;   /* summed encode times of the class's images */
+    float base_ms, tuned_ms;   /* summed search times of the class's images */
 } fic_tune_entry;
 size_t fic_autotune_workspace_bytes(int32_t n_images, const fic_image_desc *descs);
 fic_status fic_autotune(fic_ctx *ctx, int32_t n_images, const fic_image_desc *descs,

@@ -790,17 +790,33 @@ struct TuneImage {
     int b, dlog, bucket;
 };
 
+// Events around the search launch only: the tuned parameters change the
+// work list and the search, and the rest of an encode (classification,
+// pool, preparation, finalization) would only add its own noise.
+struct SearchTimer {
+    hipEvent_t b, e;
+    hipError_t err;
+    static void mark(void *self, int stage, int begin, hipStream_t s)
+    {
+        SearchTimer *t = (SearchTimer *)self;
+        if (stage == FIC_STAGE_SEARCH && t->err == hipSuccess)
+            t->err = hipEventRecord(begin ? t->b : t->e, s);
+    }
+};
+
 // One whole encode of image `im` (classify, pool, prep, search, finalize)
-// with row `row`, timed by events on s. Blocks the host.
+// with row `row`; ms = the search launch's time, from events on s. Blocks
+// the host.
 hipError_t timed_encode(fic_ctx *c, TuneImage &im, const fic::TuneRow &row, void *ws, hipStream_t s,
                         hipEvent_t e0, hipEvent_t e1, float &ms)
 {
     im.bp.part[0].plan.tune = row;
     im.bp.part[0].plan.dbg = 0;
     im.bp.dbg = 0;
-    hipError_t e = hipEventRecord(e0, s);
-    if (e == hipSuccess) e = fic::run_encode_batch(&im.job, im.bp, ws, c->num_cu, nullptr, s, nullptr, nullptr);
-    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    SearchTimer st{e0, e1, hipSuccess};
+    const fic::Tracer tr{&st, &SearchTimer::mark};
+    hipError_t e = fic::run_encode_batch(&im.job, im.bp, ws, c->num_cu, nullptr, s, &tr, nullptr);
+    if (e == hipSuccess) e = st.err;
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
     return e;
