@@ -367,25 +367,32 @@ __device__ uint32_t pool_min_wave(const uint32_t *perm, const uint32_t *bmin, ui
     return m;
 }
 
-// Exact F of (range at (ry, rx), domain at (dy, dx), isometry q), from pixels.
+// Row i's part of the exact cross sums of (range at (ry, rx), domain at
+// (dy, dx), isometry q), from pixels: cx = sum_j r[i][j] * D[src(i, j)],
+// sd and sdd the sums of the domain values those cells take (over all rows
+// they are the domain's sums, whatever q).
 template <int B>
-__device__ int64_t pair_f_image(const uint8_t *img, int32_t pitch, int ry, int rx, int dy,
-                                int dx, int q, int32_t sr, int64_t srr, int &k)
+__device__ void pair_row_sums(const uint8_t *img, int32_t pitch, int ry, int rx, int dy, int dx,
+                              int q, int i, int64_t &cx, int64_t &sd, int64_t &sdd)
 {
-    constexpr int n = B * B;
-    int64_t cx = 0, sd = 0, sdd = 0;
-    for (int i = 0; i < B; ++i)
-        for (int j = 0; j < B; ++j) {
-            int si, sj;
-            iso_src(q, B, i, j, si, sj);
-            const uint8_t *pp = img + (int64_t)(dy + 2 * si) * pitch + dx + 2 * sj;
-            const int dv = pp[0] + pp[1] + pp[pitch] + pp[pitch + 1];
-            cx += (int64_t)img[(int64_t)(ry + i) * pitch + rx + j] * dv;
-            sd += dv;
-            sdd += dv * dv;
-        }
-    const int64_t srd = n * cx - (int64_t)sr * sd;
-    return fit_f(srr, srd, n * sdd - sd * sd, k);
+    cx = sd = sdd = 0;
+    for (int j = 0; j < B; ++j) {
+        int si, sj;
+        iso_src(q, B, i, j, si, sj);
+        const uint8_t *pp = img + (int64_t)(dy + 2 * si) * pitch + dx + 2 * sj;
+        const int dv = pp[0] + pp[1] + pp[pitch] + pp[pitch + 1];
+        cx += (int64_t)img[(int64_t)(ry + i) * pitch + rx + j] * dv;
+        sd += dv;
+        sdd += dv * dv;
+    }
+}
+
+// Sum over the B lanes of an aligned segment of a wave (B a power of two).
+template <int B, class T> __device__ __forceinline__ T segment_sum(T v)
+{
+#pragma unroll
+    for (int off = 1; off < B; off <<= 1) v += __shfl_xor(v, off);
+    return v;
 }
 
 // Initial best key per range, so the screen starts from a real threshold:
@@ -483,17 +490,19 @@ struct SearchArgs {
 // Also adds the group's pool sizes to *pool_sum (zeroed before), from which
 // the work list picks its parameters.
 // One wave per group, a lane per range, wave reductions: the range records
-// are loaded side by side, not one after another.
-__global__ void k_group_bounds(const RangeStat *__restrict__ rs, int64_t G, int GR, uint32_t Dp,
-                               uint32_t bw, uint4 *__restrict__ grp, u64 *pool_sum)
+// are loaded side by side, not one after another; one atomic per workgroup
+// (of 4 groups) for the pool sizes, not one per group on the same word.
+__global__ __launch_bounds__(256) void k_group_bounds(const RangeStat *__restrict__ rs, int64_t G,
+                                                      int GR, uint32_t Dp, uint32_t bw,
+                                                      uint4 *__restrict__ grp, u64 *pool_sum)
 {
+    __shared__ u64 part[4];
     const int64_t gi = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int lane = threadIdx.x & 63;
-    if (gi >= G) return;                     // wave-uniform
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     uint32_t L = 0xffffffffu, H = 0, ilo = 0, ihi = 0xffffffffu;
     u64 psum = 0;
     bool act = false;
-    for (int r = lane; r < GR; r += 64) {
+    for (int r = lane; gi < G && r < GR; r += 64) {
         const RangeStat st = rs[gi * GR + r];
         if (st.flags & kIdle) continue;
         act = true;
@@ -513,9 +522,15 @@ __global__ void k_group_bounds(const RangeStat *__restrict__ rs, int64_t G, int 
     }
     const bool any = __ballot(act) != 0ull;
     if (lane == 0) {
-        grp[gi] = any ? make_uint4(L & ~(bw - 1u), (H + bw - 1u) & ~(bw - 1u), ilo, ihi)
-                      : make_uint4(Dp, Dp, 0, 0);
-        if (psum) atomicAdd(pool_sum, psum);
+        if (gi < G)
+            grp[gi] = any ? make_uint4(L & ~(bw - 1u), (H + bw - 1u) & ~(bw - 1u), ilo, ihi)
+                          : make_uint4(Dp, Dp, 0, 0);
+        part[w] = psum;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const u64 tot = part[0] + part[1] + part[2] + part[3];
+        if (tot) atomicAdd(pool_sum, tot);
     }
 }
 
@@ -2267,37 +2282,56 @@ __global__ __launch_bounds__(256) void k_search_plain(
 }
 
 // ------------------------------------------------------------ finalize
+// B lanes per range, lane i summing row i, so a range's pixel reads are
+// spread over B lanes (one lane per range left the launch latency-bound).
 template <int B>
-__global__ void k_finalize(const uint8_t *__restrict__ img, Geom g,
-                           const uint32_t *__restrict__ order, const u64 *__restrict__ keys,
-                           const uint8_t *__restrict__ sel, int shift,
-                           fic_code *__restrict__ codes)
+__global__ __launch_bounds__(256) void k_finalize(const uint8_t *__restrict__ img, Geom g,
+                                                  const uint32_t *__restrict__ order,
+                                                  const u64 *__restrict__ keys,
+                                                  const uint8_t *__restrict__ sel, int shift,
+                                                  fic_code *__restrict__ codes)
 {
     constexpr int n = B * B;
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= g.R) return;
-    const uint32_t ridx = order ? order[s] : (uint32_t)s;
-    if (sel && !sel[ridx]) {             // not coded: flag bit 2, everything else 0
-        fic_code c;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t s = t / B;
+    const int i = (int)(t % B);
+    // a segment of B lanes is one range; segments past the ranges take part
+    // in the shuffles and write nothing
+    const bool live = s < g.R;
+    const uint32_t ridx = live ? (order ? order[s] : (uint32_t)s) : 0u;
+    const bool coded = live && !(sel && !sel[ridx]);
+    const int ry = (int)(ridx / g.rcols) * B, rx = (int)(ridx % g.rcols) * B;
+    int64_t sr = 0, sq = 0;
+    if (coded)
+        for (int j = 0; j < B; ++j) {
+            const int v = img[(int64_t)(ry + i) * g.pitch + rx + j];
+            sr += v;
+            sq += v * v;
+        }
+    sr = segment_sum<B>(sr);
+    sq = segment_sum<B>(sq);
+    const u64 key = coded ? keys[s] : kNoKey;
+    const uint32_t d = (uint32_t)((key >> 3) & ((1ull << (shift - 3)) - 1ull));
+    const int q = (int)(key & 7ull);
+    int64_t cx = 0, sd = 0, sdd = 0;
+    if (key != kNoKey) {
+        const int dy = (int)(d / g.dcols) * g.t, dx = (int)(d % g.dcols) * g.t;
+        pair_row_sums<B>(img, g.pitch, ry, rx, dy, dx, q, i, cx, sd, sdd);
+    }
+    cx = segment_sum<B>(cx);
+    sd = segment_sum<B>(sd);
+    sdd = segment_sum<B>(sdd);
+    if (!live || i != 0) return;
+    fic_code c;
+    if (!coded) {                        // not coded: flag bit 2, everything else 0
         c.domain = 0; c.iso = 0; c.s_idx = 0; c.o_idx = 0; c.flags = 4; c.err = 0;
         codes[ridx] = c;
         return;
     }
-    const int ry = (int)(ridx / g.rcols) * B, rx = (int)(ridx % g.rcols) * B;
-    int32_t sr = 0;
-    int64_t sq = 0;
-    for (int i = 0; i < B; ++i)
-        for (int j = 0; j < B; ++j) {
-            int v = img[(int64_t)(ry + i) * g.pitch + rx + j];
-            sr += v;
-            sq += v * v;
-        }
-    const int64_t srr = (int64_t)n * sq - (int64_t)sr * sr;
-    const int32_t j = (sr + n - 1) / (2 * n);
+    const int64_t srr = (int64_t)n * sq - sr * sr;
+    const int32_t j = (int32_t)((sr + n - 1) / (2 * n));
     const int64_t e = sr - 2 * (int64_t)n * j;
     const int64_t jcost = 4096 * e * e;
-    const u64 key = keys[s];
-    fic_code c;
     c.o_idx = (uint8_t)j;
     if (key == kNoKey) {
         c.domain = 0;
@@ -2306,11 +2340,9 @@ __global__ void k_finalize(const uint8_t *__restrict__ img, Geom g,
         c.flags = 1;
         c.err = 4096 * srr + jcost;
     } else {
-        const uint32_t d = (uint32_t)((key >> 3) & ((1ull << (shift - 3)) - 1ull));
-        const int q = (int)(key & 7ull);
-        const int dy = (int)(d / g.dcols) * g.t, dx = (int)(d % g.dcols) * g.t;
         int k;
-        const int64_t f = pair_f_image<B>(img, g.pitch, ry, rx, dy, dx, q, sr, srr, k);
+        const int64_t srd = (int64_t)n * cx - sr * sd;
+        const int64_t f = fit_f(srr, srd, (int64_t)n * sdd - sd * sd, k);
         c.domain = d;
         c.iso = (uint8_t)q;
         c.s_idx = (int8_t)k;
@@ -2365,7 +2397,7 @@ hipError_t run_plain_b(const EncodePlan &p, const uint8_t *img, const uint32_t *
     }
     trace(tr, FIC_STAGE_SEARCH, 0, s);
     trace(tr, FIC_STAGE_FINAL, 1, s);
-    hipLaunchKernelGGL(k_finalize<B>, dim3(blocks_for(g.R, th)), dim3(th), 0, s, img, g,
+    hipLaunchKernelGGL(k_finalize<B>, dim3(blocks_for(g.R * B, th)), dim3(th), 0, s, img, g,
                        (const uint32_t *)nullptr, keys, p.sel, p.shift, codes);
     trace(tr, FIC_STAGE_FINAL, 0, s);
     return hipGetLastError();
@@ -2490,7 +2522,7 @@ hipError_t finalize_b(const EncodePlan &p, const uint8_t *img, void *ws, fic_cod
 {
     char *w = (char *)ws;
     trace(tr, FIC_STAGE_FINAL, 1, s);
-    hipLaunchKernelGGL(k_finalize<B>, dim3(blocks_for(p.g.R, 256)), dim3(256), 0, s, img, p.g,
+    hipLaunchKernelGGL(k_finalize<B>, dim3(blocks_for(p.g.R * B, 256)), dim3(256), 0, s, img, p.g,
                        (const uint32_t *)(w + p.off_order), (const u64 *)(w + p.off_keys), p.sel,
                        p.shift, codes);
     trace(tr, FIC_STAGE_FINAL, 0, s);
