@@ -566,6 +566,9 @@ def bench_quadtree(args, fic, wl, img_np):
         "stage_ms_per_step": {k: round(v, 4) for k, v in stage_ms.items()},
         "roofline": roofline,
         "autotune": tune,
+        # codes whose key disagreed with finalize's recompute from pixels
+        "codes_flag7": int(sum(int(np.count_nonzero(fic.unpack_codes(c)["flags"] & 0x80))
+                               for c in (c1, c2))),
     }
     if not args.no_cpu:
         out["cpu_baseline"] = oracle_rate(img_np, b1, t1, tol1, sizes[0], None, args.cpu_seconds,
@@ -804,6 +807,9 @@ def bench_batch(args, fic, wl):
         "roofline": roofline,
         "autotune": tune,
         "pool_margin_min": float("%.3g" % margin),
+        # codes whose key disagreed with finalize's recompute from pixels
+        "codes_flag7": int(sum(int(np.count_nonzero(fic.unpack_codes(c)["flags"] & 0x80))
+                               for c in codes)),
     }
     if not args.no_cpu:
         big = max(range(len(items)), key=lambda i: int(sizes[i].sum()))
