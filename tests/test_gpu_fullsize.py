@@ -105,9 +105,10 @@ def check_digests(orc, rec, img, got, what):
 
 
 def job_record(golden, jid):
+    """The job's digest record; the committed file covers every range of
+    every full-size job."""
     rec = golden["jobs"].get(jid)
-    if rec is None or not rec["blocks"]:
-        pytest.skip("no oracle digests for %s yet" % jid)
+    assert rec is not None and rec.get("complete"), "no complete oracle digests for " + jid
     return rec
 
 
@@ -158,9 +159,7 @@ def test_reverse_item_order(fic, orc, golden, job):
         ctx.set_debug(0)
     for f in fwd.dtype.names:
         assert np.array_equal(fwd[f], rev[f]), f
-    rec = golden["jobs"].get(jid_of(*job))
-    if rec and rec["blocks"]:
-        check_digests(orc, rec, img, rev, jid_of(*job) + " reversed")
+    check_digests(orc, job_record(golden, jid_of(*job)), img, rev, jid_of(*job) + " reversed")
 
 
 @pytest.mark.parametrize("chunk_log2", [13, 16])
@@ -182,9 +181,7 @@ def test_xcd_queues_every_range(fic, orc, golden, tmp_path, chunk_log2):
         for job in [("fbm1024_b8t1", 8, 1, None), ("fbm1024_b8t1", 8, 1, 0.02),
                     ("fbm1024_b8t1", 8, 1, 0.1), ("fbm2048_twolevel", 8, 2, 0.05),
                     ("fbm2048_twolevel", 16, 4, 0.05)]:
-            rec = golden["jobs"].get(jid_of(*job))
-            if not rec or not rec["blocks"]:
-                continue
+            rec = job_record(golden, jid_of(*job))
             img = workload_images(job[0])
             got = gpu_codes(fic, img, *job[1:])
             check_digests(orc, rec, img, got, jid_of(*job) + " xcd queues")
@@ -208,13 +205,11 @@ def test_batch64_every_range(fic, orc, golden):
     for m, ((im, b, t, tol), g) in enumerate(zip(items, got)):
         jid = "batch64_mixed/%02d_%d_%d_%s" % (m, b, t, MK._tol_name(tol))
         total += g.size
-        rec = golden["jobs"].get(jid)
         assert not np.any(g["flags"] & 0x80)
-        if rec and rec["blocks"]:
-            checked += check_digests(orc, rec, im, g, jid)
+        checked += check_digests(orc, job_record(golden, jid), im, g, jid)
     print("batch64: %d of %d ranges checked against the oracle digests" % (checked, total))
-    if checked == 0:
-        pytest.skip("no batch digests yet")
+    # the committed digests cover every range of every image
+    assert checked == total, "the digests cover %d of %d ranges" % (checked, total)
     ctx = fic.fic.context()
     ctx.set_debug(fic.fic.DEBUG_REVERSE_ITEMS)
     try:
