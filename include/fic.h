@@ -386,7 +386,8 @@ fic_status fic_decode_quadtree(fic_ctx *ctx, const fic_code *codes1, const fic_g
  *               queue per XCD (the column chunks c = x mod 8 on XCD x, so
  *               each XCD's L2 streams an eighth of the domain columns;
  *               waves take from other queues once theirs is empty); 0: one
- *               queue in chunk order. Batches always use one queue.
+ *               queue in chunk order. Batches of several images always use
+ *               one queue (a batch of one image follows its row).
  * A row serves one (range size B, floor(log2 D)) class; classes without a
  * row use the built-in defaults (exhaustive 2^14, pooled 2^12; flush 64 at
  * B = 8, else 0; xcd 0). Every choice gives the same codes.

@@ -2547,10 +2547,13 @@ hipError_t run_encode_b(const EncodePlan &p, const uint8_t *img, const uint32_t 
 template <int B>
 hipError_t batch_phase(int phase, const EncodePlan &p, const uint8_t *img, const uint32_t *perm,
                        const uint32_t *lo, const uint32_t *hi, void *ws, u64 *counters,
-                       SearchArgs *slot, fic_code *codes, hipStream_t s, const Tracer *tr)
+                       SearchArgs *slot, fic_code *codes, hipStream_t s, const Tracer *tr,
+                       int single = 0)
 {
-    // batches share one queue over all images: chunk-major work lists
-    return phase == 0 ? prep_b<B>(p, img, perm, lo, hi, ws, counters, slot, s, tr, 0)
+    // batches of several images share one queue: chunk-major work lists; a
+    // batch of one image searches as a single-image encode does (its tuning
+    // row may choose the per-XCD queues)
+    return phase == 0 ? prep_b<B>(p, img, perm, lo, hi, ws, counters, slot, s, tr, single)
                       : finalize_b<B>(p, img, ws, codes, s, tr);
 }
 
@@ -2748,9 +2751,9 @@ hipError_t run_encode_batch(const BatchJob *jobs, const BatchPlan &bp, void *ws,
         const uint32_t *ph = j.pooled ? hi : nullptr;
         void *ew = w + pt.off_enc;
         switch (g.b) {
-        case 4: e = batch_phase<4>(0, pt.plan, j.img, pp, pl, ph, ew, counters, tab + k, nullptr, ps, tr); break;
-        case 8: e = batch_phase<8>(0, pt.plan, j.img, pp, pl, ph, ew, counters, tab + k, nullptr, ps, tr); break;
-        default: e = batch_phase<16>(0, pt.plan, j.img, pp, pl, ph, ew, counters, tab + k, nullptr, ps, tr); break;
+        case 4: e = batch_phase<4>(0, pt.plan, j.img, pp, pl, ph, ew, counters, tab + k, nullptr, ps, tr, bp.n == 1); break;
+        case 8: e = batch_phase<8>(0, pt.plan, j.img, pp, pl, ph, ew, counters, tab + k, nullptr, ps, tr, bp.n == 1); break;
+        default: e = batch_phase<16>(0, pt.plan, j.img, pp, pl, ph, ew, counters, tab + k, nullptr, ps, tr, bp.n == 1); break;
         }
     }
     if (ns > 0 && e == hipSuccess) e = join();
