@@ -397,7 +397,7 @@ fic_status fic_decode_quadtree(fic_ctx *ctx, const fic_code *codes1, const fic_g
  * floor(log2 D), bucket) and, per group, time encodes of each image alone
  * (classify, pool, search, finalize; the time taken is the search launch's,
  * from events around it, best of `reps`) of candidate rows by
- * coordinate descent (chunk_log2 over 11..16, then flush_at over 0, 32, 64,
+ * coordinate descent (chunk_log2 over 11..16, then flush_at over 0, 16, 32, 64,
  * 128, then xcd), keep the winner only if a final interleaved re-measurement still has
  * it faster than the starting row, and store it in the context. BLOCKS THE
  * HOST (event synchronisation); not for stream capture. Recorded batch graphs

@@ -907,8 +907,8 @@ fic_status fic_autotune(fic_ctx *ctx, int32_t n_images, const fic_image_desc *de
             cost(cand, t);
             if (t < t_best) { t_best = t; best = cand; }
         }
-        static const int kFlush[] = {0, 32, 64, 128};
-        for (int fi = 0; fi < 4 && e == hipSuccess; ++fi) {
+        static const int kFlush[] = {0, 16, 32, 64, 128};
+        for (int fi = 0; fi < 5 && e == hipSuccess; ++fi) {
             if (kFlush[fi] == best.flush_at[k]) continue;
             fic::TuneRow cand = best;
             cand.flush_at[k] = (int16_t)kFlush[fi];

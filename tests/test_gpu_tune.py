@@ -65,7 +65,7 @@ def test_codes_identical_under_every_candidate(fic, tmp_path):
     path = str(tmp_path / "cand.json")
     try:
         for cl in range(11, 17):
-            for fl in (0, 32, 128):
+            for fl in (0, 16, 32, 128):
                 for xc in (0, 1):
                     _write_rows(path, cl, fl, xc)
                     assert ctx.tune_load(path) == fic.fic.OK
@@ -99,7 +99,7 @@ def test_autotune_then_cache_round_trip(fic, tmp_path):
             assert len(launch) == 1 and launch[0]["flush_at"] in (0, 1)
             assert launch[0]["tuned_ms"] <= launch[0]["base_ms"]
         for r in rep:
-            assert 11 <= r["chunk_log2"] <= 16 and r["flush_at"] in (0, 32, 64, 128)
+            assert 11 <= r["chunk_log2"] <= 16 and r["flush_at"] in (0, 16, 32, 64, 128)
             assert r["xcd"] in (0, 1)
             assert r["tuned_ms"] <= r["base_ms"]
             print("B=%d log2 D=%d bucket %d (%d images): chunk 2^%d flush %d, %.3f -> %.3f ms"
