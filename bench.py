@@ -65,7 +65,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="fbm1024_b8t1")
+    from synth import WORKLOADS
+    ap.add_argument("--workload", default="fbm1024_b8t1",
+                    choices=sorted(WORKLOADS) + ["adaptive_window"],
+                    help="the synthetic job set a step runs (default fbm1024_b8t1: the 1024x1024 "
+                         "exhaustive, pool 0.02 and pool 0.1 searches)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-kernel comparison")
