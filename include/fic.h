@@ -60,7 +60,9 @@ typedef enum {
     FIC_ERR_UNSUPPORTED = 2,   /* a valid request the library does not handle   */
     FIC_ERR_WORKSPACE = 3,     /* ws_bytes below fic_*_workspace_bytes()        */
     FIC_ERR_CAPACITY = 4,      /* the packed (F, domain, isometry) key would
-                                  not fit 64 bits for this geometry             */
+                                  not fit 64 bits for this geometry, the 4x4 /
+                                  8x8 B operand would reach 2^31 bytes, or the
+                                  work list could exceed 2^32 - 1 items        */
     FIC_ERR_DEVICE = 5         /* no HIP device, or a HIP call / launch failed  */
 } fic_status;
 

@@ -176,7 +176,12 @@ bool key_fits(const Geom &g)
     int dbits = 1;
     while (((int64_t)1 << dbits) < g.D) ++dbits;
     if (g.b != 16 && (double)(g.D + 64) * (double)g.n * 2.0 >= 2147483648.0) return false;
-    return fbits + dbits + 3 <= 64;
+    if (fbits + dbits + 3 > 64) return false;
+    // the work list (every group x every chunk of the narrowest item width)
+    // is counted in 32 bits
+    fic::EncodePlan p;
+    fic::plan_encode(g, 1, p);
+    return p.max_items <= (int64_t)0xffffffffll;
 }
 
 fic_status dev_status(hipError_t e) { return e == hipSuccess ? FIC_OK : FIC_ERR_DEVICE; }

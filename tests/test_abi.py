@@ -96,7 +96,8 @@ def test_encode_validation(L, hctx):
 def test_capacity_limit(L, hctx):
     """F needs 42 bits at 16x16 ranges; 2^19 or more domains leave fewer than
     the 64 - 42 - 3 bits an index needs. 4x4 and 8x8 searches also need their
-    B operand below 2^31 bytes."""
+    B operand below 2^31 bytes, and every search a work list of at most
+    2^32 - 1 items."""
     ok = fic.make_geom(2048, 2048, 16, 4)         # 255,025 domains: 18 bits
     assert _encode(L, hctx, ok, wsb=1 << 40) == fic.ERR_DEVICE
     big = fic.make_geom(8192, 8192, 16, 4)        # 4,182,025 domains: 22 bits
@@ -105,10 +106,15 @@ def test_capacity_limit(L, hctx):
     assert _encode(L, hctx, b8, wsb=1 << 40) == fic.ERR_CAPACITY
     # 4x4: the key fits 67M domains, but the B operand (32 bytes a domain) is
     # addressed with 32-bit offsets and must stay below 2^31 bytes
-    b4ok = fic.make_geom(8192, 8192, 4, 1)        # 66,994,225 domains
-    assert _encode(L, hctx, b4ok, wsb=1 << 40) == fic.ERR_DEVICE
     b4big = fic.make_geom(8200, 8200, 4, 1)       # 67,125,249 domains: 2^31 bytes
     assert _encode(L, hctx, b4big, wsb=1 << 40) == fic.ERR_CAPACITY
+    # and the work list (range groups x 2048-column chunks) is counted in 32
+    # bits: 262,144 groups x 32,712 chunks is too many, 16,744,464 domains
+    # at step 2 (8,184 chunks) fit
+    b4items = fic.make_geom(8192, 8192, 4, 1)     # 66,994,225 domains
+    assert _encode(L, hctx, b4items, wsb=1 << 40) == fic.ERR_CAPACITY
+    b4ok = fic.make_geom(8192, 8192, 4, 2)
+    assert _encode(L, hctx, b4ok, wsb=1 << 40) == fic.ERR_DEVICE
 
 
 def test_classify_validation(L, hctx):
