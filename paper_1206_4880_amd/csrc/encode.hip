@@ -538,11 +538,11 @@ __global__ __launch_bounds__(256) void k_group_bounds(const RangeStat *__restric
 // and the pool-fraction bucket of its pool sizes (exact integer sum).
 struct ItemParams { uint32_t chunk; int flush_at; int xcd; };
 __device__ inline ItemParams item_params(const TuneRow &t, int pooled, const u64 *pool_sum,
-                                         int64_t R, int64_t D, int allow_xcd)
+                                         int64_t R, int64_t D, int allow_xcd, int chunk_min)
 {
     const int b = tune_bucket(pooled, pooled ? *pool_sum : 0ull, R, D);
     ItemParams ip;
-    ip.chunk = 1u << t.chunk_log2[b];
+    ip.chunk = 1u << max((int)t.chunk_log2[b], chunk_min);
     ip.flush_at = t.flush_at[b];
     ip.xcd = allow_xcd && t.xcd[b];
     return ip;
@@ -564,13 +564,13 @@ __device__ inline int64_t slot_chunk(int64_t p, int xcd, int64_t ncx)
 // at the chunk's slot. NC counts chunk slots of the narrowest item width (a
 // multiple of 8); with wider items the chunks past the lattice get no groups.
 __global__ void k_chunk_span(const uint4 *__restrict__ grp, int64_t G, int64_t NC, TuneRow tune,
-                             int pooled, const u64 *__restrict__ pool_sum, int64_t R, int64_t D,
-                             int allow_xcd, uint32_t *__restrict__ cnt,
+                             int chunk_min, int pooled, const u64 *__restrict__ pool_sum,
+                             int64_t R, int64_t D, int allow_xcd, uint32_t *__restrict__ cnt,
                              uint32_t *__restrict__ gfirst)
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= NC) return;
-    const ItemParams ip = item_params(tune, pooled, pool_sum, R, D, allow_xcd);
+    const ItemParams ip = item_params(tune, pooled, pool_sum, R, D, allow_xcd, chunk_min);
     const uint32_t chunk = ip.chunk;
     const int64_t pc = chunk_slot(c, ip.xcd, NC / kXcds);
     if ((uint64_t)c * chunk >= (uint64_t)D) {   // past the lattice (also past its padding)
@@ -599,13 +599,14 @@ __global__ void k_chunk_span(const uint4 *__restrict__ grp, int64_t G, int64_t N
 // Thread 0 also publishes the image's table entry.
 __global__ void k_emit_items(const uint4 *__restrict__ grp, const uint32_t *__restrict__ chunkoff,
                              const uint32_t *__restrict__ gfirst, int64_t NC, TuneRow tune,
-                             int pooled, const u64 *__restrict__ pool_sum, int64_t R, int64_t D,
-                             int allow_xcd, const uint32_t *__restrict__ total, int64_t max_items,
+                             int chunk_min, int pooled, const u64 *__restrict__ pool_sum,
+                             int64_t R, int64_t D, int allow_xcd,
+                             const uint32_t *__restrict__ total, int64_t max_items,
                              WorkItem *__restrict__ items, SearchArgs args,
                              SearchArgs *__restrict__ slot)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const ItemParams ip = item_params(tune, pooled, pool_sum, R, D, allow_xcd);
+    const ItemParams ip = item_params(tune, pooled, pool_sum, R, D, allow_xcd, chunk_min);
     const uint32_t chunk = ip.chunk;
     const int64_t ncx = NC / kXcds;
     if (i == 0) {
@@ -2460,8 +2461,8 @@ hipError_t prep_b(const EncodePlan &p, const uint8_t *img, const uint32_t *perm,
     hipLaunchKernelGGL(k_group_bounds, dim3(blocks_for(p.IG * 64, th)), dim3(th), 0, s, rs, p.IG,
                        (int)(p.GR * p.IGW), (uint32_t)p.Dp, (uint32_t)Cfg<B>::MR, grp, pool_sum);
     hipLaunchKernelGGL(k_chunk_span, dim3(blocks_for(p.NC, th)), dim3(th), 0, s, grp, p.IG, p.NC,
-                       p.tune, p.pooled, (const u64 *)pool_sum, g.R, g.D, allow_xcd, chunkcnt,
-                       chunkfill);
+                       p.tune, p.chunk_min, p.pooled, (const u64 *)pool_sum, g.R, g.D, allow_xcd,
+                       chunkcnt, chunkfill);
     // exclusive scan of the per-chunk counts; the total is the item count
     const hipError_t se = scan_u32(chunkcnt, p.NC, ctr + 1, w + p.off_scan, s);
     if (se != hipSuccess) return se;
@@ -2470,8 +2471,9 @@ hipError_t prep_b(const EncodePlan &p, const uint8_t *img, const uint32_t *perm,
     a.items = items; a.n_items = ctr + 1; a.keys = keys; a.shift = p.shift; a.flush_at = 0;
     a.xcd = 0; a.ncx = 0; a.xq = nullptr;
     hipLaunchKernelGGL(k_emit_items, dim3(blocks_for(p.max_items, th)), dim3(th), 0, s, grp,
-                       chunkcnt, chunkfill, p.NC, p.tune, p.pooled, (const u64 *)pool_sum, g.R,
-                       g.D, allow_xcd, ctr + 1, p.max_items, items, a, slot);
+                       chunkcnt, chunkfill, p.NC, p.tune, p.chunk_min, p.pooled,
+                       (const u64 *)pool_sum, g.R, g.D, allow_xcd, ctr + 1, p.max_items, items, a,
+                       slot);
     trace(tr, FIC_STAGE_WORKLIST, 0, s);
     return hipGetLastError();
 }
@@ -2586,8 +2588,15 @@ void plan_encode(const Geom &g, int pooled, EncodePlan &p)
     p.G = p.Rp / p.GR;
     p.IG = p.G / p.IGW;
     p.Dp = (g.D + mr - 1) / mr * mr;
-    p.NC = (p.Dp + ((int64_t)1 << kChunkLog2Min) - 1) >> kChunkLog2Min;
-    p.NC = (p.NC + kXcds - 1) / kXcds * kXcds;
+    // chunk slots at the narrowest item width, widened until the work list's
+    // worst case (every group against every chunk) stays within kMaxItems
+    auto slots = [&](int cl) {
+        const int64_t nc = (p.Dp + ((int64_t)1 << cl) - 1) >> cl;
+        return (nc + kXcds - 1) / kXcds * kXcds;
+    };
+    p.chunk_min = kChunkLog2Min;
+    while (p.chunk_min < kChunkLog2Max && p.IG * slots(p.chunk_min) > kMaxItems) ++p.chunk_min;
+    p.NC = slots(p.chunk_min);
     p.max_items = p.IG * p.NC;
     int dbits = 1;
     while (((int64_t)1 << dbits) < g.D) ++dbits;

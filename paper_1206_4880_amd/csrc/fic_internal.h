@@ -114,6 +114,9 @@ struct WorkItem { uint32_t grp, c0, c1, pad; };
 // defaults are below.
 constexpr int kTuneBuckets = 6;
 constexpr int kChunkLog2Min = 11, kChunkLog2Max = 16;
+// Work-list entries a single search plans for at most (16 bytes each: 1 GiB);
+// a job that would need more at 2^kChunkLog2Min columns uses wider items.
+constexpr int64_t kMaxItems = (int64_t)1 << 26;
 constexpr int kXcds = 8;             // MI355X: 8 XCDs, workgroups assigned round robin
 struct TuneRow {
     int8_t chunk_log2[kTuneBuckets];
@@ -305,8 +308,10 @@ struct EncodePlan {
     int pooled;
     int64_t Rp, Dp, G, GR, NC;   // padded ranges/columns, groups, ranges per group, chunks
     int64_t IGW, IG;              // groups per work item (one per wave of a workgroup), item groups
-    int32_t shift;                // NC: chunk slots at the narrowest item (2^kChunkLog2Min
+    int32_t shift;                // NC: chunk slots at the narrowest item (2^chunk_min
                                   // columns), a multiple of kXcds
+    int32_t chunk_min;            // narrowest item width (log2): kChunkLog2Min, raised for
+                                  // large jobs so the work list stays within kMaxItems
     int64_t max_items;
     size_t off_A, off_rs, off_order, off_B, off_u, off_eps, off_sdd, off_dom, off_keys,
         off_items, off_ctr, off_args, off_chunkcnt, off_chunkfill, off_grp, off_bmin, off_S,

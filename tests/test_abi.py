@@ -108,13 +108,12 @@ def test_capacity_limit(L, hctx):
     # addressed with 32-bit offsets and must stay below 2^31 bytes
     b4big = fic.make_geom(8200, 8200, 4, 1)       # 67,125,249 domains: 2^31 bytes
     assert _encode(L, hctx, b4big, wsb=1 << 40) == fic.ERR_CAPACITY
-    # and the work list (range groups x 2048-column chunks) is counted in 32
-    # bits: 262,144 groups x 32,712 chunks is too many, 16,744,464 domains
-    # at step 2 (8,184 chunks) fit
-    b4items = fic.make_geom(8192, 8192, 4, 1)     # 66,994,225 domains
-    assert _encode(L, hctx, b4items, wsb=1 << 40) == fic.ERR_CAPACITY
-    b4ok = fic.make_geom(8192, 8192, 4, 2)
+    # 66,994,225 domains fit; its work list (262,144 groups x 32,712 chunks
+    # of 2048 columns) would not, so it plans wider items (at most 2^26
+    # entries where possible, never more than 2^32 - 1)
+    b4ok = fic.make_geom(8192, 8192, 4, 1)
     assert _encode(L, hctx, b4ok, wsb=1 << 40) == fic.ERR_DEVICE
+    assert L.fic_encode_workspace_bytes(ctypes.byref(b4ok), 0) < 10 << 30
 
 
 def test_classify_validation(L, hctx):

@@ -9,6 +9,12 @@ domain step 1 has 8,346,321 domains for 8x8 ranges (2^23 = 8,388,608), and a
 ranges (the first, the last, seeded random ones and those whose best domain
 has the highest indices) must equal the oracle's, exhaustively and with the
 Sec. 3.1 pool; no code may fail finalize's recompute (bit 7).
+
+The work list is planned for every range group against every chunk of the
+narrowest item width; a job whose list would pass 2^26 entries at 2048
+columns plans wider items instead. 4x4 ranges on a 4096 x 4096 image at
+step 1 (65,536 groups, 16.7 M domains) take 16384-column items: their codes
+are checked the same way.
 """
 import numpy as np
 import pytest
@@ -78,3 +84,22 @@ def test_keys_at_the_domain_limit(fic, orc, b, tol, n_random):
     sel = np.unique(np.concatenate([[0, R - 1], top, rnd])).astype(np.int64)
     ref = orc.encode(img, b, t, tol=tol, sel=sel)
     assert_codes(got[sel], ref, "%dx%d, %dx%d ranges, step %d, tol %s" % (size, size, b, b, t, tol))
+
+
+def test_work_list_with_wider_items(fic, orc):
+    import ctypes
+    size, b, t = 4096, 4, 1
+    img = image(size)
+    g = fic.fic.make_geom(size, size, b, t)
+    # 65,536 groups x 8,176 chunks of 2048 columns would be 8.6 GB of items
+    assert fic.fic.lib().fic_encode_workspace_bytes(ctypes.byref(g), 1) < 3 << 30
+    R = orc.num_ranges(size, size, b)
+    x = torch.from_numpy(np.ascontiguousarray(img)).cuda()
+    for tol in (0.01, None):
+        codes, _ = fic.encode(x, b, t, tol=tol)
+        torch.cuda.synchronize()
+        got = fic.unpack_codes(codes)
+        assert got.size == R and not np.any(got["flags"] & 0x80)
+        sel = np.unique(np.concatenate([[0, R - 1], np.random.default_rng(6).choice(R, 8, replace=False)]))
+        ref = orc.encode(img, b, t, tol=tol, sel=sel.astype(np.int64))
+        assert_codes(got[sel], ref, "%dx%d, 4x4 ranges, step 1, tol %s" % (size, size, tol))
