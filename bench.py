@@ -606,12 +606,15 @@ def bench_color(args, fic, wl, rgb_np):
     ctx.timing(True)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
+    out = None
     for _ in range(args.steps):
-        fic.encode_color(rgb, b, t, tol=tol)
+        out = fic.encode_color(rgb, b, t, tol=tol)
     torch.cuda.synchronize()
     ms_step = (time.perf_counter() - t_start) * 1e3 / args.steps
     recs = ctx.timing_read()
     ctx.timing(False)
+    if out is None:
+        out = fic.encode_color(rgb, b, t, tol=tol)
     progress("timed %d steps: %.3f ms per step" % (args.steps, ms_step))
     searches = [ms for (name, ms) in recs if name == "search"]
     t_s = float(np.mean(searches)) / 1e3
@@ -626,6 +629,9 @@ def bench_color(args, fic, wl, rgb_np):
         "encode_s_per_image": round(ms_step / 1e3, 6),
         "stage_ms_per_step": {k: round(v, 4) for k, v in stage_sums(recs, args.steps).items()},
         "roofline": roofline,
+        # codes whose key disagreed with finalize's recompute from pixels
+        "codes_flag7": int(sum(int(np.count_nonzero(fic.unpack_codes(c)["flags"] & 0x80))
+                               for c in out)),
     }
 
 
